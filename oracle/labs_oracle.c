@@ -1,0 +1,624 @@
+/*
+ * labs_oracle.c -- plain CPU reference ("the oracle") for memetic tabu search
+ * on Low Autocorrelation Binary Sequences (LABS).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the slow, obviously-correct statement of
+ * what the GPU library computes.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it; the product path never calls
+ * it and shares no code, header, table or helper with it.
+ *
+ * Paper: Z. Zhang, J. Shen, et al., "New Improvements in Solving Large LABS
+ * Instances Using Massively Parallelizable Memetic Tabu Search",
+ * arXiv:2504.00987.  Citations below name the paper's section, equation,
+ * algorithm or table.
+ *
+ * Conventions
+ *   - A sequence is int8_t s[0..n-1] with s_i in {-1,+1}; indices are 0-based
+ *     (the paper is 1-based).
+ *   - All arithmetic is exact integer arithmetic (int64 accumulators).
+ *   - Randomness: every draw is Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
+ *     "Parallel random numbers: as easy as 1, 2, 3", SC'11), keyed by the
+ *     64-bit seed and addressed by a counter (entity, generation, index, tag).
+ *     The paper only says that replicas use different seeds (Sec. IV); the
+ *     counter layout below is this implementation's reading, written once and
+ *     implemented independently on each side.
+ *   - A uniform integer in [0, r) is drawn from a 32-bit word u as
+ *     (u * r) >> 32.
+ *
+ * Parity pins: see tests/test_oracle_*.py.  Every function here is pinned by
+ * at least one check that does not re-use this file's arithmetic.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <pthread.h>
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10, from the published definition (SC'11, Sec. 2.3 / Fig. 2).   */
+/* Round: (hi0,lo0) = M0*x0, (hi1,lo1) = M1*x2;                               */
+/*        x' = (hi1 ^ x1 ^ k0, lo1, hi0 ^ x3 ^ k1, lo0); the key is bumped by */
+/*        the Weyl constants between rounds.                                  */
+/* ------------------------------------------------------------------------- */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y1 = lo1;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        uint32_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Purpose tags: the fourth counter word, one per kind of draw. */
+enum {
+    ORC_TAG_START = 1, /* random start of a stand-alone walk               */
+    ORC_TAG_STEP  = 2, /* per tabu step: tie-break word, tenure word       */
+    ORC_TAG_LEN   = 3, /* per walk: random walk length                     */
+    ORC_TAG_INIT  = 4, /* per population member: initial sequence          */
+    ORC_TAG_GEN   = 5, /* per generation: crossover/parents/cut/replacement */
+    ORC_TAG_MUT   = 6  /* per generation: mutation words                   */
+};
+
+static void draw(uint64_t seed, uint32_t entity, uint32_t gen, uint32_t index,
+                 uint32_t tag, uint32_t out[4])
+{
+    uint32_t ctr[4] = { entity, gen, index, tag };
+    uint32_t key[2] = { (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32) };
+    orc_philox4x32_10(ctr, key, out);
+}
+
+static uint32_t uniform_below(uint32_t u, uint32_t range)
+{
+    return (uint32_t)(((uint64_t)u * (uint64_t)range) >> 32);
+}
+
+void orc_draw(uint64_t seed, uint32_t entity, uint32_t gen, uint32_t index,
+              uint32_t tag, uint32_t out[4])
+{
+    draw(seed, entity, gen, index, tag, out);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Objective: Eq. (1) aperiodic autocorrelation, Eq. (2) energy.             */
+/* ------------------------------------------------------------------------- */
+
+/* C[k] = sum_{i=0}^{n-1-k} s_i s_{i+k} for k = 0..n-1 (Eq. 1; C[0] = n). */
+void orc_autocorrelation(const int8_t *s, int n, int64_t *C)
+{
+    for (int k = 0; k < n; ++k) {
+        int64_t c = 0;
+        for (int i = 0; i + k < n; ++i)
+            c += (int64_t)s[i] * (int64_t)s[i + k];
+        C[k] = c;
+    }
+}
+
+/* E(s) = sum_{k=1}^{n-1} C_k^2 (Eq. 2). */
+int64_t orc_energy(const int8_t *s, int n)
+{
+    int64_t e = 0;
+    for (int k = 1; k < n; ++k) {
+        int64_t c = 0;
+        for (int i = 0; i + k < n; ++i)
+            c += (int64_t)s[i] * (int64_t)s[i + k];
+        e += c * c;
+    }
+    return e;
+}
+
+/* Batch form of Eq. (2): energies of B sequences stored with a row stride. */
+void orc_energy_batch(const int8_t *seqs, const int32_t *ns, int32_t n_uniform,
+                      int32_t stride, int64_t B, int64_t *out)
+{
+    for (int64_t b = 0; b < B; ++b) {
+        int n = ns ? ns[b] : n_uniform;
+        out[b] = orc_energy(seqs + b * stride, n);
+    }
+}
+
+/* Exhaustive minimum of Eq. (2) over all 2^n sequences (n <= 24), and the
+ * number of sequences attaining it.  Every sequence is scored from Eq. (2)
+ * directly; no symmetry is used. */
+int orc_bruteforce_min(int n, int64_t *emin, int64_t *count)
+{
+    if (n < 1 || n > 24)
+        return -1;
+    int8_t s[24];
+    int64_t best = -1, cnt = 0;
+    uint32_t total = 1u << n;
+    for (uint32_t code = 0; code < total; ++code) {
+        for (int i = 0; i < n; ++i)
+            s[i] = ((code >> i) & 1u) ? -1 : 1;
+        int64_t e = orc_energy(s, n);
+        if (best < 0 || e < best) {
+            best = e;
+            cnt = 1;
+        } else if (e == best) {
+            ++cnt;
+        }
+    }
+    *emin = best;
+    *count = cnt;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Neighbourhood energies.                                                    */
+/* ------------------------------------------------------------------------- */
+
+/* Definition: out[i] = E(flip(s, i)) for every i, each recomputed from
+ * Eq. (2) (the O(N^3)-per-step route the paper calls prohibitive, Sec. III.C). */
+void orc_neighbour_energies_recompute(const int8_t *s, int n, int64_t *out)
+{
+    int8_t t[256];
+    memcpy(t, s, (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        t[i] = (int8_t)-t[i];
+        out[i] = orc_energy(t, n);
+        t[i] = (int8_t)-t[i];
+    }
+}
+
+/* The paper's data structures (Sec. III.C, Table "combinedTable"):
+ * tableC[k][i] = s_i s_{i+k} (row k, the products behind C_k), and
+ * vectorC[k] = C_k, the row sums.  Flipping bit i negates the products that
+ * contain s_i: tableC[k][i] (when i+k < n) and tableC[k][i-k] (when i-k >= 0),
+ * so each neighbour's energy costs O(n) and the update after a move touches
+ * one "row and column" of products. */
+typedef struct {
+    int n;
+    int8_t table[128][128]; /* table[k][i], valid for 1 <= k < n, 0 <= i < n-k */
+    int64_t vec[128];       /* vec[k] = C_k */
+} tables_t;
+
+static void tables_build(tables_t *T, const int8_t *s, int n)
+{
+    T->n = n;
+    for (int k = 1; k < n; ++k) {
+        int64_t c = 0;
+        for (int i = 0; i + k < n; ++i) {
+            T->table[k][i] = (int8_t)(s[i] * s[i + k]);
+            c += T->table[k][i];
+        }
+        T->vec[k] = c;
+    }
+}
+
+/* Energy of flip(s, i) from the tables. */
+static int64_t tables_neighbour_energy(const tables_t *T, int i)
+{
+    int n = T->n;
+    int64_t e = 0;
+    for (int k = 1; k < n; ++k) {
+        int64_t c = T->vec[k];
+        if (i + k < n)
+            c -= 2 * (int64_t)T->table[k][i];
+        if (i - k >= 0)
+            c -= 2 * (int64_t)T->table[k][i - k];
+        e += c * c;
+    }
+    return e;
+}
+
+/* Apply flip(s, i) to the tables. */
+static void tables_flip(tables_t *T, int i)
+{
+    int n = T->n;
+    for (int k = 1; k < n; ++k) {
+        if (i + k < n) {
+            T->vec[k] -= 2 * (int64_t)T->table[k][i];
+            T->table[k][i] = (int8_t)-T->table[k][i];
+        }
+        if (i - k >= 0) {
+            T->vec[k] -= 2 * (int64_t)T->table[k][i - k];
+            T->table[k][i - k] = (int8_t)-T->table[k][i - k];
+        }
+    }
+}
+
+void orc_neighbour_energies_tables(const int8_t *s, int n, int64_t *out)
+{
+    tables_t *T = (tables_t *)malloc(sizeof(tables_t));
+    tables_build(T, s, n);
+    for (int i = 0; i < n; ++i)
+        out[i] = tables_neighbour_energy(T, i);
+    free(T);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Walk schedule: walk length maxIter and tenure range [minTabu, maxTabu].    */
+/* ------------------------------------------------------------------------- */
+enum { ORC_STEPS_FIXED = 0, ORC_STEPS_MULT_N = 1, ORC_STEPS_PAPER = 2 };
+enum { ORC_TENURE_LINEAR = 0, ORC_TENURE_PAPER = 1 };
+
+/*
+ * steps_rule
+ *   FIXED : maxIter = a
+ *   MULT_N: maxIter = a * n
+ *   PAPER : maxIter = randomInt(0, n) + floor(n/2) (Alg. 4, both ends
+ *           inclusive), one draw (entity, gen, 0, TAG_LEN), word 0.
+ * tenure_rule
+ *   LINEAR: minTabu = floor(lo_num*n/lo_den) + lo_add,
+ *           maxTabu = floor(hi_num*n/hi_den) + hi_add
+ *   PAPER : minTabu = floor(0.1*maxIter), maxTabu = floor(0.12*maxIter)
+ *           (Sec. III.B), in integers floor(T/10) and floor(3T/25).
+ * Returns 0, or -1 when the schedule is invalid (0 <= lo <= hi < n fails).
+ */
+int orc_walk_schedule(int n, int steps_rule, int steps_a, int tenure_rule,
+                      int lo_num, int lo_den, int lo_add,
+                      int hi_num, int hi_den, int hi_add,
+                      uint64_t seed, uint32_t entity, uint32_t gen,
+                      int *steps, int *lo, int *hi)
+{
+    int T;
+    if (steps_rule == ORC_STEPS_FIXED) {
+        T = steps_a;
+    } else if (steps_rule == ORC_STEPS_MULT_N) {
+        T = steps_a * n;
+    } else if (steps_rule == ORC_STEPS_PAPER) {
+        uint32_t w[4];
+        draw(seed, entity, gen, 0, ORC_TAG_LEN, w);
+        T = n / 2 + (int)uniform_below(w[0], (uint32_t)(n + 1));
+    } else {
+        return -1;
+    }
+    int l, h;
+    if (tenure_rule == ORC_TENURE_LINEAR) {
+        if (lo_den <= 0 || hi_den <= 0)
+            return -1;
+        l = lo_num * n / lo_den + lo_add;
+        h = hi_num * n / hi_den + hi_add;
+    } else if (tenure_rule == ORC_TENURE_PAPER) {
+        l = T / 10;
+        h = 3 * T / 25;
+    } else {
+        return -1;
+    }
+    if (T < 0 || l < 0 || h < l || h >= n)
+        return -1;
+    *steps = T;
+    *lo = l;
+    *hi = h;
+    return 0;
+}
+
+/* Random start of stand-alone walk `walk`: bit i of the 128-bit draw
+ * (walk, 0, 0, TAG_START) -- word i/32, bit i%32 -- set means s_i = -1. */
+void orc_random_start(int n, uint64_t seed, uint32_t walk, int8_t *s)
+{
+    uint32_t w[4];
+    draw(seed, walk, 0, 0, ORC_TAG_START, w);
+    for (int i = 0; i < n; ++i)
+        s[i] = ((w[i >> 5] >> (i & 31)) & 1u) ? -1 : 1;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Tabu search: Alg. 2 (and its thread-parallel form, Alg. 4).                */
+/* ------------------------------------------------------------------------- */
+/*
+ * One walk of `steps` iterations from `start`.
+ *   - tabuList starts at 0 and bestSeqTS = start (the start counts as
+ *     visited).
+ *   - Step t = 1..steps: every neighbour flip(pivot, i) is scored; i is
+ *     admissible when tabuList[i] < t, or -- with aspiration -- when its
+ *     energy is strictly below the walk's best so far (aspiration is this
+ *     implementation's addition; aspiration = 0 is the paper's rule).
+ *   - The admissible minimum is taken; ties are broken uniformly: with
+ *     (u0, u1) = words 0, 1 of draw (entity, gen, t, TAG_STEP), the tied
+ *     indices in ascending order T[0..c-1] give the move T[(u0*c) >> 32].
+ *   - pivot <- flip(pivot, i); tabuList[i] = t + lo + ((u1*(hi-lo+1)) >> 32).
+ *   - bestSeqTS <- pivot when E(pivot) < E(bestSeqTS) (strict).
+ * recompute = 1 scores every neighbour from Eq. (2) directly; recompute = 0
+ * uses tableC/vectorC (Sec. III.C).  Both must give identical walks.
+ * trace[t-1] (optional) receives the flipped index, trace_e[t-1] (optional)
+ * the energy after step t.
+ * Returns 0, or -1 if a step has no admissible move (cannot happen when
+ * hi < n: at most hi bits are tabu at any step).
+ */
+int orc_tabu_walk(int n, const int8_t *start, uint64_t seed, uint32_t entity,
+                  uint32_t gen, int steps, int lo, int hi, int aspiration,
+                  int recompute, int8_t *best, int64_t *best_e,
+                  int64_t *final_e, int16_t *trace, int64_t *trace_e)
+{
+    int8_t pivot[128];
+    int64_t tabu[128];
+    int64_t cand[128];
+    int ties[128];
+    if (n < 1 || n > 128 || lo < 0 || hi < lo)
+        return -1;
+
+    memcpy(pivot, start, (size_t)n);
+    memcpy(best, start, (size_t)n);
+    for (int i = 0; i < n; ++i)
+        tabu[i] = 0;
+    int64_t E = orc_energy(pivot, n);
+    int64_t bestE = E;
+
+    tables_t *T = NULL;
+    if (!recompute) {
+        T = (tables_t *)malloc(sizeof(tables_t));
+        tables_build(T, pivot, n);
+    }
+
+    for (int t = 1; t <= steps; ++t) {
+        if (recompute)
+            orc_neighbour_energies_recompute(pivot, n, cand);
+        else
+            for (int i = 0; i < n; ++i)
+                cand[i] = tables_neighbour_energy(T, i);
+
+        int64_t m = INT64_MAX;
+        int found = 0;
+        for (int i = 0; i < n; ++i) {
+            int admissible = (tabu[i] < t) || (aspiration && cand[i] < bestE);
+            if (admissible && (!found || cand[i] < m)) {
+                m = cand[i];
+                found = 1;
+            }
+        }
+        if (!found) {
+            free(T);
+            return -1;
+        }
+        int c = 0;
+        for (int i = 0; i < n; ++i) {
+            int admissible = (tabu[i] < t) || (aspiration && cand[i] < bestE);
+            if (admissible && cand[i] == m)
+                ties[c++] = i;
+        }
+        uint32_t w[4];
+        draw(seed, entity, gen, (uint32_t)t, ORC_TAG_STEP, w);
+        int pick = ties[uniform_below(w[0], (uint32_t)c)];
+
+        pivot[pick] = (int8_t)-pivot[pick];
+        if (!recompute)
+            tables_flip(T, pick);
+        E = m;
+        tabu[pick] = (int64_t)t + lo + (int64_t)uniform_below(w[1], (uint32_t)(hi - lo + 1));
+        if (E < bestE) {
+            bestE = E;
+            memcpy(best, pivot, (size_t)n);
+        }
+        if (trace)
+            trace[t - 1] = (int16_t)pick;
+        if (trace_e)
+            trace_e[t - 1] = E;
+    }
+    free(T);
+    *best_e = bestE;
+    *final_e = E;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Batched stand-alone walks (the batch driver), optionally over threads.     */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int64_t W;
+    const int32_t *ns;
+    int32_t n_uniform;
+    const int8_t *starts; /* [W][stride] or NULL for random starts */
+    int32_t stride;
+    uint64_t seed;
+    int steps_rule, steps_a, tenure_rule;
+    int lo_num, lo_den, lo_add, hi_num, hi_den, hi_add;
+    int aspiration;
+    int8_t *best_seq;     /* [W][stride], positions >= n are set to 0 */
+    int64_t *best_e;
+    int64_t *final_e;
+    int64_t next;         /* next walk to take (guarded by lock) */
+    pthread_mutex_t lock;
+    int status;
+} batch_job_t;
+
+static int run_one_walk(batch_job_t *J, int64_t w)
+{
+    int n = J->ns ? J->ns[w] : J->n_uniform;
+    int8_t start[128];
+    int steps, lo, hi;
+    if (n < 3 || n > 128 || n > J->stride)
+        return -1;
+    if (orc_walk_schedule(n, J->steps_rule, J->steps_a, J->tenure_rule,
+                          J->lo_num, J->lo_den, J->lo_add,
+                          J->hi_num, J->hi_den, J->hi_add,
+                          J->seed, (uint32_t)w, 0, &steps, &lo, &hi))
+        return -1;
+    if (J->starts)
+        memcpy(start, J->starts + w * J->stride, (size_t)n);
+    else
+        orc_random_start(n, J->seed, (uint32_t)w, start);
+    int8_t *out = J->best_seq + w * J->stride;
+    memset(out, 0, (size_t)J->stride);
+    return orc_tabu_walk(n, start, J->seed, (uint32_t)w, 0, steps, lo, hi,
+                         J->aspiration, 0, out, &J->best_e[w], &J->final_e[w],
+                         NULL, NULL);
+}
+
+static void *batch_worker(void *arg)
+{
+    batch_job_t *J = (batch_job_t *)arg;
+    for (;;) {
+        pthread_mutex_lock(&J->lock);
+        int64_t w = J->next++;
+        pthread_mutex_unlock(&J->lock);
+        if (w >= J->W)
+            break;
+        if (run_one_walk(J, w)) {
+            pthread_mutex_lock(&J->lock);
+            J->status = -1;
+            pthread_mutex_unlock(&J->lock);
+        }
+    }
+    return NULL;
+}
+
+int orc_tabu_batch(int64_t W, const int32_t *ns, int32_t n_uniform,
+                   const int8_t *starts, int32_t stride, uint64_t seed,
+                   int steps_rule, int steps_a, int tenure_rule,
+                   int lo_num, int lo_den, int lo_add,
+                   int hi_num, int hi_den, int hi_add, int aspiration,
+                   int8_t *best_seq, int64_t *best_e, int64_t *final_e,
+                   int nthreads)
+{
+    batch_job_t J;
+    memset(&J, 0, sizeof(J));
+    J.W = W; J.ns = ns; J.n_uniform = n_uniform; J.starts = starts;
+    J.stride = stride; J.seed = seed;
+    J.steps_rule = steps_rule; J.steps_a = steps_a; J.tenure_rule = tenure_rule;
+    J.lo_num = lo_num; J.lo_den = lo_den; J.lo_add = lo_add;
+    J.hi_num = hi_num; J.hi_den = hi_den; J.hi_add = hi_add;
+    J.aspiration = aspiration;
+    J.best_seq = best_seq; J.best_e = best_e; J.final_e = final_e;
+    pthread_mutex_init(&J.lock, NULL);
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > 256)
+        nthreads = 256;
+    pthread_t th[256];
+    int started = 0;
+    for (int i = 1; i < nthreads; ++i)
+        if (pthread_create(&th[started], NULL, batch_worker, &J) == 0)
+            ++started;
+    batch_worker(&J);
+    for (int i = 0; i < started; ++i)
+        pthread_join(th[i], NULL);
+    pthread_mutex_destroy(&J.lock);
+    return J.status;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Memetic tabu search: Alg. 1 (per replica, Alg. 3).                         */
+/* ------------------------------------------------------------------------- */
+/*
+ * Population state of one replica: pop[K][n] (+-1), popE[K], best[n], bestE.
+ *
+ * Initialisation (Alg. 1, first two lines): member m is the 128-bit draw
+ * (pop_id, m, 0, TAG_INIT) read as in orc_random_start; bestSeq is the
+ * lowest-index member of minimum energy.
+ */
+void orc_memetic_init(int n, int K, uint64_t seed, uint32_t pop_id,
+                      int8_t *pop, int64_t *popE, int8_t *best, int64_t *best_e)
+{
+    int argmin = 0;
+    for (int m = 0; m < K; ++m) {
+        uint32_t w[4];
+        draw(seed, pop_id, (uint32_t)m, 0, ORC_TAG_INIT, w);
+        int8_t *s = pop + (int64_t)m * n;
+        for (int i = 0; i < n; ++i)
+            s[i] = ((w[i >> 5] >> (i & 31)) & 1u) ? -1 : 1;
+        popE[m] = orc_energy(s, n);
+        if (popE[m] < popE[argmin])
+            argmin = m;
+    }
+    memcpy(best, pop + (int64_t)argmin * n, (size_t)n);
+    *best_e = popE[argmin];
+}
+
+/* Binary tournament (selectParents is unspecified in Alg. 1; this reading):
+ * two uniform draws with replacement, the lower energy wins, ties go to the
+ * first draw. */
+static int tournament(const int64_t *popE, int K, uint32_t u, uint32_t v)
+{
+    int i = (int)uniform_below(u, (uint32_t)K);
+    int j = (int)uniform_below(v, (uint32_t)K);
+    return popE[i] <= popE[j] ? i : j;
+}
+
+/*
+ * Advance one replica from generation g0 by up to n_gens generations
+ * (one generation = one pass of Alg. 1's loop body = one child).
+ * Generation g uses words w0..w7 = draws (pop_id, g, 0|1, TAG_GEN):
+ *   crossover when w0 < p_comb (randReal < p_comb with p_comb = p_comb/2^32):
+ *     parents a = tournament(w1, w2), b = tournament(w3, w4);
+ *     Combine = one-point crossover at cut = 1 + ((w5*(n-1)) >> 32):
+ *     child = a[0:cut] ++ b[cut:n];
+ *   otherwise Sample: child = pop[(w1*K) >> 32].
+ *   Mutate: bit i flips when word i%4 of draw (pop_id, g, i/4, TAG_MUT) is
+ *     below p_mut (probability p_mut/2^32).
+ *   child <- Tabu-Search(child) with entity pop_id and generation g.
+ *   bestSeq <- child when E(child) < E(bestSeq) (strict).
+ *   The child replaces member (w6*K) >> 32 (a uniform random individual).
+ * Stopping (Alg. 1's while condition): with target >= 0 the replica stops as
+ * soon as bestE <= target; *hit_gen is then the number of children produced
+ * when that first held (0 for the initial population); it stays -1 otherwise
+ * and is left unchanged if already set.
+ * Returns the number of generations executed, or -1 on an invalid schedule.
+ */
+int64_t orc_memetic_advance(int n, int K, uint32_t p_comb, uint32_t p_mut,
+                            int steps_rule, int steps_a, int tenure_rule,
+                            int lo_num, int lo_den, int lo_add,
+                            int hi_num, int hi_den, int hi_add, int aspiration,
+                            uint64_t seed, uint32_t pop_id, int64_t g0,
+                            int64_t n_gens, int64_t target,
+                            int8_t *pop, int64_t *popE, int8_t *best,
+                            int64_t *best_e, int64_t *hit_gen)
+{
+    int8_t child[128], child_best[128];
+    int64_t done = 0;
+    for (int64_t g = g0; g < g0 + n_gens; ++g) {
+        if (target >= 0 && *best_e <= target) {
+            if (*hit_gen < 0)
+                *hit_gen = g;
+            break;
+        }
+        uint32_t wa[4], wb[4];
+        draw(seed, pop_id, (uint32_t)g, 0, ORC_TAG_GEN, wa);
+        draw(seed, pop_id, (uint32_t)g, 1, ORC_TAG_GEN, wb);
+        if (wa[0] < p_comb) {
+            int a = tournament(popE, K, wa[1], wa[2]);
+            int b = tournament(popE, K, wa[3], wb[0]);
+            int cut = 1 + (int)uniform_below(wb[1], (uint32_t)(n - 1));
+            for (int i = 0; i < n; ++i)
+                child[i] = i < cut ? pop[(int64_t)a * n + i] : pop[(int64_t)b * n + i];
+        } else {
+            int c = (int)uniform_below(wa[1], (uint32_t)K);
+            memcpy(child, pop + (int64_t)c * n, (size_t)n);
+        }
+        for (int i = 0; i < n; ++i) {
+            uint32_t wm[4];
+            draw(seed, pop_id, (uint32_t)g, (uint32_t)(i >> 2), ORC_TAG_MUT, wm);
+            if (wm[i & 3] < p_mut)
+                child[i] = (int8_t)-child[i];
+        }
+        int steps, lo, hi;
+        if (orc_walk_schedule(n, steps_rule, steps_a, tenure_rule, lo_num, lo_den,
+                              lo_add, hi_num, hi_den, hi_add, seed, pop_id,
+                              (uint32_t)g, &steps, &lo, &hi))
+            return -1;
+        int64_t ce, fe;
+        if (orc_tabu_walk(n, child, seed, pop_id, (uint32_t)g, steps, lo, hi,
+                          aspiration, 0, child_best, &ce, &fe, NULL, NULL))
+            return -1;
+        if (ce < *best_e) {
+            *best_e = ce;
+            memcpy(best, child_best, (size_t)n);
+        }
+        int r = (int)uniform_below(wb[2], (uint32_t)K);
+        memcpy(pop + (int64_t)r * n, child_best, (size_t)n);
+        popE[r] = ce;
+        ++done;
+        if (target >= 0 && *best_e <= target) {
+            if (*hit_gen < 0)
+                *hit_gen = g + 1;
+            break;
+        }
+    }
+    return done;
+}

@@ -1,0 +1,115 @@
+"""Pins of the oracle's memetic search (Alg. 1 / Alg. 3).
+
+Checked against properties that hold for any correct run, with energies
+recomputed in numpy: the population's energies match its sequences, the best
+is never lost and never increases, the degenerate configuration (no
+crossover, no mutation, empty walks) only shuffles copies of the initial
+members, a run split into two calls equals the uninterrupted run, the
+early-stop generation is the first one at which the target holds, and no run
+beats the exhaustive optimum.
+"""
+import numpy as np
+
+from oracle import oracle as O
+from tests import npref
+
+MEM = O.Schedule(O.STEPS_PAPER, 0, O.TENURE_LINEAR, 0, 1, 1, 1, 10, 1, 1)
+
+
+def test_init():
+    st = O.MemeticState(20, 100, 1000, 0)
+    assert list(st.popE) == list(npref.energies_rows(st.pop))
+    a = int(np.argmin(st.popE))
+    assert st.bestE == st.popE[a] and np.array_equal(st.best, st.pop[a])
+    w = O.draw(1000, 0, 3, 0, O.TAG_INIT)  # member 3 of population 0
+    assert list(st.pop[3]) == [1 - 2 * ((int(w[i >> 5]) >> (i & 31)) & 1) for i in range(20)]
+
+
+def test_generation_invariants():
+    n = 20
+    st = O.MemeticState(n, 100, 1000, 0)
+    prev = st.bestE
+    for g in range(50):
+        assert st.advance(1, MEM, O.P_COMB_090, O.p_mut_inv_n(n)) == 1
+        assert st.bestE <= prev
+        prev = st.bestE
+        assert npref.energy(st.best) == st.bestE
+        assert list(st.popE) == list(npref.energies_rows(st.pop))
+        assert st.bestE <= st.popE.min()
+    emin, _ = O.bruteforce_min(n)
+    assert st.bestE >= emin
+    assert st.gen == 50
+
+
+def test_degenerate_copies_only():
+    # p_comb = 0, p_mutate = 0 and zero-step walks: every child is a copy of a
+    # member, so best never changes and every member stays an initial one
+    n = 24
+    zero = O.Schedule(O.STEPS_FIXED, 0, O.TENURE_LINEAR, 0, 1, 0, 0, 1, 0, 1)
+    st = O.MemeticState(n, 30, 5, 2)
+    init_rows = {tuple(r) for r in st.pop}
+    init_best = st.bestE
+    st.advance(200, zero, 0, 0)
+    assert st.bestE == init_best
+    assert all(tuple(r) in init_rows for r in st.pop)
+    assert list(st.popE) == list(npref.energies_rows(st.pop))
+
+
+def test_crossover_child_is_two_parents():
+    # with mutation off and empty walks, a crossover child is a prefix of one
+    # member followed by the suffix of another, cut in [1, N-1]
+    n = 16
+    zero = O.Schedule(O.STEPS_FIXED, 0, O.TENURE_LINEAR, 0, 1, 0, 0, 1, 0, 1)
+    st = O.MemeticState(n, 10, 11, 0)
+    for _ in range(100):
+        before = st.pop.copy()
+        st.advance(1, zero, 0xFFFFFFFF, 0)
+        changed = [r for r in range(10) if not np.array_equal(before[r], st.pop[r])]
+        for r in changed:
+            child = st.pop[r]
+            ok = any(np.array_equal(child[:c], before[a, :c]) and np.array_equal(child[c:], before[b, c:])
+                     for c in range(1, n) for a in range(10) for b in range(10))
+            assert ok
+
+
+def test_mutation_rate():
+    # p_mutate = 1/N: flips per child average 1 (sample-only, empty walks)
+    n = 32
+    zero = O.Schedule(O.STEPS_FIXED, 0, O.TENURE_LINEAR, 0, 1, 0, 0, 1, 0, 1)
+    st = O.MemeticState(n, 1, 3, 0)  # K = 1: the sampled parent is member 0
+    flips = []
+    for _ in range(3000):
+        before = st.pop[0].copy()
+        st.advance(1, zero, 0, O.p_mut_inv_n(n))
+        flips.append(int(np.sum(before != st.pop[0])))
+    assert abs(np.mean(flips) - 1.0) < 0.08
+
+
+def test_resume_equals_uninterrupted():
+    n = 28
+    a = O.MemeticState(n, 40, 99, 4)
+    b = a.copy()
+    a.advance(30, MEM, O.P_COMB_090, O.p_mut_inv_n(n))
+    b.advance(13, MEM, O.P_COMB_090, O.p_mut_inv_n(n))
+    b.advance(17, MEM, O.P_COMB_090, O.p_mut_inv_n(n))
+    assert np.array_equal(a.pop, b.pop) and np.array_equal(a.popE, b.popE)
+    assert np.array_equal(a.best, b.best) and a.bestE == b.bestE and a.gen == b.gen == 30
+
+
+def test_target_stops_at_first_hit():
+    n = 30
+    base = O.MemeticState(n, 50, 21, 1)
+    hist = [base.bestE]
+    run = base.copy()
+    for _ in range(40):
+        run.advance(1, MEM, O.P_COMB_090, O.p_mut_inv_n(n))
+        hist.append(run.bestE)
+    target = hist[25]
+    first = next(g for g, e in enumerate(hist) if e <= target)
+    st = base.copy()
+    done = st.advance(40, MEM, O.P_COMB_090, O.p_mut_inv_n(n), target=target)
+    assert st.hit == first and done == first and st.bestE == hist[first]
+    # a target met by the initial population is a hit at generation 0
+    st = base.copy()
+    assert st.advance(10, MEM, O.P_COMB_090, O.p_mut_inv_n(n), target=base.bestE) == 0
+    assert st.hit == 0
