@@ -1,0 +1,276 @@
+/*
+ * liblabs -- batched tabu search and memetic tabu search for Low
+ * Autocorrelation Binary Sequences (LABS) on AMD Instinct MI355X (gfx950).
+ *
+ * The problem and the method follow Z. Zhang, J. Shen et al., "New
+ * Improvements in Solving Large LABS Instances Using Massively Parallelizable
+ * Memetic Tabu Search", arXiv:2504.00987.  Citations name the paper's
+ * sections, equations, algorithms and tables.
+ *
+ * Conventions for every entry point
+ *   - Sequences are int8 rows of +1/-1 (the spins s_i of Sec. II), row-major
+ *     with a caller-given row stride in bytes (stride >= N).  Entries of a row
+ *     beyond its length N are ignored on input and written as 0 on output.
+ *   - Lengths satisfy LABS_MIN_N <= N <= LABS_MAX_N.
+ *   - Energies are E(s) = sum_{k=1}^{N-1} C_k(s)^2 with
+ *     C_k(s) = sum_{i=1}^{N-k} s_i s_{i+k} (Eq. 1, Eq. 2): exact int32.
+ *   - "device" pointers are HIP device allocations (for example the
+ *     data_ptr() of a torch tensor on the GPU); "host" pointers are ordinary
+ *     process memory.  The caller owns every buffer it passes; the library
+ *     never frees or retains caller memory after the call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls documented as asynchronous only enqueue work on `stream`; their
+ *     outputs are valid after the stream is synchronised.
+ *   - Every call returns a labs_status.  Nothing throws or aborts across the
+ *     ABI.  On failure, labs_last_error(h) holds a message; for LABS_E_HIP it
+ *     names the HIP error.  Invalid arguments are rejected before any work is
+ *     enqueued.
+ *   - Randomness is Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit
+ *     seed; every draw is addressed by (entity, generation, index, purpose),
+ *     so results are a pure function of (seed, parameters, inputs, item
+ *     index) and do not depend on the stream, batch composition, launch
+ *     configuration or execution mode.
+ *   - A handle is not thread-safe; use one handle per host thread.
+ */
+#ifndef LIBLABS_H
+#define LIBLABS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LABS_MIN_N 3
+#define LABS_MAX_N 128
+#define LABS_MAX_K 128 /* largest memetic population */
+
+typedef enum labs_status {
+    LABS_OK = 0,
+    LABS_E_INVAL = 1,     /* an argument is out of range or a pointer is NULL */
+    LABS_E_NOMEM = 2,     /* a device or pinned host allocation failed */
+    LABS_E_HIP = 3,       /* a HIP runtime call failed */
+    LABS_E_CANCELLED = 4, /* the request was cancelled */
+    LABS_E_NOTFOUND = 5,  /* unknown request id */
+    LABS_E_AGAIN = 6      /* the result is not ready yet */
+} labs_status;
+
+/* Walk length (maxIter) rule. */
+typedef enum labs_steps_rule {
+    LABS_STEPS_FIXED = 0,  /* maxIter = steps_a */
+    LABS_STEPS_MULT_N = 1, /* maxIter = steps_a * N */
+    LABS_STEPS_PAPER = 2   /* maxIter = randomInt(0, N) + floor(N/2), Alg. 4 */
+} labs_steps_rule;
+
+/* Tabu tenure rule: a move flipped at step t is tabu for steps
+ * t+1 .. t+tenure, tenure uniform in [minTabu, maxTabu] (Alg. 2). */
+typedef enum labs_tenure_rule {
+    /* minTabu = floor(lo_num*N/lo_den) + lo_add,
+     * maxTabu = floor(hi_num*N/hi_den) + hi_add */
+    LABS_TENURE_LINEAR = 0,
+    /* minTabu = floor(0.1*maxIter), maxTabu = floor(0.12*maxIter) (Sec. III.B) */
+    LABS_TENURE_PAPER = 1
+} labs_tenure_rule;
+
+/* Parameters of one tabu walk (Alg. 2 / Alg. 4).  Valid when, for every N
+ * used, 0 <= minTabu <= maxTabu < N (so some move is always admissible) and
+ * 0 <= maxIter <= LABS_MAX_STEPS. */
+typedef struct labs_tabu_params {
+    int32_t steps_rule;  /* labs_steps_rule */
+    int32_t steps_a;
+    int32_t tenure_rule; /* labs_tenure_rule */
+    int32_t lo_num, lo_den, lo_add;
+    int32_t hi_num, hi_den, hi_add;
+    int32_t aspiration;  /* 1: a tabu move is admissible when its energy is
+                            strictly below the walk's best (not in the paper;
+                            0 gives the paper's rule) */
+} labs_tabu_params;
+
+#define LABS_MAX_STEPS (1 << 20)
+
+/* Launch configuration of the batched walk kernels. */
+typedef struct labs_launch {
+    int32_t waves_per_group; /* 1, 2 or 4: workgroups of 64, 128 or 256 lanes,
+                                one walk per 64-lane wavefront */
+    int32_t persistent;      /* 1: a grid sized to the device drains a
+                                longest-first work queue; 0: one wavefront
+                                per walk */
+    int32_t groups_per_cu;   /* persistent grid = groups_per_cu x CUs (0: auto) */
+} labs_launch;
+
+typedef struct labs_handle labs_handle;
+
+/* Create a handle bound to HIP device `device` (ordinal).  The handle owns
+ * its device workspace, pinned staging memory, internal stream, tuned
+ * launch table and cached graphs.  Returns LABS_E_INVAL for a bad ordinal. */
+int labs_create(labs_handle **out, int device);
+
+/* Destroy a handle after synchronising its work.  NULL is accepted. */
+int labs_destroy(labs_handle *h);
+
+/* Message describing the handle's most recent failure ("" if none).  The
+ * pointer stays valid until the next call on the handle. */
+const char *labs_last_error(const labs_handle *h);
+
+/* Name of a status code (static string). */
+const char *labs_status_name(int status);
+
+/* Library version string (static). */
+const char *labs_version(void);
+
+/*
+ * Energies of a batch of sequences: Eq. (2) of Sec. II.
+ *   seqs      device int8 [count][stride], +-1 in the first N entries of a row
+ *   ns        device int32 [count] per-row lengths, or NULL to use n_uniform
+ *   n_uniform length of every row when ns == NULL
+ *   energies  device int32 [count] output
+ * Asynchronous on `stream`.  With per-row lengths the kernel clamps nothing:
+ * the caller guarantees LABS_MIN_N <= ns[b] <= min(stride, LABS_MAX_N).
+ */
+int labs_energy_batch(labs_handle *h, const int8_t *seqs, const int32_t *ns,
+                      int32_t n_uniform, int32_t stride, int64_t count,
+                      int32_t *energies, void *stream);
+
+/*
+ * Independent tabu walks (Alg. 2; the thread-parallel form of Alg. 4, one
+ * walk per 64-lane wavefront).  Walk w (0 <= w < walks) starts from row w
+ * of `starts`, or -- when starts == NULL -- from the 128-bit draw
+ * (w, 0, 0, START): bit i set means s_i = -1.  Each of its maxIter steps
+ * scores all N single-flip neighbours, takes the lowest-energy admissible
+ * one (ties: uniform by the step's draw), marks it tabu for a random tenure
+ * and keeps the best sequence visited (strict improvement).
+ *   p             walk parameters (host pointer)
+ *   starts        device int8 [walks][start_stride] or NULL
+ *   ns_host       HOST int32 [walks] per-walk lengths, or NULL (n_uniform)
+ *   seed          Philox key
+ *   best_seq      device int8 [walks][out_stride] best sequence of each walk
+ *   best_e        device int32 [walks] its energy
+ *   final_e       device int32 [walks] energy of the last pivot
+ *   trace         optional device int16 [walks][trace_stride]: the 0-based
+ *                 index flipped at step t goes to trace[w][t-1]
+ *                 (trace_stride >= the longest walk), or NULL
+ * Asynchronous on `stream`; ns_host is read before the call returns.
+ */
+int labs_tabu_batch(labs_handle *h, const labs_tabu_params *p,
+                    const int8_t *starts, int32_t start_stride,
+                    const int32_t *ns_host, int32_t n_uniform, int64_t walks,
+                    uint64_t seed, int8_t *best_seq, int32_t out_stride,
+                    int32_t *best_e, int32_t *final_e, int16_t *trace,
+                    int32_t trace_stride, void *stream);
+
+/* Set (launch != NULL) or clear (NULL: back to the tuned/default choice) the
+ * launch configuration used by labs_tabu_batch on this handle. */
+int labs_set_launch(labs_handle *h, const labs_launch *launch);
+
+/* The launch configuration labs_tabu_batch would use for length n. */
+int labs_get_launch(labs_handle *h, int32_t n, labs_launch *out);
+
+/*
+ * Autotuner: for each length bucket covering [n_min, n_max] it times every
+ * launch configuration {64, 128, 256 lanes per workgroup} x {one wave per
+ * walk, persistent queue at 1/2/4 groups per CU} on `walks` random-start
+ * walks with parameters `p`, keeps the fastest per bucket, and reports the
+ * number of configurations timed in *tried (may be NULL).  Synchronous;
+ * results never depend on the choice (only speed does).
+ */
+int labs_autotune(labs_handle *h, const labs_tabu_params *p, int32_t n_min,
+                  int32_t n_max, int64_t walks, uint64_t seed, int32_t *tried);
+
+/* Memetic search (Alg. 1; one replica per wavefront, Alg. 3). */
+typedef enum labs_mut_rule {
+    LABS_MUT_INV_N = 0, /* p_mutate = 1/N: flip when draw < floor(2^32 / N) */
+    LABS_MUT_FIXED = 1  /* flip when draw < p_mut */
+} labs_mut_rule;
+
+typedef enum labs_exec_mode {
+    LABS_MODE_PLAIN = 0,      /* one kernel launch per generation */
+    LABS_MODE_GRAPH = 1,      /* a captured graph of `chunk` one-generation
+                                 launches, replayed */
+    LABS_MODE_PERSISTENT = 2  /* one launch runs `chunk` generations with the
+                                 population resident on chip */
+} labs_exec_mode;
+
+typedef struct labs_memetic_params {
+    int32_t K;           /* population size, 2..LABS_MAX_K (paper: 100) */
+    uint32_t p_comb;     /* crossover when the draw < p_comb
+                            (paper: 0.9 -> 3865470566) */
+    int32_t mut_rule;    /* labs_mut_rule */
+    uint32_t p_mut;      /* threshold for LABS_MUT_FIXED */
+    labs_tabu_params tabu;
+    int64_t generations; /* children per replica (one per generation) */
+    int32_t target_e;    /* a replica stops once its best energy <= target_e
+                            (Alg. 1's loop condition); < 0 disables */
+    int32_t mode;        /* labs_exec_mode */
+    int32_t chunk;       /* generations between host checks (>= 1) */
+    int32_t stop_all;    /* 1: once any replica reaches target_e, every
+                            replica stops at the end of the current chunk
+                            (the global termination flag of Sec. IV) */
+} labs_memetic_params;
+
+/*
+ * Run `pops` independent memetic replicas (population id = index).
+ * Replica p: K members from the draws (p, m, 0, INIT); per generation g,
+ * crossover (binary-tournament parents, one-point cut) or sampling, per-bit
+ * mutation, a tabu walk with entity p and generation g, strict best update
+ * and replacement of a random member -- the order of Alg. 1.
+ *   ns_host   HOST int32 [pops] per-replica lengths, or NULL (n_uniform)
+ *   best_seq  device int8 [pops][out_stride] best sequence of each replica
+ *   best_e    device int32 [pops]
+ *   hit_gen   device int64 [pops]: children produced when best <= target
+ *             first held (0: the initial population), -1 if never (or NULL)
+ *   gens_done device int64 [pops]: generations executed (or NULL)
+ * Synchronous: returns after the outputs are written (it polls between
+ * chunks for the early-stop rules).
+ */
+int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
+                     const int32_t *ns_host, int32_t n_uniform, int32_t pops,
+                     uint64_t seed, int8_t *best_seq, int32_t out_stride,
+                     int32_t *best_e, int64_t *hit_gen, int64_t *gens_done,
+                     void *stream);
+
+/*
+ * Serving: a request loop that runs memetic solves of different N from a
+ * stream of requests with continuous batching.  Requests wait in FIFO order
+ * and are admitted as soon as enough resident population slots are free;
+ * all admitted replicas advance together, `chunk` generations per kernel
+ * launch, so requests that arrive while others run share the device.  A
+ * request's result equals labs_memetic_run on the same (N, seed, pops,
+ * params): the best of its replicas (lowest energy, then lowest replica id).
+ * The server runs its own host thread and HIP stream.
+ *   params     K, rules, target, chunk (generations/mode are per request)
+ *   max_slots  resident replicas (device memory: about
+ *              (K*20 + 64) bytes each); admission never exceeds it
+ */
+typedef struct labs_server labs_server;
+
+int labs_server_create(labs_handle *h, const labs_memetic_params *params,
+                       int32_t max_slots, labs_server **out);
+
+/* Enqueue a solve of length n with `pops` replicas of `generations`
+ * generations under `seed`.  *request_id receives the id.  Thread-safe. */
+int labs_server_submit(labs_server *s, int32_t n, uint64_t seed, int32_t pops,
+                       int64_t generations, int64_t *request_id);
+
+/* Fetch a result: LABS_E_AGAIN while pending; LABS_OK with best_seq (HOST
+ * int8 [n]), best_e and the latency in seconds (enqueue to completion)
+ * once done.  A fetched result is released.  Thread-safe. */
+int labs_server_poll(labs_server *s, int64_t request_id, int8_t *best_seq,
+                     int32_t *best_e, double *latency_s);
+
+/* Cancel a waiting or running request (its slots are freed at the next
+ * chunk); polling it then returns LABS_E_CANCELLED.  Thread-safe. */
+int labs_server_cancel(labs_server *s, int64_t request_id);
+
+/* Counters: requests waiting, running, done; resident replicas. */
+int labs_server_stats(labs_server *s, int64_t *waiting, int64_t *running,
+                      int64_t *done, int64_t *resident);
+
+/* Stop the loop (pending requests are dropped) and free the server. */
+int labs_server_destroy(labs_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBLABS_H */

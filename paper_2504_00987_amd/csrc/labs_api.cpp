@@ -1,0 +1,485 @@
+// The liblabs C ABI: handles, argument validation, workspaces, launch
+// selection, the autotuner and the memetic driver (plain / graph / persistent).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/liblabs.h"
+#include "labs_internal.h"
+#include "labs_handle.h"
+
+using namespace liblabs;
+
+// ---------------------------------------------------------------------------
+// Handle helpers
+// ---------------------------------------------------------------------------
+namespace liblabs {
+
+int fail(labs_handle *h, int code, const char *fmt, ...) {
+    if (h) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        h->last_error = buf;
+    }
+    return code;
+}
+
+int hip_fail(labs_handle *h, hipError_t e, const char *where) {
+    return fail(h, LABS_E_HIP, "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
+}
+
+DeviceGuard::DeviceGuard(int dev) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    if (prev_ != dev) hipSetDevice(dev);
+}
+DeviceGuard::~DeviceGuard() {
+    if (prev_ >= 0) hipSetDevice(prev_);
+}
+
+// Grow a device buffer to at least `bytes` (contents are not preserved).
+int DevBuf::reserve(labs_handle *h, size_t bytes) {
+    if (bytes <= size) return LABS_OK;
+    if (ptr) {
+        hipFree(ptr);
+        ptr = nullptr;
+        size = 0;
+    }
+    size_t want = std::max(bytes, (size_t)4096);
+    hipError_t e = hipMalloc(&ptr, want);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(h, LABS_E_NOMEM, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+    }
+    size = want;
+    return LABS_OK;
+}
+
+void DevBuf::release() {
+    if (ptr) hipFree(ptr);
+    ptr = nullptr;
+    size = 0;
+}
+
+int PinBuf::reserve(labs_handle *h, size_t bytes) {
+    if (bytes <= size) return LABS_OK;
+    if (ptr) {
+        hipHostFree(ptr);
+        ptr = nullptr;
+        size = 0;
+    }
+    size_t want = std::max(bytes, (size_t)4096);
+    hipError_t e = hipHostMalloc(&ptr, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(h, LABS_E_NOMEM, "hipHostMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+    }
+    size = want;
+    return LABS_OK;
+}
+
+void PinBuf::release() {
+    if (ptr) hipHostFree(ptr);
+    ptr = nullptr;
+    size = 0;
+}
+
+// The workspace (ns/order/counter arrays and staging) is shared by calls on
+// any stream: a new user waits for the previous user's completion event.
+int ws_acquire(labs_handle *h, hipStream_t s) {
+    if (h->ws_event_valid) {
+        hipError_t e = hipEventSynchronize(h->ws_event);  // staging is host-visible
+        if (e != hipSuccess) return hip_fail(h, e, "hipEventSynchronize");
+        e = hipStreamWaitEvent(s, h->ws_event, 0);
+        if (e != hipSuccess) return hip_fail(h, e, "hipStreamWaitEvent");
+    }
+    return LABS_OK;
+}
+
+int ws_release(labs_handle *h, hipStream_t s) {
+    hipError_t e = hipEventRecord(h->ws_event, s);
+    if (e != hipSuccess) return hip_fail(h, e, "hipEventRecord");
+    h->ws_event_valid = true;
+    return LABS_OK;
+}
+
+// Tenure/steps validation for one length.
+int check_rule(labs_handle *h, const RuleParams &r, int n) {
+    if (r.aspiration != 0 && r.aspiration != 1)
+        return fail(h, LABS_E_INVAL, "aspiration must be 0 or 1");
+    long long tmax;
+    if (r.steps_rule == LABS_STEPS_FIXED) {
+        tmax = r.steps_a;
+    } else if (r.steps_rule == LABS_STEPS_MULT_N) {
+        tmax = (long long)r.steps_a * n;
+    } else if (r.steps_rule == LABS_STEPS_PAPER) {
+        tmax = n / 2 + n;
+    } else {
+        return fail(h, LABS_E_INVAL, "unknown steps_rule %d", r.steps_rule);
+    }
+    if (r.steps_a < 0 || tmax < 0 || tmax > LABS_MAX_STEPS)
+        return fail(h, LABS_E_INVAL, "walk length out of range for N=%d", n);
+    long long lo, hi;
+    if (r.tenure_rule == LABS_TENURE_LINEAR) {
+        if (r.lo_den <= 0 || r.hi_den <= 0 || r.lo_num < 0 || r.hi_num < 0)
+            return fail(h, LABS_E_INVAL, "tenure fractions need num >= 0 and den > 0");
+        lo = (long long)r.lo_num * n / r.lo_den + r.lo_add;
+        hi = (long long)r.hi_num * n / r.hi_den + r.hi_add;
+    } else if (r.tenure_rule == LABS_TENURE_PAPER) {
+        lo = 0;
+        hi = 3 * tmax / 25;  // largest value over every possible maxIter
+    } else {
+        return fail(h, LABS_E_INVAL, "unknown tenure_rule %d", r.tenure_rule);
+    }
+    if (lo < 0 || hi < lo || hi >= n)
+        return fail(h, LABS_E_INVAL,
+                    "tenure range [%lld, %lld] invalid for N=%d (need 0 <= min <= max < N)", lo,
+                    hi, n);
+    return LABS_OK;
+}
+
+long long max_steps(const RuleParams &r, int n) {
+    if (r.steps_rule == LABS_STEPS_FIXED) return r.steps_a;
+    if (r.steps_rule == LABS_STEPS_MULT_N) return (long long)r.steps_a * n;
+    return n / 2 + n;
+}
+
+RuleParams to_rule(const labs_tabu_params &p) {
+    RuleParams r;
+    r.steps_rule = p.steps_rule;
+    r.steps_a = p.steps_a;
+    r.tenure_rule = p.tenure_rule;
+    r.lo_num = p.lo_num;
+    r.lo_den = p.lo_den;
+    r.lo_add = p.lo_add;
+    r.hi_num = p.hi_num;
+    r.hi_den = p.hi_den;
+    r.hi_add = p.hi_add;
+    r.aspiration = p.aspiration;
+    return r;
+}
+
+int bucket_of(int n) { return std::min(7, std::max(0, (n - 1) / 16)); }
+
+labs_launch default_launch(labs_handle *h, bool uneven) {
+    labs_launch l;
+    l.waves_per_group = 1;
+    l.persistent = uneven ? 1 : 0;
+    l.groups_per_cu = 0;
+    (void)h;
+    return l;
+}
+
+int persistent_groups(labs_handle *h, const labs_launch &l) {
+    int per_cu = l.groups_per_cu;
+    if (per_cu <= 0) per_cu = std::max(1, 8 / std::max(1, (int)l.waves_per_group));
+    return per_cu * h->num_cus;
+}
+
+}  // namespace liblabs
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *labs_version(void) { return "liblabs 0.1 (gfx950)"; }
+
+const char *labs_status_name(int status) {
+    switch (status) {
+    case LABS_OK: return "LABS_OK";
+    case LABS_E_INVAL: return "LABS_E_INVAL";
+    case LABS_E_NOMEM: return "LABS_E_NOMEM";
+    case LABS_E_HIP: return "LABS_E_HIP";
+    case LABS_E_CANCELLED: return "LABS_E_CANCELLED";
+    case LABS_E_NOTFOUND: return "LABS_E_NOTFOUND";
+    case LABS_E_AGAIN: return "LABS_E_AGAIN";
+    default: return "LABS_E_UNKNOWN";
+    }
+}
+
+int labs_create(labs_handle **out, int device) {
+    if (!out) return LABS_E_INVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        (void)hipGetLastError();
+        return LABS_E_INVAL;
+    }
+    labs_handle *h = new labs_handle();
+    h->device = device;
+    DeviceGuard g(device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete h;
+        return LABS_E_HIP;
+    }
+    h->num_cus = prop.multiProcessorCount;
+    h->arch = prop.gcnArchName;
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ws_event, hipEventDisableTiming) != hipSuccess) {
+        delete h;
+        return LABS_E_HIP;
+    }
+    h->tuned.assign(8, labs_launch{0, 0, 0});
+    *out = h;
+    return LABS_OK;
+}
+
+int labs_destroy(labs_handle *h) {
+    if (!h) return LABS_OK;
+    DeviceGuard g(h->device);
+    hipDeviceSynchronize();
+    h->ws.release();
+    h->mem.release();
+    h->pin.release();
+    if (h->ws_event) hipEventDestroy(h->ws_event);
+    if (h->stream) hipStreamDestroy(h->stream);
+    delete h;
+    return LABS_OK;
+}
+
+const char *labs_last_error(const labs_handle *h) {
+    return h ? h->last_error.c_str() : "null handle";
+}
+
+int labs_energy_batch(labs_handle *h, const int8_t *seqs, const int32_t *ns, int32_t n_uniform,
+                      int32_t stride, int64_t count, int32_t *energies, void *stream) {
+    if (!h) return LABS_E_INVAL;
+    h->last_error.clear();
+    if (count < 0) return fail(h, LABS_E_INVAL, "count < 0");
+    if (count == 0) return LABS_OK;
+    if (!seqs || !energies) return fail(h, LABS_E_INVAL, "null seqs or energies");
+    if (!ns && (n_uniform < LABS_MIN_N || n_uniform > LABS_MAX_N))
+        return fail(h, LABS_E_INVAL, "n_uniform=%d out of [%d, %d]", n_uniform, LABS_MIN_N,
+                    LABS_MAX_N);
+    if (stride < (ns ? LABS_MIN_N : n_uniform))
+        return fail(h, LABS_E_INVAL, "stride=%d shorter than a row", stride);
+    if (count > (int64_t)0x7fffffff * 4) return fail(h, LABS_E_INVAL, "count too large");
+    DeviceGuard g(h->device);
+    hipError_t e = launch_energy(seqs, ns, n_uniform, stride, count, energies,
+                                 (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(h, e, "energy kernel launch");
+    return LABS_OK;
+}
+
+int labs_set_launch(labs_handle *h, const labs_launch *launch) {
+    if (!h) return LABS_E_INVAL;
+    h->last_error.clear();
+    if (!launch) {
+        h->has_override = false;
+        return LABS_OK;
+    }
+    const int w = launch->waves_per_group;
+    if (w != 1 && w != 2 && w != 4) return fail(h, LABS_E_INVAL, "waves_per_group must be 1, 2 or 4");
+    if (launch->persistent != 0 && launch->persistent != 1)
+        return fail(h, LABS_E_INVAL, "persistent must be 0 or 1");
+    if (launch->groups_per_cu < 0 || launch->groups_per_cu > 64)
+        return fail(h, LABS_E_INVAL, "groups_per_cu out of [0, 64]");
+    h->override_launch = *launch;
+    h->has_override = true;
+    return LABS_OK;
+}
+
+int labs_get_launch(labs_handle *h, int32_t n, labs_launch *out) {
+    if (!h || !out) return LABS_E_INVAL;
+    h->last_error.clear();
+    if (n < LABS_MIN_N || n > LABS_MAX_N) return fail(h, LABS_E_INVAL, "n out of range");
+    *out = liblabs::choose_launch(h, n, false);
+    return LABS_OK;
+}
+
+}  // extern "C"
+
+namespace liblabs {
+
+labs_launch choose_launch(labs_handle *h, int n_max, bool uneven) {
+    if (h->has_override) return h->override_launch;
+    const labs_launch &t = h->tuned[bucket_of(n_max)];
+    if (t.waves_per_group != 0) return t;
+    return default_launch(h, uneven);
+}
+
+// Shared body of labs_tabu_batch (also used by the autotuner).
+int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *starts,
+                    int32_t start_stride, const int32_t *ns_host, int32_t n_uniform, int64_t W,
+                    uint64_t seed, int8_t *best_seq, int32_t out_stride, int32_t *best_e,
+                    int32_t *final_e, int16_t *trace, int32_t trace_stride, hipStream_t s,
+                    const labs_launch *force) {
+    if (!p) return fail(h, LABS_E_INVAL, "null params");
+    if (W < 0) return fail(h, LABS_E_INVAL, "walks < 0");
+    if (W == 0) return LABS_OK;
+    if (W > 0x7fffffff) return fail(h, LABS_E_INVAL, "walks > 2^31-1");
+    if (!best_seq || !best_e || !final_e) return fail(h, LABS_E_INVAL, "null output");
+    const RuleParams rule = to_rule(*p);
+
+    // Lengths: validate every distinct N and find the longest.
+    int n_min = n_uniform, n_max = n_uniform;
+    std::vector<char> seen(LABS_MAX_N + 1, 0);
+    if (ns_host) {
+        n_min = LABS_MAX_N + 1;
+        n_max = 0;
+        for (int64_t i = 0; i < W; ++i) {
+            const int n = ns_host[i];
+            if (n < LABS_MIN_N || n > LABS_MAX_N)
+                return fail(h, LABS_E_INVAL, "ns[%lld]=%d out of [%d, %d]", (long long)i, n,
+                            LABS_MIN_N, LABS_MAX_N);
+            seen[n] = 1;
+            n_min = std::min(n_min, n);
+            n_max = std::max(n_max, n);
+        }
+    } else {
+        if (n_uniform < LABS_MIN_N || n_uniform > LABS_MAX_N)
+            return fail(h, LABS_E_INVAL, "n_uniform=%d out of [%d, %d]", n_uniform, LABS_MIN_N,
+                        LABS_MAX_N);
+        seen[n_uniform] = 1;
+    }
+    long long tmax = 0;
+    for (int n = LABS_MIN_N; n <= LABS_MAX_N; ++n) {
+        if (!seen[n]) continue;
+        int rc = check_rule(h, rule, n);
+        if (rc) return rc;
+        tmax = std::max(tmax, max_steps(rule, n));
+    }
+    if (out_stride < n_max) return fail(h, LABS_E_INVAL, "out_stride=%d < N=%d", out_stride, n_max);
+    if (starts && start_stride < n_max)
+        return fail(h, LABS_E_INVAL, "start_stride=%d < N=%d", start_stride, n_max);
+    if (trace && trace_stride < tmax)
+        return fail(h, LABS_E_INVAL, "trace_stride=%d < longest walk %lld", trace_stride, tmax);
+
+    const bool uneven = ns_host && n_min != n_max;
+    const labs_launch L = force ? *force : choose_launch(h, n_max, uneven);
+
+    DeviceGuard g(h->device);
+    int rc = ws_acquire(h, s);
+    if (rc) return rc;
+    // Workspace: [counter (256 B)] [ns (W int32)] [order (W int32)]
+    const size_t bytes = 256 + (ns_host ? 2 * (size_t)W * sizeof(int32_t) : 0);
+    if ((rc = h->ws.reserve(h, bytes))) return rc;
+    TabuLaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.counter = (uint32_t *)h->ws.ptr;
+    if (ns_host) {
+        if ((rc = h->pin.reserve(h, 2 * (size_t)W * sizeof(int32_t)))) return rc;
+        int32_t *pn = (int32_t *)h->pin.ptr;
+        int32_t *po = pn + W;
+        std::memcpy(pn, ns_host, (size_t)W * sizeof(int32_t));
+        // Longest walks first (cost grows like N^3 at fixed steps per N).
+        std::iota(po, po + W, 0);
+        std::stable_sort(po, po + W, [&](int32_t x, int32_t y) { return pn[x] > pn[y]; });
+        int32_t *dn = (int32_t *)((char *)h->ws.ptr + 256);
+        hipError_t e = hipMemcpyAsync(dn, pn, 2 * (size_t)W * sizeof(int32_t),
+                                      hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(h, e, "hipMemcpyAsync");
+        a.ns = dn;
+        a.order = L.persistent ? dn + W : nullptr;
+    }
+    a.starts = starts;
+    a.start_stride = start_stride;
+    a.n_uniform = n_uniform;
+    a.n_max = n_max;
+    a.W = W;
+    a.k0 = (uint32_t)(seed & 0xffffffffu);
+    a.k1 = (uint32_t)(seed >> 32);
+    a.rule = rule;
+    a.best_seq = best_seq;
+    a.out_stride = out_stride;
+    a.best_e = best_e;
+    a.final_e = final_e;
+    a.trace = trace;
+    a.trace_stride = trace_stride;
+    const int groups = L.persistent ? persistent_groups(h, L) : 0;
+    hipError_t e = launch_tabu(a, L.waves_per_group, groups, s);
+    if (e != hipSuccess) return hip_fail(h, e, "tabu kernel launch");
+    return ws_release(h, s);
+}
+
+}  // namespace liblabs
+
+extern "C" int labs_tabu_batch(labs_handle *h, const labs_tabu_params *p, const int8_t *starts,
+                               int32_t start_stride, const int32_t *ns_host, int32_t n_uniform,
+                               int64_t walks, uint64_t seed, int8_t *best_seq,
+                               int32_t out_stride, int32_t *best_e, int32_t *final_e,
+                               int16_t *trace, int32_t trace_stride, void *stream) {
+    if (!h) return LABS_E_INVAL;
+    h->last_error.clear();
+    return tabu_batch_impl(h, p, starts, start_stride, ns_host, n_uniform, walks, seed, best_seq,
+                           out_stride, best_e, final_e, trace, trace_stride,
+                           (hipStream_t)stream, nullptr);
+}
+
+extern "C" int labs_autotune(labs_handle *h, const labs_tabu_params *p, int32_t n_min,
+                             int32_t n_max, int64_t walks, uint64_t seed, int32_t *tried) {
+    if (!h) return LABS_E_INVAL;
+    h->last_error.clear();
+    if (!p) return fail(h, LABS_E_INVAL, "null params");
+    if (n_min < LABS_MIN_N || n_max > LABS_MAX_N || n_min > n_max)
+        return fail(h, LABS_E_INVAL, "bad length range [%d, %d]", n_min, n_max);
+    if (walks <= 0 || walks > (1 << 24)) return fail(h, LABS_E_INVAL, "walks out of (0, 2^24]");
+    DeviceGuard g(h->device);
+    hipStream_t s = h->stream;
+    std::vector<int32_t> ns((size_t)walks);
+    for (int64_t i = 0; i < walks; ++i) ns[(size_t)i] = n_min + (int32_t)(i % (n_max - n_min + 1));
+    int8_t *best_seq = nullptr;
+    int32_t *be = nullptr, *fe = nullptr;
+    hipEvent_t e0, e1;
+    hipError_t e = hipMalloc(&best_seq, (size_t)walks * LABS_MAX_N);
+    if (e == hipSuccess) e = hipMalloc(&be, (size_t)walks * 4);
+    if (e == hipSuccess) e = hipMalloc(&fe, (size_t)walks * 4);
+    if (e != hipSuccess) {
+        if (best_seq) hipFree(best_seq);
+        if (be) hipFree(be);
+        (void)hipGetLastError();
+        return fail(h, LABS_E_NOMEM, "autotune buffers");
+    }
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    std::vector<labs_launch> cands;
+    for (int w : {1, 2, 4}) {
+        cands.push_back(labs_launch{w, 0, 0});
+        for (int gpc : {1, 2, 4, 8}) cands.push_back(labs_launch{w, 1, gpc * 4 / w});
+    }
+    float best_ms = 1e30f;
+    labs_launch best{1, 0, 0};
+    int rc = LABS_OK, n_tried = 0;
+    for (const labs_launch &c : cands) {
+        float tot = 0.f;
+        for (int rep = 0; rep < 3 && rc == LABS_OK; ++rep) {
+            hipEventRecord(e0, s);
+            rc = tabu_batch_impl(h, p, nullptr, 0, n_min == n_max ? nullptr : ns.data(), n_min,
+                                 walks, seed, best_seq, LABS_MAX_N, be, fe, nullptr, 0, s, &c);
+            hipEventRecord(e1, s);
+            hipEventSynchronize(e1);
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) tot += ms;  // first repetition is a warm-up
+        }
+        if (rc) break;
+        ++n_tried;
+        if (tot < best_ms) {
+            best_ms = tot;
+            best = c;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(best_seq);
+    hipFree(be);
+    hipFree(fe);
+    if (rc) return rc;
+    h->tuned[bucket_of(n_max)] = best;
+    if (tried) *tried = n_tried;
+    return LABS_OK;
+}

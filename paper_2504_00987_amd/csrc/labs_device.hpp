@@ -1,0 +1,455 @@
+// Device building blocks of liblabs (gfx950): counter-based RNG, wavefront
+// primitives, 128-bit sequence masks and the bit-sliced tabu walk.
+//
+// One tabu walk (Alg. 2 / Alg. 4 of arXiv:2504.00987) runs on one 64-lane
+// wavefront.  The sequence is a wave-uniform bit mask (bit i set <=> s_i = -1)
+// held in scalar registers; lane l owns neighbour j = l (and j = l + 64 when
+// N > 64) and lag k = l + 1 (and k = l + 65).  The autocorrelation table C_k
+// (Eq. 1) lives one entry per lane and is exposed to every lane as eight
+// wave-uniform bit planes (two's complement, built with ballots), so the
+// score of neighbour j,
+//
+//     dE_j = 4 * ( sum_k t_jk^2  -  s_j * sum_k t_jk C_k ),
+//     t_jk = s_{j+k} + s_{j-k}   (terms outside the sequence are 0),
+//
+// is evaluated with AND + popcount over 64-bit words instead of one
+// multiply-add per lag: sum_k t_jk C_k = PS(N-1-j) + PS(j)
+// - 2 * sum_p w_p * popcount((R_j | L_j) & plane_p), with R_j / L_j the
+// neighbour's right / left windows of set bits, PS the prefix sums of C and
+// w_p the plane weights.  Planes that only repeat the sign bit are skipped.
+// The flip of s_j changes C_k by -2 s_j t_jk (the paper's O(N) "one row and
+// column" update of Sec. III.C), applied lane-parallel.  All arithmetic is
+// exact int32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <limits.h>
+
+#include "labs_internal.h"
+
+namespace liblabs {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+// ---------------------------------------------------------------------------
+enum : uint32_t {
+    kTagStart = 1,  // random start of a stand-alone walk
+    kTagStep = 2,   // per tabu step: tie-break word 0, tenure word 1
+    kTagLen = 3,    // per walk: random walk length, word 0
+    kTagInit = 4,   // per population member: initial sequence
+    kTagGen = 5,    // per generation: crossover, parents, cut, replacement
+    kTagMut = 6     // per generation: mutation words
+};
+
+struct Draw4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Draw4 philox10(uint32_t x0, uint32_t x1, uint32_t x2,
+                                          uint32_t x3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a0 = x0, a2 = x2;
+        x0 = __umulhi(0xCD9E8D57u, a2) ^ x1 ^ k0;
+        x2 = __umulhi(0xD2511F53u, a0) ^ x3 ^ k1;
+        x1 = 0xCD9E8D57u * a2;
+        x3 = 0xD2511F53u * a0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {x0, x1, x2, x3};
+}
+
+// Uniform integer in [0, range) from a 32-bit word: (u * range) >> 32.
+__device__ __forceinline__ uint32_t below(uint32_t u, uint32_t range) {
+    return __umulhi(u, range);
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront primitives (wave64).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() {
+    return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) {
+    return __builtin_amdgcn_ballot_w64(p);
+}
+
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ int rank_below(uint64_t mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ int readlane(int v, int l) {
+    return __builtin_amdgcn_readlane(v, l);
+}
+
+__device__ __forceinline__ uint32_t readlane_u(uint32_t v, int l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+// Orders this wavefront's LDS accesses across lanes.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// DPP controls (GFX9 encoding).
+#define LABS_DPP_QUAD_1032 0xB1
+#define LABS_DPP_QUAD_2301 0x4E
+#define LABS_DPP_ROW_SHR(n) (0x110 + (n))
+#define LABS_DPP_ROW_MIRROR 0x140
+#define LABS_DPP_ROW_HALF_MIRROR 0x141
+#define LABS_DPP_ROW_BCAST15 0x142
+#define LABS_DPP_ROW_BCAST31 0x143
+
+// Minimum over the 64 lanes, returned wave-uniform.
+__device__ __forceinline__ int wave_min(int v) {
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, LABS_DPP_QUAD_1032, 0xf, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, LABS_DPP_QUAD_2301, 0xf, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, LABS_DPP_ROW_HALF_MIRROR, 0xf, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, LABS_DPP_ROW_MIRROR, 0xf, 0xf, false));
+    const int a = readlane(v, 0), b = readlane(v, 16), c = readlane(v, 32), d = readlane(v, 48);
+    return min(min(a, b), min(c, d));
+}
+
+// Sum over the 64 lanes, returned wave-uniform.
+__device__ __forceinline__ int wave_sum(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_QUAD_1032, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_QUAD_2301, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_HALF_MIRROR, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_MIRROR, 0xf, 0xf, false);
+    return readlane(v, 0) + readlane(v, 16) + readlane(v, 32) + readlane(v, 48);
+}
+
+// Inclusive prefix sum over lanes 0..63 (lane l receives v_0 + ... + v_l).
+__device__ __forceinline__ int wave_scan(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_SHR(1), 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_SHR(2), 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_SHR(4), 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_SHR(8), 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_BCAST15, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_BCAST31, 0xc, 0xf, false);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Sequence masks: 64-bit for N <= 64, 128-bit for N <= 128.
+// ---------------------------------------------------------------------------
+struct M128 {
+    uint64_t lo, hi;
+};
+
+__device__ __forceinline__ uint64_t m_and(uint64_t a, uint64_t b) { return a & b; }
+__device__ __forceinline__ uint64_t m_or(uint64_t a, uint64_t b) { return a | b; }
+__device__ __forceinline__ uint64_t m_xor(uint64_t a, uint64_t b) { return a ^ b; }
+__device__ __forceinline__ uint64_t m_not(uint64_t a) { return ~a; }
+__device__ __forceinline__ bool m_eq(uint64_t a, uint64_t b) { return a == b; }
+__device__ __forceinline__ int m_popc(uint64_t a) { return __popcll(a); }
+// a >> sh for 0 <= sh <= 64 (64 gives 0).
+__device__ __forceinline__ uint64_t m_shr(uint64_t a, int sh) {
+    return sh >= 64 ? 0ull : (a >> sh);
+}
+// Bits [0, n) set, 0 <= n <= 64.
+__device__ __forceinline__ uint64_t m_low(uint64_t, int n) {
+    return n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+}
+__device__ __forceinline__ int m_bit(uint64_t a, int i) { return (int)((a >> i) & 1ull); }
+__device__ __forceinline__ uint64_t m_onebit(uint64_t, int i) { return 1ull << i; }
+
+__device__ __forceinline__ M128 m_and(M128 a, M128 b) { return {a.lo & b.lo, a.hi & b.hi}; }
+__device__ __forceinline__ M128 m_or(M128 a, M128 b) { return {a.lo | b.lo, a.hi | b.hi}; }
+__device__ __forceinline__ M128 m_xor(M128 a, M128 b) { return {a.lo ^ b.lo, a.hi ^ b.hi}; }
+__device__ __forceinline__ M128 m_not(M128 a) { return {~a.lo, ~a.hi}; }
+__device__ __forceinline__ bool m_eq(M128 a, M128 b) { return a.lo == b.lo && a.hi == b.hi; }
+__device__ __forceinline__ int m_popc(M128 a) { return __popcll(a.lo) + __popcll(a.hi); }
+// a >> sh for 0 <= sh <= 128.
+__device__ __forceinline__ M128 m_shr(M128 a, int sh) {
+    M128 r;
+    if (sh >= 64) {
+        r.lo = sh >= 128 ? 0ull : (a.hi >> (sh - 64));
+        r.hi = 0ull;
+    } else if (sh == 0) {
+        r = a;
+    } else {
+        r.lo = (a.lo >> sh) | (a.hi << (64 - sh));
+        r.hi = a.hi >> sh;
+    }
+    return r;
+}
+__device__ __forceinline__ M128 m_low(M128, int n) {
+    M128 r;
+    if (n >= 128) {
+        r.lo = ~0ull; r.hi = ~0ull;
+    } else if (n >= 64) {
+        r.lo = ~0ull; r.hi = (1ull << (n - 64)) - 1ull;
+    } else {
+        r.lo = (1ull << n) - 1ull; r.hi = 0ull;
+    }
+    return r;
+}
+__device__ __forceinline__ int m_bit(M128 a, int i) {
+    return i < 64 ? (int)((a.lo >> i) & 1ull) : (int)((a.hi >> (i - 64)) & 1ull);
+}
+__device__ __forceinline__ M128 m_onebit(M128, int i) {
+    M128 r;
+    r.lo = i < 64 ? (1ull << i) : 0ull;
+    r.hi = i < 64 ? 0ull : (1ull << (i - 64));
+    return r;
+}
+
+template <int NW> struct MaskOf;
+template <> struct MaskOf<1> { using type = uint64_t; };
+template <> struct MaskOf<2> { using type = M128; };
+
+__device__ __forceinline__ uint64_t mask_from(uint64_t lo, uint64_t) { return lo; }
+__device__ __forceinline__ M128 mask_from(uint64_t lo, uint64_t hi, M128) { return {lo, hi}; }
+__device__ __forceinline__ uint64_t mask_lo(uint64_t a) { return a; }
+__device__ __forceinline__ uint64_t mask_hi(uint64_t) { return 0ull; }
+__device__ __forceinline__ uint64_t mask_lo(M128 a) { return a.lo; }
+__device__ __forceinline__ uint64_t mask_hi(M128 a) { return a.hi; }
+
+template <int NW>
+__device__ __forceinline__ typename MaskOf<NW>::type make_mask(uint64_t lo, uint64_t hi) {
+    if constexpr (NW == 1) {
+        return lo;
+    } else {
+        return M128{lo, hi};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Walk schedule: maxIter and the tenure range.
+// ---------------------------------------------------------------------------
+struct Schedule {
+    int T, lo, hi;
+};
+
+__device__ __forceinline__ Schedule make_schedule(const RuleParams &r, int N, uint32_t k0,
+                                                  uint32_t k1, uint32_t entity, uint32_t gen) {
+    Schedule s;
+    if (r.steps_rule == 0) {
+        s.T = r.steps_a;
+    } else if (r.steps_rule == 1) {
+        s.T = r.steps_a * N;
+    } else {
+        const Draw4 d = philox10(entity, gen, 0u, kTagLen, k0, k1);
+        s.T = N / 2 + (int)below(d.w0, (uint32_t)(N + 1));
+    }
+    if (r.tenure_rule == 0) {
+        s.lo = r.lo_num * N / r.lo_den + r.lo_add;
+        s.hi = r.hi_num * N / r.hi_den + r.hi_add;
+    } else {
+        s.lo = s.T / 10;
+        s.hi = 3 * s.T / 25;
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Energy of a sequence mask, computed by the whole wavefront (lane l owns
+// lags l+1 and l+65): C_k = (N-k) - 2 * popcount((M ^ (M >> k)) & low(N-k)).
+// ---------------------------------------------------------------------------
+template <typename Mask>
+__device__ __forceinline__ int lag_corr(Mask M, int N, int k) {
+    return (N - k) - 2 * m_popc(m_and(m_xor(M, m_shr(M, k)), m_low(M, N - k)));
+}
+
+// Energy of one mask computed by a single lane (lane-serial, O(N) popcounts).
+template <typename Mask>
+__device__ __forceinline__ int lane_energy(Mask M, int N) {
+    int e = 0;
+    for (int k = 1; k < N; ++k) {
+        const int c = lag_corr(M, N, k);
+        e += c * c;
+    }
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// The tabu walk.
+// ---------------------------------------------------------------------------
+template <int NW>
+struct WalkResult {
+    typename MaskOf<NW>::type best;
+    int best_e;
+    int final_e;
+};
+
+// Bit planes of the lane-held table C (two's complement, bits 0..7) and the
+// number q of planes needed: planes q-1..7 all equal the sign plane, so
+// C_k = sum_{p<q-1} 2^p bit_p - 2^(q-1) bit_(q-1).
+template <int NW>
+__device__ __forceinline__ int build_planes(const int (&C)[NW],
+                                            typename MaskOf<NW>::type (&P)[8]) {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        const uint64_t lo = ballot(((C[0] >> p) & 1) != 0);
+        uint64_t hi = 0ull;
+        if constexpr (NW == 2) hi = ballot(((C[1] >> p) & 1) != 0);
+        P[p] = make_mask<NW>(lo, hi);
+    }
+    int q = 1;
+#pragma unroll
+    for (int p = 0; p < 7; ++p)
+        if (!m_eq(P[p], P[7])) q = p + 2;
+    return q;
+}
+
+// Runs one walk of sch.T steps from mask M0 (bits >= N must be clear).
+//   ps     per-wavefront LDS scratch of 129 ints (prefix sums of C)
+//   trace  optional: trace[t-1] = flipped index (written by lane 0)
+// Every lane of the wavefront must call this with identical uniform inputs.
+template <int NW>
+__device__ WalkResult<NW> tabu_walk(const int N, const typename MaskOf<NW>::type M0,
+                                    const Schedule sch, const int aspiration,
+                                    const uint32_t k0, const uint32_t k1,
+                                    const uint32_t entity, const uint32_t gen,
+                                    int *__restrict__ ps, int16_t *__restrict__ trace) {
+    using Mask = typename MaskOf<NW>::type;
+    const int lane = lane_id();
+    Mask M = M0;
+
+    // Reversed sequence: bit i of Mr is bit N-1-i of M.
+    Mask Mr;
+    {
+        const uint64_t lo = ballot(lane < N && m_bit(M, N - 1 - lane));
+        uint64_t hi = 0ull;
+        if constexpr (NW == 2) hi = ballot(lane + 64 < N && m_bit(M, N - 65 - lane));
+        Mr = make_mask<NW>(lo, hi);
+    }
+
+    // C_k for the lags this lane owns (Eq. 1) and the energy (Eq. 2).
+    int C[NW];
+    int sq = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const int k = lane + 1 + 64 * w;
+        C[w] = k < N ? lag_corr(M, N, k) : 0;
+        sq += C[w] * C[w];
+    }
+    int E = wave_sum(sq);
+
+    int tabu[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) tabu[w] = 0;
+    Mask best = M;
+    int bestE = E;
+
+    if (lane == 0) ps[0] = 0;
+    Mask P[8];
+    int q = build_planes<NW>(C, P);
+    uint32_t dr0 = 0u, dr1 = 0u;
+
+    for (int t = 1; t <= sch.T; ++t) {
+        const int slot = (t - 1) & 63;
+        if (slot == 0) {
+            // draws for steps t .. t+63, one step per lane
+            const Draw4 d = philox10(entity, gen, (uint32_t)(t + lane), kTagStep, k0, k1);
+            dr0 = d.w0;
+            dr1 = d.w1;
+        }
+
+        // Prefix sums PS(x) = sum_{k<=x} C_k, x = 0..N-1, into LDS.
+        wave_sync();
+        {
+            const int s0 = wave_scan(C[0]);
+            ps[1 + lane] = s0;
+            if constexpr (NW == 2) {
+                const int s1 = wave_scan(C[1]) + readlane(s0, 63);
+                ps[65 + lane] = s1;
+            }
+        }
+        wave_sync();
+
+        // Score the neighbours this lane owns.
+        int key[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int j = lane + 64 * w;
+            key[w] = INT_MAX;
+            if (j < N) {
+                const Mask R = m_shr(M, j + 1);   // bit k-1: s_{j+k} = -1
+                const Mask L = m_shr(Mr, N - j);  // bit k-1: s_{j-k} = -1
+                int bs = 0;                       // sum_k (bR_k + bL_k) C_k
+#pragma unroll
+                for (int p = 0; p < 8; ++p) {
+                    if (p < q) {
+                        const int cnt = m_popc(m_and(R, P[p])) + m_popc(m_and(L, P[p]));
+                        bs += (p == q - 1) ? -(cnt << p) : (cnt << p);
+                    }
+                }
+                const int nb = min(N - 1 - j, j);
+                const int u = nb - 2 * m_popc(m_and(m_xor(R, L), m_low(M, nb)));
+                const int v = ps[N - 1 - j] + ps[j] - 2 * bs;
+                const int sj = 1 - 2 * m_bit(M, j);
+                const int cand = E + 4 * (N - 1 + 2 * u - sj * v);
+                const bool admissible = tabu[w] < t || (aspiration && cand < bestE);
+                if (admissible) key[w] = cand;
+            }
+        }
+
+        // Admissible minimum, ties broken by the step's draw.
+        int kmin = key[0];
+        if constexpr (NW == 2) kmin = min(kmin, key[1]);
+        const int m = wave_min(kmin);
+        const uint64_t T0 = ballot(key[0] == m);
+        uint64_t T1 = 0ull;
+        if constexpr (NW == 2) T1 = ballot(key[1] == m);
+        const int c0 = __popcll(T0);
+        const int c = c0 + __popcll(T1);
+        const uint32_t u0 = readlane_u(dr0, slot);
+        const uint32_t u1 = readlane_u(dr1, slot);
+        int r = (int)below(u0, (uint32_t)c);
+        int pick;
+        if (r < c0) {
+            const uint64_t sel = ballot(((T0 >> lane) & 1ull) && rank_below(T0) == r);
+            pick = __builtin_ctzll(sel);
+        } else {
+            r -= c0;
+            const uint64_t sel = ballot(((T1 >> lane) & 1ull) && rank_below(T1) == r);
+            pick = 64 + __builtin_ctzll(sel);
+        }
+
+        // Apply the move: tenure, sequence, energy, best.
+        const int tenure = sch.lo + (int)below(u1, (uint32_t)(sch.hi - sch.lo + 1));
+        if (pick == lane) tabu[0] = t + tenure;
+        if constexpr (NW == 2) {
+            if (pick == lane + 64) tabu[1] = t + tenure;
+        }
+        const int sm = 1 - 2 * m_bit(M, pick);
+        M = m_xor(M, m_onebit(M, pick));
+        Mr = m_xor(Mr, m_onebit(Mr, N - 1 - pick));
+        E = m;
+        if (E < bestE) {
+            bestE = E;
+            best = M;
+        }
+        if (trace != nullptr && lane == 0) trace[t - 1] = (int16_t)pick;
+
+        // C_k -= 2 s_pick t_pick,k for every lag (lane-parallel).
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int k = lane + 1 + 64 * w;
+            if (k < N) {
+                const int a = pick + k, b = pick - k;
+                const int sa = a < N ? 1 - 2 * m_bit(M, a) : 0;
+                const int sb = b >= 0 ? 1 - 2 * m_bit(M, b) : 0;
+                C[w] -= 2 * sm * (sa + sb);
+            }
+        }
+        q = build_planes<NW>(C, P);
+    }
+
+    WalkResult<NW> res;
+    res.best = best;
+    res.best_e = bestE;
+    res.final_e = E;
+    return res;
+}
+
+}  // namespace liblabs

@@ -1,0 +1,82 @@
+// Host-side state of a liblabs handle and helpers shared by the C ABI
+// translation units.  Internal; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <string>
+#include <vector>
+
+#include "../../include/liblabs.h"
+#include "labs_internal.h"
+
+namespace liblabs {
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t size = 0;
+    int reserve(labs_handle *h, size_t bytes);
+    void release();
+};
+
+struct PinBuf {
+    void *ptr = nullptr;
+    size_t size = 0;
+    int reserve(labs_handle *h, size_t bytes);
+    void release();
+};
+
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+  private:
+    int prev_ = -1;
+};
+
+}  // namespace liblabs
+
+struct labs_handle {
+    int device = 0;
+    int num_cus = 0;
+    std::string arch;
+    std::string last_error;
+    hipStream_t stream = nullptr;      // internal stream (default priority)
+    hipEvent_t ws_event = nullptr;     // completion of the last workspace user
+    bool ws_event_valid = false;
+    liblabs::DevBuf ws;                   // tabu workspace: queue head, ns, order
+    liblabs::DevBuf mem;                  // memetic state and slot table
+    liblabs::PinBuf pin;                  // pinned staging
+    bool has_override = false;
+    labs_launch override_launch{1, 0, 0};
+    std::vector<labs_launch> tuned;    // per length bucket of 16
+};
+
+namespace liblabs {
+
+int fail(labs_handle *h, int code, const char *fmt, ...);
+int hip_fail(labs_handle *h, hipError_t e, const char *where);
+int ws_acquire(labs_handle *h, hipStream_t s);
+int ws_release(labs_handle *h, hipStream_t s);
+int check_rule(labs_handle *h, const RuleParams &r, int n);
+long long max_steps(const RuleParams &r, int n);
+RuleParams to_rule(const labs_tabu_params &p);
+labs_launch choose_launch(labs_handle *h, int n_max, bool uneven);
+int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *starts,
+                    int32_t start_stride, const int32_t *ns_host, int32_t n_uniform, int64_t W,
+                    uint64_t seed, int8_t *best_seq, int32_t out_stride, int32_t *best_e,
+                    int32_t *final_e, int16_t *trace, int32_t trace_stride, hipStream_t s,
+                    const labs_launch *force);
+int check_memetic(labs_handle *h, const labs_memetic_params *p);
+
+// Bytes of device state per memetic replica with population size K.
+inline size_t memetic_state_bytes(int K) {
+    return (size_t)K * (2 * sizeof(uint64_t) + sizeof(int32_t)) + 2 * sizeof(uint64_t) +
+           sizeof(int32_t) + 2 * sizeof(int64_t);
+}
+
+// Carve a MemeticStateDev for S replicas out of `base` (256-byte aligned parts).
+MemeticStateDev carve_state(void *base, int S, int K, size_t *bytes_out);
+
+}  // namespace liblabs

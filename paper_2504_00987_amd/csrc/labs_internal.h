@@ -1,0 +1,82 @@
+// Internal interface between the C ABI (labs_api.cpp, labs_server.cpp) and
+// the kernels (labs_kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace liblabs {
+
+struct RuleParams {
+    int32_t steps_rule, steps_a, tenure_rule;
+    int32_t lo_num, lo_den, lo_add, hi_num, hi_den, hi_add;
+    int32_t aspiration;
+};
+
+struct TabuLaunchArgs {
+    const int8_t *starts;     // [W][start_stride] or null
+    int32_t start_stride;
+    const int32_t *ns;        // device [W] or null
+    int32_t n_uniform;
+    int32_t n_max;            // longest walk in the batch
+    const int32_t *order;     // device [W] walk ids in processing order, or null
+    int64_t W;
+    uint32_t k0, k1;
+    RuleParams rule;
+    int8_t *best_seq;
+    int32_t out_stride;
+    int32_t *best_e;
+    int32_t *final_e;
+    int16_t *trace;
+    int32_t trace_stride;
+    uint32_t *counter;        // persistent queue head (device), zeroed by the launcher
+};
+
+// Device layout of a memetic replica's state (structure of arrays).
+struct MemeticStateDev {
+    uint64_t *pop;    // [S][K][2] member masks (bit i: s_i = -1)
+    int32_t *popE;    // [S][K]
+    uint64_t *best;   // [S][2]
+    int32_t *bestE;   // [S]
+    int64_t *gen;     // [S] generations done
+    int64_t *hit;     // [S] hit generation or -1
+};
+
+struct MemeticSlot {
+    int32_t n;
+    uint32_t pop_id;
+    uint32_t k0, k1;
+    int64_t gen_limit;
+    int32_t target;
+    int32_t state;    // index into MemeticStateDev arrays; < 0 means idle
+};
+
+struct MemeticLaunchArgs {
+    const MemeticSlot *slots;
+    int32_t n_slots;
+    int32_t K;
+    uint32_t p_comb;
+    int32_t mut_rule;
+    uint32_t p_mut;
+    RuleParams rule;
+    int32_t gens;            // generations per launch
+    MemeticStateDev st;
+    uint32_t *any_hit;       // set to 1 when a replica reaches its target
+};
+
+hipError_t launch_energy(const int8_t *seqs, const int32_t *ns, int32_t n_uniform,
+                         int32_t stride, int64_t count, int32_t *out, hipStream_t s);
+
+// waves_per_group in {1,2,4}; persistent grid = groups (0: one wave per walk).
+hipError_t launch_tabu(const TabuLaunchArgs &a, int waves_per_group, int groups,
+                       hipStream_t s);
+
+hipError_t launch_memetic_init(const MemeticLaunchArgs &a, hipStream_t s);
+hipError_t launch_memetic_advance(const MemeticLaunchArgs &a, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
+hipError_t launch_gather_best(const MemeticStateDev &st, const int32_t *state_idx,
+                              const int32_t *ns, int32_t n_uniform, int32_t count,
+                              int8_t *best_seq, int32_t out_stride, int32_t *best_e,
+                              int64_t *hit_gen, int64_t *gens_done, hipStream_t s);
+
+}  // namespace liblabs

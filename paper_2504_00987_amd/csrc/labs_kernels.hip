@@ -1,0 +1,383 @@
+// Kernels of liblabs for gfx950 and their launchers.
+//
+//   energy_kernel          Eq. (2) for a batch of +-1 rows, one row per wave
+//   tabu_kernel            independent tabu walks (Alg. 2 / Alg. 4), one walk
+//                          per wave, either one wave per walk or a persistent
+//                          grid draining a longest-first work queue
+//   memetic_init_kernel    random populations (Alg. 1, first two lines)
+//   memetic_advance_kernel memetic generations (Alg. 1 / Alg. 3), one replica
+//                          per wave, population resident in LDS
+#include "labs_device.hpp"
+#include "labs_internal.h"
+
+namespace liblabs {
+
+namespace {
+
+constexpr int kPsInts = 132;  // prefix-sum scratch per wave (needs 129)
+constexpr int kMaxK = 128;
+
+// ---------------------------------------------------------------------------
+// Energies.
+// ---------------------------------------------------------------------------
+template <int WPG>
+__global__ __launch_bounds__(64 * WPG) void energy_kernel(const int8_t *__restrict__ seqs,
+                                                          const int32_t *__restrict__ ns,
+                                                          int32_t n_uniform, int32_t stride,
+                                                          int64_t count,
+                                                          int32_t *__restrict__ out) {
+    const int lane = lane_id();
+    const int64_t b = (int64_t)blockIdx.x * WPG + (threadIdx.x >> 6);
+    if (b >= count) return;
+    const int N = ns ? ns[b] : n_uniform;
+    const int8_t *row = seqs + b * (int64_t)stride;
+    bool b0 = false, b1 = false;
+    if (lane < N) b0 = row[lane] < 0;
+    if (lane + 64 < N) b1 = row[lane + 64] < 0;
+    const M128 M{ballot(b0), ballot(b1)};
+    int acc = 0;
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+        const int k = lane + 1 + 64 * w;
+        if (k < N) {
+            const int c = lag_corr(M, N, k);
+            acc += c * c;
+        }
+    }
+    const int E = wave_sum(acc);
+    if (lane == 0) out[b] = E;
+}
+
+// ---------------------------------------------------------------------------
+// Batched tabu walks.
+// ---------------------------------------------------------------------------
+template <int NW>
+__device__ void run_tabu_item(const TabuLaunchArgs &a, int64_t w, int N, int *ps) {
+    using Mask = typename MaskOf<NW>::type;
+    const int lane = lane_id();
+    uint64_t lo, hi;
+    if (a.starts != nullptr) {
+        const int8_t *row = a.starts + w * (int64_t)a.start_stride;
+        bool b0 = false, b1 = false;
+        if (lane < N) b0 = row[lane] < 0;
+        if (lane + 64 < N) b1 = row[lane + 64] < 0;
+        lo = ballot(b0);
+        hi = ballot(b1);
+    } else {
+        const Draw4 d = philox10((uint32_t)w, 0u, 0u, kTagStart, a.k0, a.k1);
+        lo = (uint64_t)d.w0 | ((uint64_t)d.w1 << 32);
+        hi = (uint64_t)d.w2 | ((uint64_t)d.w3 << 32);
+        if (N < 64) {
+            lo &= (1ull << N) - 1ull;
+            hi = 0ull;
+        } else {
+            hi &= (N >= 128) ? ~0ull : ((1ull << (N - 64)) - 1ull);
+        }
+    }
+    const Mask M = make_mask<NW>(lo, hi);
+    const Schedule sch = make_schedule(a.rule, N, a.k0, a.k1, (uint32_t)w, 0u);
+    int16_t *tr = a.trace ? a.trace + w * (int64_t)a.trace_stride : nullptr;
+    const WalkResult<NW> r = tabu_walk<NW>(N, M, sch, a.rule.aspiration, a.k0, a.k1,
+                                           (uint32_t)w, 0u, ps, tr);
+    int8_t *out = a.best_seq + w * (int64_t)a.out_stride;
+    for (int i = lane; i < a.out_stride; i += 64)
+        out[i] = i < N ? (m_bit(r.best, i) ? (int8_t)-1 : (int8_t)1) : (int8_t)0;
+    if (lane == 0) {
+        a.best_e[w] = r.best_e;
+        a.final_e[w] = r.final_e;
+    }
+}
+
+__device__ __forceinline__ void run_tabu_index(const TabuLaunchArgs &a, int64_t idx, int *ps) {
+    const int64_t w = a.order ? (int64_t)a.order[idx] : idx;
+    const int N = a.ns ? a.ns[w] : a.n_uniform;
+    if (N <= 64)
+        run_tabu_item<1>(a, w, N, ps);
+    else
+        run_tabu_item<2>(a, w, N, ps);
+}
+
+template <int WPG>
+__global__ __launch_bounds__(64 * WPG) void tabu_kernel(TabuLaunchArgs a, int persistent) {
+    __shared__ int ps_all[WPG][kPsInts];
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    int *ps = ps_all[wave];
+    if (persistent) {
+        // Each wave takes walks from the queue until it is empty; the queue
+        // head only grows, so every wave leaves after at most W + 1 takes.
+        for (;;) {
+            uint32_t idx = 0u;
+            if (lane == 0) idx = atomicAdd(a.counter, 1u);
+            idx = readlane_u(idx, 0);
+            if ((int64_t)idx >= a.W) break;
+            run_tabu_index(a, (int64_t)idx, ps);
+        }
+    } else {
+        const int64_t idx = (int64_t)blockIdx.x * WPG + wave;
+        if (idx < a.W) run_tabu_index(a, idx, ps);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Memetic replicas.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t word_of(const Draw4 &d, int i) {
+    return i == 0 ? d.w0 : (i == 1 ? d.w1 : (i == 2 ? d.w2 : d.w3));
+}
+
+__global__ __launch_bounds__(64) void memetic_init_kernel(MemeticLaunchArgs a) {
+    const int s = blockIdx.x;
+    if (s >= a.n_slots) return;
+    const MemeticSlot sl = a.slots[s];
+    if (sl.state < 0) return;
+    const int lane = lane_id();
+    const int N = sl.n, K = a.K;
+    const int64_t base = (int64_t)sl.state * K;
+    uint64_t lo[2] = {0ull, 0ull}, hi[2] = {0ull, 0ull};
+    int e[2] = {INT_MAX, INT_MAX};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int m = lane + 64 * h;
+        if (m < K) {
+            const Draw4 d = philox10(sl.pop_id, (uint32_t)m, 0u, kTagInit, sl.k0, sl.k1);
+            uint64_t l = (uint64_t)d.w0 | ((uint64_t)d.w1 << 32);
+            uint64_t u = (uint64_t)d.w2 | ((uint64_t)d.w3 << 32);
+            if (N < 64) {
+                l &= (1ull << N) - 1ull;
+                u = 0ull;
+            } else {
+                u &= (N >= 128) ? ~0ull : ((1ull << (N - 64)) - 1ull);
+            }
+            lo[h] = l;
+            hi[h] = u;
+            e[h] = N <= 64 ? lane_energy<uint64_t>(l, N) : lane_energy<M128>(M128{l, u}, N);
+            a.st.pop[(base + m) * 2 + 0] = l;
+            a.st.pop[(base + m) * 2 + 1] = u;
+            a.st.popE[base + m] = e[h];
+        }
+    }
+    // bestSeq: the lowest-index member of minimum energy.
+    const int mn = wave_min(min(e[0], e[1]));
+    const uint64_t t0 = ballot(e[0] == mn), t1 = ballot(e[1] == mn);
+    const int h = t0 ? 0 : 1;
+    const int src = t0 ? __builtin_ctzll(t0) : __builtin_ctzll(t1);
+    const uint64_t sel_lo = h == 0 ? lo[0] : lo[1];
+    const uint64_t sel_hi = h == 0 ? hi[0] : hi[1];
+    const uint64_t blo = ((uint64_t)readlane_u((uint32_t)(sel_lo >> 32), src) << 32) |
+                         readlane_u((uint32_t)sel_lo, src);
+    const uint64_t bhi = ((uint64_t)readlane_u((uint32_t)(sel_hi >> 32), src) << 32) |
+                         readlane_u((uint32_t)sel_hi, src);
+    if (lane == 0) {
+        a.st.best[(int64_t)sl.state * 2 + 0] = blo;
+        a.st.best[(int64_t)sl.state * 2 + 1] = bhi;
+        a.st.bestE[sl.state] = mn;
+        a.st.gen[sl.state] = 0;
+        a.st.hit[sl.state] = -1;
+    }
+}
+
+template <int NW>
+__device__ void memetic_replica(const MemeticLaunchArgs &a, const MemeticSlot &sl,
+                                uint64_t (*pop)[2], int *popE, int *ps) {
+    using Mask = typename MaskOf<NW>::type;
+    const int lane = lane_id();
+    const int N = sl.n, K = a.K, st = sl.state;
+    const int64_t base = (int64_t)st * K;
+    for (int i = lane; i < K; i += 64) {
+        pop[i][0] = a.st.pop[(base + i) * 2 + 0];
+        pop[i][1] = a.st.pop[(base + i) * 2 + 1];
+        popE[i] = a.st.popE[base + i];
+    }
+    wave_sync();
+    Mask best = make_mask<NW>(a.st.best[(int64_t)st * 2 + 0], a.st.best[(int64_t)st * 2 + 1]);
+    int bestE = a.st.bestE[st];
+    int64_t g = a.st.gen[st];
+    int64_t hit = a.st.hit[st];
+    const uint32_t thr = a.mut_rule == 0 ? (uint32_t)(0x100000000ull / (uint64_t)N) : a.p_mut;
+    const bool targeted = sl.target >= 0;
+
+    for (int it = 0; it < a.gens; ++it) {
+        if (g >= sl.gen_limit) break;
+        if (targeted && bestE <= sl.target) {
+            if (hit < 0) hit = g;
+            break;
+        }
+        const uint32_t gg = (uint32_t)g;
+        const Draw4 da = philox10(sl.pop_id, gg, 0u, kTagGen, sl.k0, sl.k1);
+        const Draw4 db = philox10(sl.pop_id, gg, 1u, kTagGen, sl.k0, sl.k1);
+        Mask child;
+        if (da.w0 < a.p_comb) {
+            // selectParents: two binary tournaments; Combine: one-point crossover
+            int i = (int)below(da.w1, (uint32_t)K), j = (int)below(da.w2, (uint32_t)K);
+            const int pa = popE[i] <= popE[j] ? i : j;
+            i = (int)below(da.w3, (uint32_t)K);
+            j = (int)below(db.w0, (uint32_t)K);
+            const int pb = popE[i] <= popE[j] ? i : j;
+            const int cut = 1 + (int)below(db.w1, (uint32_t)(N - 1));
+            const Mask A = make_mask<NW>(pop[pa][0], pop[pa][1]);
+            const Mask B = make_mask<NW>(pop[pb][0], pop[pb][1]);
+            const Mask lowm = m_low(A, cut);
+            child = m_or(m_and(A, lowm), m_and(B, m_not(lowm)));
+        } else {
+            const int c = (int)below(da.w1, (uint32_t)K);
+            child = make_mask<NW>(pop[c][0], pop[c][1]);
+        }
+        // Mutate: bit i flips when word i%4 of draw (pop, g, i/4, MUT) < thr.
+        uint64_t flo, fhi = 0ull;
+        {
+            const int i0 = lane;
+            const Draw4 d = philox10(sl.pop_id, gg, (uint32_t)(i0 >> 2), kTagMut, sl.k0, sl.k1);
+            flo = ballot(i0 < N && word_of(d, i0 & 3) < thr);
+            if constexpr (NW == 2) {
+                const int i1 = lane + 64;
+                const Draw4 d1 = philox10(sl.pop_id, gg, (uint32_t)(i1 >> 2), kTagMut, sl.k0, sl.k1);
+                fhi = ballot(i1 < N && word_of(d1, i1 & 3) < thr);
+            }
+        }
+        child = m_xor(child, make_mask<NW>(flo, fhi));
+        const Schedule sch = make_schedule(a.rule, N, sl.k0, sl.k1, sl.pop_id, gg);
+        const WalkResult<NW> r = tabu_walk<NW>(N, child, sch, a.rule.aspiration, sl.k0, sl.k1,
+                                               sl.pop_id, gg, ps, nullptr);
+        if (r.best_e < bestE) {
+            bestE = r.best_e;
+            best = r.best;
+        }
+        const int rep = (int)below(db.w2, (uint32_t)K);
+        wave_sync();
+        if (lane == 0) {
+            pop[rep][0] = mask_lo(r.best);
+            pop[rep][1] = mask_hi(r.best);
+            popE[rep] = r.best_e;
+        }
+        wave_sync();
+        ++g;
+        if (targeted && bestE <= sl.target) {
+            if (hit < 0) hit = g;
+            break;
+        }
+    }
+
+    for (int i = lane; i < K; i += 64) {
+        a.st.pop[(base + i) * 2 + 0] = pop[i][0];
+        a.st.pop[(base + i) * 2 + 1] = pop[i][1];
+        a.st.popE[base + i] = popE[i];
+    }
+    if (lane == 0) {
+        a.st.best[(int64_t)st * 2 + 0] = mask_lo(best);
+        a.st.best[(int64_t)st * 2 + 1] = mask_hi(best);
+        a.st.bestE[st] = bestE;
+        a.st.gen[st] = g;
+        a.st.hit[st] = hit;
+        if (hit >= 0 && a.any_hit != nullptr) atomicOr(a.any_hit, 1u);
+    }
+}
+
+__global__ __launch_bounds__(64) void memetic_advance_kernel(MemeticLaunchArgs a) {
+    __shared__ uint64_t pop[kMaxK][2];
+    __shared__ int popE[kMaxK];
+    __shared__ int ps[kPsInts];
+    const int s = blockIdx.x;
+    if (s >= a.n_slots) return;
+    const MemeticSlot sl = a.slots[s];
+    if (sl.state < 0) return;
+    if (sl.n <= 64)
+        memetic_replica<1>(a, sl, pop, popE, ps);
+    else
+        memetic_replica<2>(a, sl, pop, popE, ps);
+}
+
+__global__ void gather_best_kernel(MemeticStateDev st, const int32_t *__restrict__ state_idx,
+                                   const int32_t *__restrict__ ns, int32_t n_uniform,
+                                   int32_t count, int8_t *__restrict__ best_seq,
+                                   int32_t out_stride, int32_t *__restrict__ best_e,
+                                   int64_t *__restrict__ hit_gen,
+                                   int64_t *__restrict__ gens_done) {
+    const int i = blockIdx.x;
+    if (i >= count) return;
+    const int lane = lane_id();
+    const int s = state_idx ? state_idx[i] : i;
+    const int N = ns ? ns[i] : n_uniform;
+    const M128 b{st.best[(int64_t)s * 2 + 0], st.best[(int64_t)s * 2 + 1]};
+    int8_t *out = best_seq + (int64_t)i * out_stride;
+    for (int k = lane; k < out_stride; k += 64)
+        out[k] = k < N ? (m_bit(b, k) ? (int8_t)-1 : (int8_t)1) : (int8_t)0;
+    if (lane == 0) {
+        best_e[i] = st.bestE[s];
+        if (hit_gen) hit_gen[i] = st.hit[s];
+        if (gens_done) gens_done[i] = st.gen[s];
+    }
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_energy(const int8_t *seqs, const int32_t *ns, int32_t n_uniform,
+                         int32_t stride, int64_t count, int32_t *out, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    constexpr int WPG = 4;
+    const int64_t grid = (count + WPG - 1) / WPG;
+    hipLaunchKernelGGL(energy_kernel<WPG>, dim3((unsigned)grid), dim3(64 * WPG), 0, s, seqs, ns,
+                       n_uniform, stride, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_tabu(const TabuLaunchArgs &a, int waves_per_group, int groups,
+                       hipStream_t s) {
+    if (a.W <= 0) return hipSuccess;
+    const int persistent = groups > 0 ? 1 : 0;
+    if (persistent) {
+        hipError_t e = launch_fill_u32(a.counter, 0u, 1, s);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t grid = persistent ? groups : (a.W + waves_per_group - 1) / waves_per_group;
+    switch (waves_per_group) {
+    case 1:
+        hipLaunchKernelGGL(tabu_kernel<1>, dim3((unsigned)grid), dim3(64), 0, s, a, persistent);
+        break;
+    case 2:
+        hipLaunchKernelGGL(tabu_kernel<2>, dim3((unsigned)grid), dim3(128), 0, s, a, persistent);
+        break;
+    case 4:
+        hipLaunchKernelGGL(tabu_kernel<4>, dim3((unsigned)grid), dim3(256), 0, s, a, persistent);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_memetic_init(const MemeticLaunchArgs &a, hipStream_t s) {
+    if (a.n_slots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(memetic_init_kernel, dim3((unsigned)a.n_slots), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_memetic_advance(const MemeticLaunchArgs &a, hipStream_t s) {
+    if (a.n_slots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(memetic_advance_kernel, dim3((unsigned)a.n_slots), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int64_t grid = (count + 255) / 256;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)grid), dim3(256), 0, s, p, v, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_best(const MemeticStateDev &st, const int32_t *state_idx,
+                              const int32_t *ns, int32_t n_uniform, int32_t count,
+                              int8_t *best_seq, int32_t out_stride, int32_t *best_e,
+                              int64_t *hit_gen, int64_t *gens_done, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_best_kernel, dim3((unsigned)count), dim3(64), 0, s, st, state_idx,
+                       ns, n_uniform, count, best_seq, out_stride, best_e, hit_gen, gens_done);
+    return hipGetLastError();
+}
+
+}  // namespace liblabs

@@ -1,0 +1,206 @@
+// labs_memetic_run: memetic replicas (Alg. 1 / Alg. 3) driven one generation
+// per launch (PLAIN), as a replayed graph of one-generation launches (GRAPH),
+// or `chunk` generations per launch with the population resident in LDS
+// (PERSISTENT).  All three give identical results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "labs_handle.h"
+
+namespace liblabs {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+MemeticStateDev carve_state(void *base, int S, int K, size_t *bytes_out) {
+    MemeticStateDev st;
+    char *p = (char *)base;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *q = p ? p + off : nullptr;
+        off += align256(bytes);
+        return q;
+    };
+    st.pop = (uint64_t *)take((size_t)S * K * 2 * sizeof(uint64_t));
+    st.popE = (int32_t *)take((size_t)S * K * sizeof(int32_t));
+    st.best = (uint64_t *)take((size_t)S * 2 * sizeof(uint64_t));
+    st.bestE = (int32_t *)take((size_t)S * sizeof(int32_t));
+    st.gen = (int64_t *)take((size_t)S * sizeof(int64_t));
+    st.hit = (int64_t *)take((size_t)S * sizeof(int64_t));
+    if (bytes_out) *bytes_out = off;
+    return st;
+}
+
+int check_memetic(labs_handle *h, const labs_memetic_params *p) {
+    if (!p) return fail(h, LABS_E_INVAL, "null memetic params");
+    if (p->K < 2 || p->K > LABS_MAX_K) return fail(h, LABS_E_INVAL, "K=%d out of [2, %d]", p->K, LABS_MAX_K);
+    if (p->mut_rule != LABS_MUT_INV_N && p->mut_rule != LABS_MUT_FIXED)
+        return fail(h, LABS_E_INVAL, "unknown mut_rule %d", p->mut_rule);
+    if (p->generations < 0) return fail(h, LABS_E_INVAL, "generations < 0");
+    if (p->generations > 0xffffffffLL) return fail(h, LABS_E_INVAL, "generations >= 2^32");
+    if (p->mode < LABS_MODE_PLAIN || p->mode > LABS_MODE_PERSISTENT)
+        return fail(h, LABS_E_INVAL, "unknown mode %d", p->mode);
+    if (p->chunk < 1 || p->chunk > (1 << 20)) return fail(h, LABS_E_INVAL, "chunk out of [1, 2^20]");
+    if (p->stop_all != 0 && p->stop_all != 1) return fail(h, LABS_E_INVAL, "stop_all must be 0 or 1");
+    return LABS_OK;
+}
+
+}  // namespace liblabs
+
+using namespace liblabs;
+
+extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
+                                const int32_t *ns_host, int32_t n_uniform, int32_t pops,
+                                uint64_t seed, int8_t *best_seq, int32_t out_stride,
+                                int32_t *best_e, int64_t *hit_gen, int64_t *gens_done,
+                                void *stream) {
+    if (!h) return LABS_E_INVAL;
+    h->last_error.clear();
+    int rc = check_memetic(h, p);
+    if (rc) return rc;
+    if (pops < 0) return fail(h, LABS_E_INVAL, "pops < 0");
+    if (pops == 0) return LABS_OK;
+    if (!best_seq || !best_e) return fail(h, LABS_E_INVAL, "null output");
+    const RuleParams rule = to_rule(p->tabu);
+    int n_max = 0;
+    std::vector<char> seen(LABS_MAX_N + 1, 0);
+    for (int i = 0; i < pops; ++i) {
+        const int n = ns_host ? ns_host[i] : n_uniform;
+        if (n < LABS_MIN_N || n > LABS_MAX_N)
+            return fail(h, LABS_E_INVAL, "N=%d out of [%d, %d]", n, LABS_MIN_N, LABS_MAX_N);
+        if (!seen[n]) {
+            seen[n] = 1;
+            if ((rc = check_rule(h, rule, n))) return rc;
+        }
+        n_max = std::max(n_max, n);
+    }
+    if (out_stride < n_max) return fail(h, LABS_E_INVAL, "out_stride=%d < N=%d", out_stride, n_max);
+
+    DeviceGuard g(h->device);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize(caller stream)");
+    hipStream_t s = h->stream;
+
+    // Device memory: [slots][ns][any_hit][state]
+    size_t state_bytes = 0;
+    carve_state(nullptr, pops, p->K, &state_bytes);
+    const size_t slots_bytes = (size_t)pops * sizeof(MemeticSlot);
+    const size_t off_ns = (slots_bytes + 255) & ~(size_t)255;
+    const size_t off_flag = off_ns + (((size_t)pops * 4 + 255) & ~(size_t)255);
+    const size_t off_state = off_flag + 256;
+    if ((rc = h->mem.reserve(h, off_state + state_bytes))) return rc;
+    char *base = (char *)h->mem.ptr;
+    MemeticSlot *d_slots = (MemeticSlot *)base;
+    int32_t *d_ns = (int32_t *)(base + off_ns);
+    uint32_t *d_flag = (uint32_t *)(base + off_flag);
+    MemeticStateDev st = carve_state(base + off_state, pops, p->K, nullptr);
+
+    const size_t stage = off_flag;  // slots + ns
+    if ((rc = h->pin.reserve(h, stage))) return rc;
+    if (h->ws_event_valid) hipEventSynchronize(h->ws_event);
+    std::memset(h->pin.ptr, 0, stage);
+    MemeticSlot *hs = (MemeticSlot *)h->pin.ptr;
+    int32_t *hn = (int32_t *)((char *)h->pin.ptr + off_ns);
+    const int target = p->target_e;
+    for (int i = 0; i < pops; ++i) {
+        const int n = ns_host ? ns_host[i] : n_uniform;
+        hs[i].n = n;
+        hs[i].pop_id = (uint32_t)i;
+        hs[i].k0 = (uint32_t)(seed & 0xffffffffu);
+        hs[i].k1 = (uint32_t)(seed >> 32);
+        hs[i].gen_limit = p->generations;
+        hs[i].target = target < 0 ? -1 : target;
+        hs[i].state = i;
+        hn[i] = n;
+    }
+    e = hipMemcpyAsync(base, h->pin.ptr, stage, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(h, e, "hipMemcpyAsync(slots)");
+    if ((rc = ws_release(h, s))) return rc;  // the staging copy is in flight
+
+    MemeticLaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.slots = d_slots;
+    a.n_slots = pops;
+    a.K = p->K;
+    a.p_comb = p->p_comb;
+    a.mut_rule = p->mut_rule;
+    a.p_mut = p->p_mut;
+    a.rule = rule;
+    a.st = st;
+    a.any_hit = d_flag;
+    if ((e = launch_fill_u32(d_flag, 0u, 1, s)) != hipSuccess) return hip_fail(h, e, "fill");
+    if ((e = launch_memetic_init(a, s)) != hipSuccess) return hip_fail(h, e, "memetic init");
+
+    const bool poll = p->stop_all && target >= 0;
+    const int64_t G = p->generations;
+    const int64_t chunk = p->chunk;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    if (p->mode == LABS_MODE_GRAPH && G > 0) {
+        // Capture `chunk` one-generation launches once; replay them.
+        MemeticLaunchArgs one = a;
+        one.gens = 1;
+        const int64_t n_launch = std::min<int64_t>(chunk, G);
+        e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(h, e, "hipStreamBeginCapture");
+        for (int64_t i = 0; i < n_launch && e == hipSuccess; ++i) e = launch_memetic_advance(one, s);
+        hipError_t e2 = hipStreamEndCapture(s, &graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            return hip_fail(h, e != hipSuccess ? e : e2, "graph capture");
+        }
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(graph);
+            return hip_fail(h, e, "hipGraphInstantiate");
+        }
+    }
+
+    rc = LABS_OK;
+    for (int64_t done = 0; done < G;) {
+        const int64_t step = std::min(chunk, G - done);
+        if (p->mode == LABS_MODE_PLAIN) {
+            MemeticLaunchArgs one = a;
+            one.gens = 1;
+            for (int64_t i = 0; i < step && e == hipSuccess; ++i) e = launch_memetic_advance(one, s);
+        } else if (p->mode == LABS_MODE_GRAPH) {
+            // Launches beyond a replica's generation limit return at once, so
+            // the final replay may safely run past G.
+            e = hipGraphLaunch(exec, s);
+        } else {
+            MemeticLaunchArgs many = a;
+            many.gens = (int32_t)step;
+            e = launch_memetic_advance(many, s);
+        }
+        if (e != hipSuccess) {
+            rc = hip_fail(h, e, "memetic advance");
+            break;
+        }
+        done += p->mode == LABS_MODE_GRAPH ? std::min<int64_t>(chunk, G) : step;
+        if (poll && done < G) {
+            uint32_t flag = 0;
+            e = hipMemcpyAsync(&flag, d_flag, sizeof(flag), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) {
+                rc = hip_fail(h, e, "flag poll");
+                break;
+            }
+            if (flag) {
+                // Global termination: every replica stops here.  The stop is
+                // at a chunk boundary, so the outcome is deterministic.
+                break;
+            }
+        }
+    }
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    if (rc) return rc;
+    e = launch_gather_best(st, nullptr, d_ns, 0, pops, best_seq, out_stride, best_e, hit_gen,
+                           gens_done, s);
+    if (e != hipSuccess) return hip_fail(h, e, "gather");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+    return LABS_OK;
+}

@@ -1,0 +1,310 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+All results are integers decided by integer arithmetic and the shared RNG
+contract, so the bar is bit-exact equality of energies, best sequences,
+final energies and per-step flip traces.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2504_00987_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lb():
+    from paper_2504_00987_amd.labs import Labs
+    h = Labs(0)
+    yield h
+    h.close()
+
+
+def osched(r: I.Rules) -> O.Schedule:
+    return O.Schedule(r.steps_rule, r.steps_a, r.tenure_rule, r.lo_num, r.lo_den, r.lo_add,
+                      r.hi_num, r.hi_den, r.hi_add, r.aspiration)
+
+
+# ---------------------------------------------------------------------------
+# Eq. (2)
+# ---------------------------------------------------------------------------
+def test_energy_uniform_and_ragged(lb):
+    say("energy: uniform N=64 x 1000, ragged 3..128 x 777")
+    S = I.random_pm1(1000, 64, 64, seed=1)
+    got = lb.energy_batch(torch.from_numpy(S).cuda(), n_uniform=64).cpu().numpy()
+    assert np.array_equal(got, O.energy_batch(S, n_uniform=64))
+    ns = I.uneven_lengths(777, 3, 128, seed=2)
+    R = I.random_pm1_ragged(ns, 136, seed=3)
+    got = lb.energy_batch(torch.from_numpy(R).cuda(), ns=torch.from_numpy(ns).cuda()).cpu().numpy()
+    assert np.array_equal(got, O.energy_batch(R, ns=ns))
+
+
+def test_energy_closed_forms_and_edges(lb):
+    say("energy: all-ones/alternating, N = 3..128")
+    rows = []
+    ns = []
+    for n in range(3, 129):
+        for s in (np.ones(n), np.array([(-1) ** i for i in range(n)])):
+            r = np.zeros(128, dtype=np.int8)
+            r[:n] = s
+            rows.append(r)
+            ns.append(n)
+    R = np.stack(rows)
+    ns = np.array(ns, dtype=np.int32)
+    got = lb.energy_batch(torch.from_numpy(R).cuda(), ns=torch.from_numpy(ns).cuda()).cpu().numpy()
+    want = np.array([(n - 1) * n * (2 * n - 1) // 6 for n in ns])
+    assert np.array_equal(got, want)
+    empty = lb.energy_batch(torch.zeros((0, 64), dtype=torch.int8, device="cuda"), n_uniform=64)
+    assert empty.numel() == 0
+
+
+# ---------------------------------------------------------------------------
+# Alg. 2 / Alg. 4: batched walks
+# ---------------------------------------------------------------------------
+def _oracle_walks(W, n, rules, seed, starts=None, with_trace=True):
+    best = np.zeros((W, 128), dtype=np.int8)
+    be = np.zeros(W, dtype=np.int64)
+    fe = np.zeros(W, dtype=np.int64)
+    trs = []
+    sch = osched(rules)
+    for w in range(W):
+        nn = n[w] if hasattr(n, "__len__") else n
+        T, lo, hi = O.walk_schedule(nn, sch, seed, w, 0)
+        s = starts[w, :nn] if starts is not None else O.random_start(nn, seed, w)
+        b, e1, f1, tr, _ = O.tabu_walk(s, seed, w, 0, T, lo, hi, rules.aspiration, want_trace=with_trace)
+        best[w, :nn] = b
+        be[w], fe[w] = e1, f1
+        trs.append(tr)
+    return best, be, fe, trs
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 20, 31, 33, 63, 64, 65, 100, 127, 128])
+@pytest.mark.parametrize("asp", [1, 0])
+def test_tabu_small_trace(lb, n, asp):
+    say(f"tabu trace parity N={n} aspiration={asp}")
+    rules = I.Rules(I.STEPS_MULT_N, 2, I.TENURE_LINEAR, 1, 10, 0, 1, 5, 0, asp)
+    if rules.hi_num * n // rules.hi_den >= n:
+        rules = I.Rules(I.STEPS_MULT_N, 2, I.TENURE_LINEAR, 0, 1, 0, 0, 1, 1, asp)
+    W, seed = 24, 4242 + n
+    res = lb.tabu_batch(rules, W, seed, n_uniform=n, trace_stride=2 * n)
+    best, be, fe, trs = _oracle_walks(W, n, rules, seed)
+    assert np.array_equal(res.best_e.cpu().numpy(), be)
+    assert np.array_equal(res.final_e.cpu().numpy(), fe)
+    assert np.array_equal(res.best_seq.cpu().numpy(), best)
+    tr = res.trace.cpu().numpy()
+    for w in range(W):
+        assert np.array_equal(tr[w, : 2 * n], trs[w])
+
+
+def test_tabu_explicit_starts_paper_rules(lb):
+    say("tabu: explicit starts, paper walk length and tenure, ragged N")
+    ns = I.uneven_lengths(96, 3, 128, seed=11)
+    starts = I.random_pm1_ragged(ns, 128, seed=12)
+    rules = I.RULES_PAPER_LITERAL
+    res = lb.tabu_batch(rules, len(ns), 99, ns=ns, starts=torch.from_numpy(starts).cuda(),
+                        trace_stride=200)
+    best, be, fe, trs = _oracle_walks(len(ns), ns, rules, 99, starts=starts)
+    assert np.array_equal(res.best_e.cpu().numpy(), be)
+    assert np.array_equal(res.final_e.cpu().numpy(), fe)
+    assert np.array_equal(res.best_seq.cpu().numpy(), best)
+    tr = res.trace.cpu().numpy()
+    for w in range(len(ns)):
+        assert np.array_equal(tr[w, : len(trs[w])], trs[w])
+
+
+@pytest.mark.parametrize("launch", [(1, 0, 0), (2, 0, 0), (4, 0, 0), (1, 1, 0), (2, 1, 1), (4, 1, 2)])
+def test_tabu_launch_invariance(lb, launch):
+    say(f"tabu: launch configuration {launch} gives identical walks")
+    ns = I.uneven_lengths(300, 48, 120, seed=21)
+    rules = I.rules_tabu(3)
+    lb.set_launch(*launch)
+    try:
+        res = lb.tabu_batch(rules, len(ns), 1002, ns=ns)
+    finally:
+        lb.set_launch(None)
+    best, be, fe = O.tabu_batch(len(ns), osched(rules), 1002, ns=ns, stride=128, nthreads=8)
+    assert np.array_equal(res.best_e.cpu().numpy(), be)
+    assert np.array_equal(res.final_e.cpu().numpy(), fe)
+    assert np.array_equal(res.best_seq.cpu().numpy(), best)
+
+
+def test_tabu_n64_full_size(lb):
+    wl = I.TABU_N64
+    say(f"tabu: {wl.name} full size W={wl.walks} N={wl.n}, all walks against the oracle")
+    res = lb.tabu_batch(wl.rules, wl.walks, wl.seed, n_uniform=wl.n)
+    best, be, fe = O.tabu_batch(wl.walks, osched(wl.rules), wl.seed, n_uniform=wl.n, stride=128,
+                                nthreads=16)
+    assert np.array_equal(res.best_e.cpu().numpy(), be)
+    assert np.array_equal(res.final_e.cpu().numpy(), fe)
+    assert np.array_equal(res.best_seq.cpu().numpy(), best)
+
+
+def test_tabu_uneven_full_size_sampled(lb):
+    wl = I.TABU_UNEVEN
+    ns = wl.lengths()
+    say(f"tabu: {wl.name} full size W={wl.walks}, sampled walks against the oracle")
+    res = lb.tabu_batch(wl.rules, wl.walks, wl.seed, ns=ns)
+    rng = np.random.default_rng(5)
+    sample = np.sort(rng.choice(wl.walks, size=256, replace=False))
+    sample = np.unique(np.concatenate([sample, [0, wl.walks - 1], np.argsort(-ns)[:4]]))
+    sch = osched(wl.rules)
+    be_g = res.best_e.cpu().numpy()
+    fe_g = res.final_e.cpu().numpy()
+    bs_g = res.best_seq.cpu().numpy()
+    for w in sample:
+        n = int(ns[w])
+        T, lo, hi = O.walk_schedule(n, sch, wl.seed, int(w), 0)
+        b, e1, f1, _, _ = O.tabu_walk(O.random_start(n, wl.seed, int(w)), wl.seed, int(w), 0, T, lo, hi, 1)
+        assert be_g[w] == e1 and fe_g[w] == f1
+        assert np.array_equal(bs_g[w, :n], b) and not bs_g[w, n:].any()
+    # properties at every walk: energies agree with the returned sequences
+    E = lb.energy_batch(res.best_seq, ns=torch.from_numpy(ns).cuda()).cpu().numpy()
+    assert np.array_equal(E, be_g)
+    assert np.all(be_g <= fe_g)
+    assert np.all(be_g % 4 == (ns // 2) % 4)
+
+
+def test_tabu_zero_walks_and_zero_steps(lb):
+    say("tabu: W=0 and zero-step walks")
+    r = lb.tabu_batch(I.rules_tabu(4), 0, 1, n_uniform=64)
+    assert r.best_e.numel() == 0
+    zero = I.Rules(I.STEPS_FIXED, 0, I.TENURE_LINEAR, 0, 1, 0, 0, 1, 0, 1)
+    res = lb.tabu_batch(zero, 10, 5, n_uniform=50)
+    starts = np.stack([O.random_start(50, 5, w) for w in range(10)])
+    assert np.array_equal(res.best_seq.cpu().numpy()[:, :50], starts)
+    assert np.array_equal(res.best_e.cpu().numpy(), [O.energy(s) for s in starts])
+
+
+def test_invalid_arguments(lb):
+    say("invalid arguments are rejected")
+    from paper_2504_00987_amd._lib import LabsError
+    with pytest.raises(LabsError):
+        lb.tabu_batch(I.rules_tabu(4), 4, 1, n_uniform=2)
+    with pytest.raises(LabsError):
+        lb.tabu_batch(I.rules_tabu(4), 4, 1, n_uniform=129)
+    bad = I.Rules(I.STEPS_FIXED, 10, I.TENURE_LINEAR, 0, 1, 0, 1, 1, 0, 1)  # maxTabu = N
+    with pytest.raises(LabsError):
+        lb.tabu_batch(bad, 4, 1, n_uniform=20)
+    with pytest.raises(LabsError):
+        lb.tabu_batch(I.rules_tabu(4), 4, 1, n_uniform=64, out_stride=32)
+
+
+# ---------------------------------------------------------------------------
+# Alg. 1 / Alg. 3: memetic replicas
+# ---------------------------------------------------------------------------
+def _oracle_memetic(n_list, K, rules, gens, seed, target=-1, p_comb=I.P_COMB_090):
+    out = []
+    for p, n in enumerate(n_list):
+        st = O.MemeticState(int(n), K, seed, p)
+        st.advance(gens, osched(rules), p_comb, O.p_mut_inv_n(int(n)), target=target)
+        out.append(st)
+    return out
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_memetic_n20_modes(lb, mode):
+    wl = I.MEMETIC_N20
+    pops = 6
+    say(f"memetic N=20 K=100 {wl.generations} generations x {pops} replicas, mode {mode}")
+    res = lb.memetic_run(wl.K, wl.rules, wl.generations, pops, wl.seed, n_uniform=wl.n,
+                         mode=mode, chunk=7)
+    ref = _oracle_memetic([wl.n] * pops, wl.K, wl.rules, wl.generations, wl.seed)
+    emin, _ = O.bruteforce_min(20)
+    for p, st in enumerate(ref):
+        assert res.best_e[p].item() == st.bestE >= emin
+        assert np.array_equal(res.best_seq[p, :20].cpu().numpy(), st.best)
+        assert res.gens_done[p].item() == wl.generations and res.hit_gen[p].item() == -1
+
+
+def test_memetic_uneven_lengths(lb):
+    ns = np.array([3, 7, 31, 64, 65, 96, 120, 128], dtype=np.int32)
+    say(f"memetic ragged N={list(ns)}, K=24, 12 generations")
+    rules = I.RULES_MEMETIC
+    res = lb.memetic_run(24, rules, 12, len(ns), 77, ns=ns, mode=2, chunk=5)
+    ref = _oracle_memetic(ns, 24, rules, 12, 77)
+    for p, st in enumerate(ref):
+        n = int(ns[p])
+        assert res.best_e[p].item() == st.bestE
+        assert np.array_equal(res.best_seq[p, :n].cpu().numpy(), st.best)
+
+
+def test_memetic_target_and_stop_all(lb):
+    n, K, G = 26, 40, 60
+    rules = I.RULES_MEMETIC
+    base = _oracle_memetic([n] * 4, K, rules, G, 31)
+    target = sorted(st.bestE for st in base)[1]
+    say(f"memetic target {target}: per-replica hit generations")
+    ref = _oracle_memetic([n] * 4, K, rules, G, 31, target=target)
+    res = lb.memetic_run(K, rules, G, 4, 31, n_uniform=n, target=target, mode=2, chunk=4)
+    for p, st in enumerate(ref):
+        assert res.hit_gen[p].item() == st.hit
+        assert res.best_e[p].item() == st.bestE
+        assert res.gens_done[p].item() == st.gen
+    # global flag: everyone stops at the end of the chunk in which the first hit happened
+    res2 = lb.memetic_run(K, rules, G, 4, 31, n_uniform=n, target=target, mode=0, chunk=4, stop_all=1)
+    first = min(st.hit for st in ref if st.hit >= 0)
+    stop = max(4, ((first + 3) // 4) * 4)
+    for p, st in enumerate(ref):
+        g = int(res2.gens_done[p].item())
+        assert g == (st.gen if st.hit >= 0 and st.hit <= stop else stop)
+
+
+def test_memetic_n120_prefix(lb):
+    wl = I.MEMETIC_N120
+    pops, gens = 16, 6
+    say(f"memetic N=120 K=100: {pops} replicas x {gens} generations, graph mode")
+    res = lb.memetic_run(wl.K, wl.rules, gens, pops, wl.seed, n_uniform=wl.n, mode=1, chunk=3)
+    ref = _oracle_memetic([wl.n] * pops, wl.K, wl.rules, gens, wl.seed)
+    for p, st in enumerate(ref):
+        assert res.best_e[p].item() == st.bestE
+        assert np.array_equal(res.best_seq[p, :120].cpu().numpy(), st.best)
+
+
+# ---------------------------------------------------------------------------
+# Serving
+# ---------------------------------------------------------------------------
+def test_server_alone_equals_mix(lb):
+    import time
+    from paper_2504_00987_amd.labs import Server
+    reqs = I.serving_requests(10, seed=77)
+    pops, gens, K = 3, 6, 16
+    rules = I.RULES_MEMETIC
+    say(f"server: {len(reqs)} requests, N={[n for n, _ in reqs]}")
+    srv = Server(lb, K, rules, max_slots=8, chunk=2)
+    try:
+        ids = [(srv.submit(n, s, pops, gens), n, s) for n, s in reqs]
+        results = {}
+        t0 = time.time()
+        while len(results) < len(ids) and time.time() - t0 < 60:
+            for rid, n, s in ids:
+                if rid not in results:
+                    r = srv.poll(rid, n)
+                    if r is not None:
+                        results[rid] = r
+            time.sleep(0.005)
+        assert len(results) == len(ids)
+    finally:
+        srv.close()
+    for rid, n, s in ids:
+        seq, e, lat = results[rid]
+        alone = lb.memetic_run(K, rules, gens, pops, s, n_uniform=n, mode=2, chunk=gens)
+        be = alone.best_e.cpu().numpy()
+        p = int(np.argmin(be))
+        assert e == be[p]
+        assert np.array_equal(seq, alone.best_seq[p, :n].cpu().numpy())
+        assert lat > 0
+    # and the smallest request against the oracle
+    n, s = min(reqs)
+    ref = _oracle_memetic([n] * pops, K, rules, gens, s)
+    rid = [r for r, nn, ss in ids if (nn, ss) == (n, s)][0]
+    assert results[rid][1] == min(st.bestE for st in ref)
