@@ -340,7 +340,7 @@ __device__ WalkResult<NW> tabu_walk(const int N, const typename MaskOf<NW>::type
     Mask best = M;
     int bestE = E;
 
-    if (lane == 0) ps[0] = 0;
+    ps[0] = 0;  // every lane stores the same value
     Mask P[8];
     int q = build_planes<NW>(C, P);
     uint32_t dr0 = 0u, dr1 = 0u;
@@ -417,10 +417,8 @@ __device__ WalkResult<NW> tabu_walk(const int N, const typename MaskOf<NW>::type
 
         // Apply the move: tenure, sequence, energy, best.
         const int tenure = sch.lo + (int)below(u1, (uint32_t)(sch.hi - sch.lo + 1));
-        if (pick == lane) tabu[0] = t + tenure;
-        if constexpr (NW == 2) {
-            if (pick == lane + 64) tabu[1] = t + tenure;
-        }
+        tabu[0] = pick == lane ? t + tenure : tabu[0];
+        if constexpr (NW == 2) tabu[1] = pick == lane + 64 ? t + tenure : tabu[1];
         const int sm = 1 - 2 * m_bit(M, pick);
         M = m_xor(M, m_onebit(M, pick));
         Mr = m_xor(Mr, m_onebit(Mr, N - 1 - pick));
@@ -429,7 +427,7 @@ __device__ WalkResult<NW> tabu_walk(const int N, const typename MaskOf<NW>::type
             bestE = E;
             best = M;
         }
-        if (trace != nullptr && lane == 0) trace[t - 1] = (int16_t)pick;
+        if (trace != nullptr) trace[t - 1] = (int16_t)pick;  // uniform store
 
         // C_k -= 2 s_pick t_pick,k for every lag (lane-parallel).
 #pragma unroll

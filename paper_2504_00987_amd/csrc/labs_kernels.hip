@@ -45,7 +45,7 @@ __global__ __launch_bounds__(64 * WPG) void energy_kernel(const int8_t *__restri
         }
     }
     const int E = wave_sum(acc);
-    if (lane == 0) out[b] = E;
+    out[b] = E;  // every lane stores the same value: no lane-0 branch
 }
 
 // ---------------------------------------------------------------------------
@@ -82,10 +82,8 @@ __device__ void run_tabu_item(const TabuLaunchArgs &a, int64_t w, int N, int *ps
     int8_t *out = a.best_seq + w * (int64_t)a.out_stride;
     for (int i = lane; i < a.out_stride; i += 64)
         out[i] = i < N ? (m_bit(r.best, i) ? (int8_t)-1 : (int8_t)1) : (int8_t)0;
-    if (lane == 0) {
-        a.best_e[w] = r.best_e;
-        a.final_e[w] = r.final_e;
-    }
+    a.best_e[w] = r.best_e;  // uniform values, stored by every lane
+    a.final_e[w] = r.final_e;
 }
 
 __device__ __forceinline__ void run_tabu_index(const TabuLaunchArgs &a, int64_t idx, int *ps) {
@@ -97,22 +95,27 @@ __device__ __forceinline__ void run_tabu_index(const TabuLaunchArgs &a, int64_t 
         run_tabu_item<2>(a, w, N, ps);
 }
 
+// Next index of the persistent work queue, wave-uniform.  Every lane executes
+// the atomic (lane 0 adds 1, the others add 0) so that the value read back
+// with readlane is never produced under a lane-dependent branch: a
+// lane-0-only fetch lets the optimiser thread that branch into the loop's
+// other lane-0 branches, and lanes then reach the readlane before lane 0 has
+// fetched, disagreeing on the index.
+__device__ __forceinline__ uint32_t next_work(uint32_t *counter) {
+    const uint32_t v = atomicAdd(counter, lane_id() == 0 ? 1u : 0u);
+    return readlane_u(v, 0);
+}
+
 template <int WPG>
 __global__ __launch_bounds__(64 * WPG) void tabu_kernel(TabuLaunchArgs a, int persistent) {
     __shared__ int ps_all[WPG][kPsInts];
     const int wave = threadIdx.x >> 6;
-    const int lane = lane_id();
     int *ps = ps_all[wave];
     if (persistent) {
         // Each wave takes walks from the queue until it is empty; the queue
         // head only grows, so every wave leaves after at most W + 1 takes.
-        for (;;) {
-            uint32_t idx = 0u;
-            if (lane == 0) idx = atomicAdd(a.counter, 1u);
-            idx = readlane_u(idx, 0);
-            if ((int64_t)idx >= a.W) break;
+        for (uint32_t idx = next_work(a.counter); (int64_t)idx < a.W; idx = next_work(a.counter))
             run_tabu_index(a, (int64_t)idx, ps);
-        }
     } else {
         const int64_t idx = (int64_t)blockIdx.x * WPG + wave;
         if (idx < a.W) run_tabu_index(a, idx, ps);
@@ -168,13 +171,11 @@ __global__ __launch_bounds__(64) void memetic_init_kernel(MemeticLaunchArgs a) {
                          readlane_u((uint32_t)sel_lo, src);
     const uint64_t bhi = ((uint64_t)readlane_u((uint32_t)(sel_hi >> 32), src) << 32) |
                          readlane_u((uint32_t)sel_hi, src);
-    if (lane == 0) {
-        a.st.best[(int64_t)sl.state * 2 + 0] = blo;
-        a.st.best[(int64_t)sl.state * 2 + 1] = bhi;
-        a.st.bestE[sl.state] = mn;
-        a.st.gen[sl.state] = 0;
-        a.st.hit[sl.state] = -1;
-    }
+    a.st.best[(int64_t)sl.state * 2 + 0] = blo;  // uniform values, every lane
+    a.st.best[(int64_t)sl.state * 2 + 1] = bhi;
+    a.st.bestE[sl.state] = mn;
+    a.st.gen[sl.state] = 0;
+    a.st.hit[sl.state] = -1;
 }
 
 template <int NW>
@@ -245,11 +246,9 @@ __device__ void memetic_replica(const MemeticLaunchArgs &a, const MemeticSlot &s
         }
         const int rep = (int)below(db.w2, (uint32_t)K);
         wave_sync();
-        if (lane == 0) {
-            pop[rep][0] = mask_lo(r.best);
-            pop[rep][1] = mask_hi(r.best);
-            popE[rep] = r.best_e;
-        }
+        pop[rep][0] = mask_lo(r.best);  // uniform values, every lane
+        pop[rep][1] = mask_hi(r.best);
+        popE[rep] = r.best_e;
         wave_sync();
         ++g;
         if (targeted && bestE <= sl.target) {
@@ -263,14 +262,12 @@ __device__ void memetic_replica(const MemeticLaunchArgs &a, const MemeticSlot &s
         a.st.pop[(base + i) * 2 + 1] = pop[i][1];
         a.st.popE[base + i] = popE[i];
     }
-    if (lane == 0) {
-        a.st.best[(int64_t)st * 2 + 0] = mask_lo(best);
-        a.st.best[(int64_t)st * 2 + 1] = mask_hi(best);
-        a.st.bestE[st] = bestE;
-        a.st.gen[st] = g;
-        a.st.hit[st] = hit;
-        if (hit >= 0 && a.any_hit != nullptr) atomicOr(a.any_hit, 1u);
-    }
+    a.st.best[(int64_t)st * 2 + 0] = mask_lo(best);  // uniform values, every lane
+    a.st.best[(int64_t)st * 2 + 1] = mask_hi(best);
+    a.st.bestE[st] = bestE;
+    a.st.gen[st] = g;
+    a.st.hit[st] = hit;
+    if (hit >= 0 && a.any_hit != nullptr) atomicOr(a.any_hit, 1u);
 }
 
 __global__ __launch_bounds__(64) void memetic_advance_kernel(MemeticLaunchArgs a) {
@@ -302,11 +299,9 @@ __global__ void gather_best_kernel(MemeticStateDev st, const int32_t *__restrict
     int8_t *out = best_seq + (int64_t)i * out_stride;
     for (int k = lane; k < out_stride; k += 64)
         out[k] = k < N ? (m_bit(b, k) ? (int8_t)-1 : (int8_t)1) : (int8_t)0;
-    if (lane == 0) {
-        best_e[i] = st.bestE[s];
-        if (hit_gen) hit_gen[i] = st.hit[s];
-        if (gens_done) gens_done[i] = st.gen[s];
-    }
+    best_e[i] = st.bestE[s];  // uniform values, every lane
+    if (hit_gen) hit_gen[i] = st.hit[s];
+    if (gens_done) gens_done[i] = st.gen[s];
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t count) {
