@@ -43,7 +43,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="tabu_n64", choices=["tabu_n64", "tabu_uneven"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-walks", type=int, default=0, help="oracle sample size (0: auto)")
+    ap.add_argument("--cpu-walks", type=int, default=0, help="oracle sample size (0: all walks)")
+    ap.add_argument("--cpu-min-s", type=float, default=10.0, help="minimum oracle timing")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -131,24 +132,32 @@ def main() -> int:
     }
 
     if not args.no_cpu:
+        # The oracle on this host's cores over the same workload, repeated
+        # until at least min_s seconds have elapsed (one pass is well under a
+        # second with 16 threads).  Walks are independent, so the oracle's
+        # batch call spreads them over threads; nothing else is tuned.
         from oracle import oracle as O
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
-        sample = args.cpu_walks or (1024 if uniform else 512)
+        sample = args.cpu_walks or W
         sched = O.Schedule(wl.rules.steps_rule, wl.rules.steps_a, wl.rules.tenure_rule,
                            wl.rules.lo_num, wl.rules.lo_den, wl.rules.lo_add, wl.rules.hi_num,
                            wl.rules.hi_den, wl.rules.hi_add, wl.rules.aspiration)
         sub_ns = ns[:sample]
-        c0 = time.perf_counter()
-        O.tabu_batch(sample, sched, wl.seed, ns=sub_ns, stride=128, nthreads=threads)
+        passes, c0 = 0, time.perf_counter()
+        while True:
+            O.tabu_batch(sample, sched, wl.seed, ns=sub_ns, stride=128, nthreads=threads)
+            passes += 1
+            if time.perf_counter() - c0 >= args.cpu_min_s or passes >= 100:
+                break
         cpu_s = time.perf_counter() - c0
-        cpu_evals = int(np.sum(sub_ns.astype(np.int64) * wl.rules.steps_a * sub_ns))
+        cpu_evals = passes * int(np.sum(sub_ns.astype(np.int64) * wl.rules.steps_a * sub_ns))
         line["cpu_baseline"] = {
             "value": cpu_evals / cpu_s,
             "unit": "evals/s",
             "cores": threads,
             "kind": "oracle",
-            "sample": f"walks 0..{sample - 1} of {wl.name} ({cpu_s:.1f} s, gcc -O2 plain C, "
-                      f"{threads} threads)",
+            "sample": f"{passes} passes over walks 0..{sample - 1} of {wl.name} in {cpu_s:.1f} s "
+                      f"(plain C, gcc -O2, {threads} threads)",
         }
     print(json.dumps(line), flush=True)
     lb.close()

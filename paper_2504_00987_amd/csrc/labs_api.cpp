@@ -176,9 +176,10 @@ int bucket_of(int n) { return std::min(7, std::max(0, (n - 1) / 16)); }
 labs_launch default_launch(labs_handle *h, bool uneven) {
     labs_launch l;
     l.waves_per_group = 1;
-    l.persistent = uneven ? 1 : 0;
+    l.persistent = 0;
     l.groups_per_cu = 0;
     (void)h;
+    (void)uneven;
     return l;
 }
 
@@ -229,7 +230,10 @@ int labs_create(labs_handle **out, int device) {
     h->num_cus = prop.multiProcessorCount;
     h->arch = prop.gcnArchName;
     if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ws_event, hipEventDisableTiming) != hipSuccess) {
+        hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ws_event, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->fork_event, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->join_event, hipEventDisableTiming) != hipSuccess) {
         delete h;
         return LABS_E_HIP;
     }
@@ -246,7 +250,10 @@ int labs_destroy(labs_handle *h) {
     h->mem.release();
     h->pin.release();
     if (h->ws_event) hipEventDestroy(h->ws_event);
+    if (h->fork_event) hipEventDestroy(h->fork_event);
+    if (h->join_event) hipEventDestroy(h->join_event);
     if (h->stream) hipStreamDestroy(h->stream);
+    if (h->side) hipStreamDestroy(h->side);
     delete h;
     return LABS_OK;
 }
@@ -384,7 +391,12 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
                                       hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(h, e, "hipMemcpyAsync");
         a.ns = dn;
-        a.order = L.persistent ? dn + W : nullptr;
+        a.order = dn + W;
+        int64_t wide = 0;
+        for (int64_t i = 0; i < W; ++i) wide += ns_host[i] > 64;
+        a.n_wide = wide;
+    } else {
+        a.n_wide = n_uniform > 64 ? W : 0;
     }
     a.starts = starts;
     a.start_stride = start_stride;
@@ -401,8 +413,22 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
     a.trace = trace;
     a.trace_stride = trace_stride;
     const int groups = L.persistent ? persistent_groups(h, L) : 0;
-    hipError_t e = launch_tabu(a, L.waves_per_group, groups, s);
+    // A batch with both length classes runs them concurrently: the narrow
+    // part on the handle's side stream, joined back into `s`.
+    const bool split = a.n_wide > 0 && a.n_wide < W;
+    hipStream_t s2 = split ? h->side : s;
+    if (split) {
+        hipError_t e = hipEventRecord(h->fork_event, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s2, h->fork_event, 0);
+        if (e != hipSuccess) return hip_fail(h, e, "fork to side stream");
+    }
+    hipError_t e = launch_tabu(a, L.waves_per_group, groups, s, s2);
     if (e != hipSuccess) return hip_fail(h, e, "tabu kernel launch");
+    if (split) {
+        e = hipEventRecord(h->join_event, s2);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, h->join_event, 0);
+        if (e != hipSuccess) return hip_fail(h, e, "join from side stream");
+    }
     return ws_release(h, s);
 }
 

@@ -117,6 +117,15 @@ __device__ __forceinline__ int wave_min(int v) {
     return min(min(a, b), min(c, d));
 }
 
+// Bitwise OR over the 64 lanes, returned wave-uniform.
+__device__ __forceinline__ int wave_or(int v) {
+    v |= __builtin_amdgcn_update_dpp(0, v, LABS_DPP_QUAD_1032, 0xf, 0xf, false);
+    v |= __builtin_amdgcn_update_dpp(0, v, LABS_DPP_QUAD_2301, 0xf, 0xf, false);
+    v |= __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_HALF_MIRROR, 0xf, 0xf, false);
+    v |= __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_MIRROR, 0xf, 0xf, false);
+    return readlane(v, 0) | readlane(v, 16) | readlane(v, 32) | readlane(v, 48);
+}
+
 // Sum over the 64 lanes, returned wave-uniform.
 __device__ __forceinline__ int wave_sum(int v) {
     v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_QUAD_1032, 0xf, 0xf, false);
@@ -213,6 +222,28 @@ __device__ __forceinline__ uint64_t mask_hi(uint64_t) { return 0ull; }
 __device__ __forceinline__ uint64_t mask_lo(M128 a) { return a.lo; }
 __device__ __forceinline__ uint64_t mask_hi(M128 a) { return a.hi; }
 
+// Half-width companion of a mask (the shorter window of a neighbour).
+template <int NW> struct SmallOf;
+template <> struct SmallOf<1> { using type = uint32_t; };
+template <> struct SmallOf<2> { using type = uint64_t; };
+
+__device__ __forceinline__ uint32_t low_half(uint64_t a) { return (uint32_t)a; }
+__device__ __forceinline__ uint64_t low_half(M128 a) { return a.lo; }
+__device__ __forceinline__ int s_popc(uint32_t a) { return __popc(a); }
+__device__ __forceinline__ int s_popc(uint64_t a) { return __popcll(a); }
+// Bits [0, n) of a half-width word, 0 <= n < its width.
+__device__ __forceinline__ uint32_t s_low(uint32_t, int n) { return (1u << n) - 1u; }
+__device__ __forceinline__ uint64_t s_low(uint64_t, int n) { return (1ull << n) - 1ull; }
+
+// popcount(big & plane) + popcount(small & low half of plane).
+__device__ __forceinline__ int plane_count(uint64_t big, uint32_t small, uint64_t P) {
+    return __popc((uint32_t)big & (uint32_t)P) + __popc((uint32_t)(big >> 32) & (uint32_t)(P >> 32)) +
+           __popc(small & (uint32_t)P);
+}
+__device__ __forceinline__ int plane_count(M128 big, uint64_t small, M128 P) {
+    return __popcll(big.lo & P.lo) + __popcll(big.hi & P.hi) + __popcll(small & P.lo);
+}
+
 template <int NW>
 __device__ __forceinline__ typename MaskOf<NW>::type make_mask(uint64_t lo, uint64_t hi) {
     if constexpr (NW == 1) {
@@ -280,24 +311,25 @@ struct WalkResult {
     int final_e;
 };
 
-// Bit planes of the lane-held table C (two's complement, bits 0..7) and the
-// number q of planes needed: planes q-1..7 all equal the sign plane, so
-// C_k = sum_{p<q-1} 2^p bit_p - 2^(q-1) bit_(q-1).
+// Bit plane p of the lane-held table C (two's complement): bit k-1 is bit p
+// of C_k.
 template <int NW>
-__device__ __forceinline__ int build_planes(const int (&C)[NW],
-                                            typename MaskOf<NW>::type (&P)[8]) {
-#pragma unroll
-    for (int p = 0; p < 8; ++p) {
-        const uint64_t lo = ballot(((C[0] >> p) & 1) != 0);
-        uint64_t hi = 0ull;
-        if constexpr (NW == 2) hi = ballot(((C[1] >> p) & 1) != 0);
-        P[p] = make_mask<NW>(lo, hi);
-    }
-    int q = 1;
-#pragma unroll
-    for (int p = 0; p < 7; ++p)
-        if (!m_eq(P[p], P[7])) q = p + 2;
-    return q;
+__device__ __forceinline__ typename MaskOf<NW>::type plane(const int (&C)[NW], int p) {
+    const uint64_t lo = ballot(((C[0] >> p) & 1) != 0);
+    uint64_t hi = 0ull;
+    if constexpr (NW == 2) hi = ballot(((C[1] >> p) & 1) != 0);
+    return make_mask<NW>(lo, hi);
+}
+
+// Number q of planes needed: every C_k lies in [-2^(q-1), 2^(q-1)), so planes
+// q-1..7 all equal the sign plane and C_k = sum_{p<q-1} 2^p bit_p(C_k)
+// - 2^(q-1) bit_(q-1)(C_k).
+template <int NW>
+__device__ __forceinline__ int planes_needed(const int (&C)[NW]) {
+    int x = C[0] ^ (C[0] >> 31);
+    if constexpr (NW == 2) x |= C[1] ^ (C[1] >> 31);
+    const int o = wave_or(x);
+    return o == 0 ? 1 : 33 - __clz(o);
 }
 
 // Runs one walk of sch.T steps from mask M0 (bits >= N must be clear).
@@ -305,12 +337,13 @@ __device__ __forceinline__ int build_planes(const int (&C)[NW],
 //   trace  optional: trace[t-1] = flipped index (written by lane 0)
 // Every lane of the wavefront must call this with identical uniform inputs.
 template <int NW>
-__device__ WalkResult<NW> tabu_walk(const int N, const typename MaskOf<NW>::type M0,
+__device__ __forceinline__ WalkResult<NW> tabu_walk(const int N, const typename MaskOf<NW>::type M0,
                                     const Schedule sch, const int aspiration,
                                     const uint32_t k0, const uint32_t k1,
                                     const uint32_t entity, const uint32_t gen,
                                     int *__restrict__ ps, int16_t *__restrict__ trace) {
     using Mask = typename MaskOf<NW>::type;
+    using Small = typename SmallOf<NW>::type;
     const int lane = lane_id();
     Mask M = M0;
 
@@ -341,8 +374,6 @@ __device__ WalkResult<NW> tabu_walk(const int N, const typename MaskOf<NW>::type
     int bestE = E;
 
     ps[0] = 0;  // every lane stores the same value
-    Mask P[8];
-    int q = build_planes<NW>(C, P);
     uint32_t dr0 = 0u, dr1 = 0u;
 
     for (int t = 1; t <= sch.T; ++t) {
@@ -366,31 +397,50 @@ __device__ WalkResult<NW> tabu_walk(const int N, const typename MaskOf<NW>::type
         }
         wave_sync();
 
-        // Score the neighbours this lane owns.
+        // Score the neighbours this lane owns.  Neighbour j's right window
+        // has N-1-j meaningful bits and its left window j; the longer one
+        // ("big") needs the full mask width, the shorter ("small") at most
+        // half of it, so each plane costs 3 (N <= 64) or 6 (N <= 128) words.
+        // Lanes past the sequence compute on empty windows and are masked
+        // out at the end, so the loop has no lane-dependent branch.
+        Mask big[NW];
+        Small small[NW];
+        int bs[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int j = lane + 64 * w;
+            const bool in = j < N;
+            const Mask R = m_shr(M, j + 1);                  // bit k-1: s_{j+k} = -1
+            const Mask L = m_shr(Mr, in ? N - j : 64 * NW);  // bit k-1: s_{j-k} = -1
+            const bool right_big = N - 1 - j >= j;
+            big[w] = right_big ? R : L;
+            small[w] = low_half(right_big ? L : R);
+            bs[w] = 0;
+        }
+        const int q = planes_needed<NW>(C);
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            if (p < q) {
+                const Mask P = plane<NW>(C, p);
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    const int cnt = plane_count(big[w], small[w], P);
+                    bs[w] += (p == q - 1) ? -(cnt << p) : (cnt << p);  // sum_k (bR_k + bL_k) C_k
+                }
+            }
+        }
         int key[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             const int j = lane + 64 * w;
-            key[w] = INT_MAX;
-            if (j < N) {
-                const Mask R = m_shr(M, j + 1);   // bit k-1: s_{j+k} = -1
-                const Mask L = m_shr(Mr, N - j);  // bit k-1: s_{j-k} = -1
-                int bs = 0;                       // sum_k (bR_k + bL_k) C_k
-#pragma unroll
-                for (int p = 0; p < 8; ++p) {
-                    if (p < q) {
-                        const int cnt = m_popc(m_and(R, P[p])) + m_popc(m_and(L, P[p]));
-                        bs += (p == q - 1) ? -(cnt << p) : (cnt << p);
-                    }
-                }
-                const int nb = min(N - 1 - j, j);
-                const int u = nb - 2 * m_popc(m_and(m_xor(R, L), m_low(M, nb)));
-                const int v = ps[N - 1 - j] + ps[j] - 2 * bs;
-                const int sj = 1 - 2 * m_bit(M, j);
-                const int cand = E + 4 * (N - 1 + 2 * u - sj * v);
-                const bool admissible = tabu[w] < t || (aspiration && cand < bestE);
-                if (admissible) key[w] = cand;
-            }
+            const bool in = j < N;
+            const int nb = in ? min(N - 1 - j, j) : 0;  // lags with both sides inside
+            const int u = nb - 2 * s_popc((low_half(big[w]) ^ small[w]) & s_low(small[w], nb));
+            const int v = ps[in ? N - 1 - j : 0] + ps[in ? j : 0] - 2 * bs[w];
+            const int sj = 1 - 2 * m_bit(M, in ? j : 0);
+            const int cand = E + 4 * (N - 1 + 2 * u - sj * v);
+            const bool admissible = tabu[w] < t || (aspiration && cand < bestE);
+            key[w] = in && admissible ? cand : INT_MAX;
         }
 
         // Admissible minimum, ties broken by the step's draw.
@@ -440,7 +490,6 @@ __device__ WalkResult<NW> tabu_walk(const int N, const typename MaskOf<NW>::type
                 C[w] -= 2 * sm * (sa + sb);
             }
         }
-        q = build_planes<NW>(C, P);
     }
 
     WalkResult<NW> res;

@@ -43,7 +43,10 @@ struct labs_handle {
     std::string arch;
     std::string last_error;
     hipStream_t stream = nullptr;      // internal stream (default priority)
+    hipStream_t side = nullptr;        // second stream for the narrow part of a mixed batch
     hipEvent_t ws_event = nullptr;     // completion of the last workspace user
+    hipEvent_t fork_event = nullptr;
+    hipEvent_t join_event = nullptr;
     bool ws_event_valid = false;
     liblabs::DevBuf ws;                   // tabu workspace: queue head, ns, order
     liblabs::DevBuf mem;                  // memetic state and slot table

@@ -21,6 +21,7 @@ struct TabuLaunchArgs {
     int32_t n_max;            // longest walk in the batch
     const int32_t *order;     // device [W] walk ids in processing order, or null
     int64_t W;
+    int64_t n_wide;           // leading positions of the order with N > 64
     uint32_t k0, k1;
     RuleParams rule;
     int8_t *best_seq;
@@ -60,6 +61,7 @@ struct MemeticLaunchArgs {
     uint32_t p_mut;
     RuleParams rule;
     int32_t gens;            // generations per launch
+    int32_t classes;         // bit 0: some slot has N <= 64; bit 1: some N > 64
     MemeticStateDev st;
     uint32_t *any_hit;       // set to 1 when a replica reaches its target
 };
@@ -68,8 +70,10 @@ hipError_t launch_energy(const int8_t *seqs, const int32_t *ns, int32_t n_unifor
                          int32_t stride, int64_t count, int32_t *out, hipStream_t s);
 
 // waves_per_group in {1,2,4}; persistent grid = groups (0: one wave per walk).
+// Walks with N > 64 run on s_wide, the others on s_narrow (may be the same).
+// a.counter must point at 64 writable uint32 (two queue heads).
 hipError_t launch_tabu(const TabuLaunchArgs &a, int waves_per_group, int groups,
-                       hipStream_t s);
+                       hipStream_t s_wide, hipStream_t s_narrow);
 
 hipError_t launch_memetic_init(const MemeticLaunchArgs &a, hipStream_t s);
 hipError_t launch_memetic_advance(const MemeticLaunchArgs &a, hipStream_t s);

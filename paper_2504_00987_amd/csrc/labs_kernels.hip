@@ -7,6 +7,8 @@
 //   memetic_init_kernel    random populations (Alg. 1, first two lines)
 //   memetic_advance_kernel memetic generations (Alg. 1 / Alg. 3), one replica
 //                          per wave, population resident in LDS
+#include <algorithm>
+
 #include "labs_device.hpp"
 #include "labs_internal.h"
 
@@ -86,15 +88,6 @@ __device__ void run_tabu_item(const TabuLaunchArgs &a, int64_t w, int N, int *ps
     a.final_e[w] = r.final_e;
 }
 
-__device__ __forceinline__ void run_tabu_index(const TabuLaunchArgs &a, int64_t idx, int *ps) {
-    const int64_t w = a.order ? (int64_t)a.order[idx] : idx;
-    const int N = a.ns ? a.ns[w] : a.n_uniform;
-    if (N <= 64)
-        run_tabu_item<1>(a, w, N, ps);
-    else
-        run_tabu_item<2>(a, w, N, ps);
-}
-
 // Next index of the persistent work queue, wave-uniform.  Every lane executes
 // the atomic (lane 0 adds 1, the others add 0) so that the value read back
 // with readlane is never produced under a lane-dependent branch: a
@@ -106,19 +99,28 @@ __device__ __forceinline__ uint32_t next_work(uint32_t *counter) {
     return readlane_u(v, 0);
 }
 
-template <int WPG>
-__global__ __launch_bounds__(64 * WPG) void tabu_kernel(TabuLaunchArgs a, int persistent) {
+// Walks at positions [begin, end) of the processing order, all with
+// N <= 64 (NW = 1) or all with 64 < N <= 128 (NW = 2).  PERSIST: a grid
+// sized to the device drains the range through the queue head `counter`;
+// otherwise one wave per position.
+template <int NW, int WPG, bool PERSIST>
+__global__ __launch_bounds__(64 * WPG) void tabu_kernel(TabuLaunchArgs a, int64_t begin,
+                                                        int64_t end) {
     __shared__ int ps_all[WPG][kPsInts];
     const int wave = threadIdx.x >> 6;
     int *ps = ps_all[wave];
-    if (persistent) {
-        // Each wave takes walks from the queue until it is empty; the queue
-        // head only grows, so every wave leaves after at most W + 1 takes.
-        for (uint32_t idx = next_work(a.counter); (int64_t)idx < a.W; idx = next_work(a.counter))
-            run_tabu_index(a, (int64_t)idx, ps);
+    if constexpr (PERSIST) {
+        for (int64_t pos = begin + next_work(a.counter); pos < end;
+             pos = begin + next_work(a.counter)) {
+            const int64_t w = a.order ? (int64_t)a.order[pos] : pos;
+            run_tabu_item<NW>(a, w, a.ns ? a.ns[w] : a.n_uniform, ps);
+        }
     } else {
-        const int64_t idx = (int64_t)blockIdx.x * WPG + wave;
-        if (idx < a.W) run_tabu_index(a, idx, ps);
+        const int64_t pos = begin + (int64_t)blockIdx.x * WPG + wave;
+        if (pos < end) {
+            const int64_t w = a.order ? (int64_t)a.order[pos] : pos;
+            run_tabu_item<NW>(a, w, a.ns ? a.ns[w] : a.n_uniform, ps);
+        }
     }
 }
 
@@ -270,6 +272,9 @@ __device__ void memetic_replica(const MemeticLaunchArgs &a, const MemeticSlot &s
     if (hit >= 0 && a.any_hit != nullptr) atomicOr(a.any_hit, 1u);
 }
 
+// Replicas of one length class: N <= 64 (NW = 1) or 64 < N <= 128 (NW = 2);
+// slots of the other class and idle slots return at once.
+template <int NW>
 __global__ __launch_bounds__(64) void memetic_advance_kernel(MemeticLaunchArgs a) {
     __shared__ uint64_t pop[kMaxK][2];
     __shared__ int popE[kMaxK];
@@ -277,11 +282,8 @@ __global__ __launch_bounds__(64) void memetic_advance_kernel(MemeticLaunchArgs a
     const int s = blockIdx.x;
     if (s >= a.n_slots) return;
     const MemeticSlot sl = a.slots[s];
-    if (sl.state < 0) return;
-    if (sl.n <= 64)
-        memetic_replica<1>(a, sl, pop, popE, ps);
-    else
-        memetic_replica<2>(a, sl, pop, popE, ps);
+    if (sl.state < 0 || (sl.n > 64) != (NW == 2)) return;
+    memetic_replica<NW>(a, sl, pop, popE, ps);
 }
 
 __global__ void gather_best_kernel(MemeticStateDev st, const int32_t *__restrict__ state_idx,
@@ -321,29 +323,49 @@ hipError_t launch_energy(const int8_t *seqs, const int32_t *ns, int32_t n_unifor
     return hipGetLastError();
 }
 
-hipError_t launch_tabu(const TabuLaunchArgs &a, int waves_per_group, int groups,
-                       hipStream_t s) {
-    if (a.W <= 0) return hipSuccess;
-    const int persistent = groups > 0 ? 1 : 0;
-    if (persistent) {
+namespace {
+
+template <int NW, int WPG>
+hipError_t launch_tabu_part(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
+                            hipStream_t s) {
+    if (end <= begin) return hipSuccess;
+    if (groups > 0) {
         hipError_t e = launch_fill_u32(a.counter, 0u, 1, s);
         if (e != hipSuccess) return e;
-    }
-    const int64_t grid = persistent ? groups : (a.W + waves_per_group - 1) / waves_per_group;
-    switch (waves_per_group) {
-    case 1:
-        hipLaunchKernelGGL(tabu_kernel<1>, dim3((unsigned)grid), dim3(64), 0, s, a, persistent);
-        break;
-    case 2:
-        hipLaunchKernelGGL(tabu_kernel<2>, dim3((unsigned)grid), dim3(128), 0, s, a, persistent);
-        break;
-    case 4:
-        hipLaunchKernelGGL(tabu_kernel<4>, dim3((unsigned)grid), dim3(256), 0, s, a, persistent);
-        break;
-    default:
-        return hipErrorInvalidValue;
+        const int64_t need = (end - begin + WPG - 1) / WPG;
+        hipLaunchKernelGGL((tabu_kernel<NW, WPG, true>), dim3((unsigned)std::min<int64_t>(groups, need)),
+                           dim3(64 * WPG), 0, s, a, begin, end);
+    } else {
+        const int64_t grid = (end - begin + WPG - 1) / WPG;
+        hipLaunchKernelGGL((tabu_kernel<NW, WPG, false>), dim3((unsigned)grid), dim3(64 * WPG), 0,
+                           s, a, begin, end);
     }
     return hipGetLastError();
+}
+
+template <int WPG>
+hipError_t launch_tabu_wpg(const TabuLaunchArgs &a, int groups, hipStream_t s_wide,
+                           hipStream_t s_narrow) {
+    // positions [0, n_wide) hold the walks with N > 64; each part has its
+    // own queue head (counter[0] and counter[32])
+    TabuLaunchArgs narrow = a;
+    narrow.counter = a.counter + 32;
+    hipError_t e = launch_tabu_part<2, WPG>(a, 0, a.n_wide, groups, s_wide);
+    if (e != hipSuccess) return e;
+    return launch_tabu_part<1, WPG>(narrow, a.n_wide, a.W, groups, s_narrow);
+}
+
+}  // namespace
+
+hipError_t launch_tabu(const TabuLaunchArgs &a, int waves_per_group, int groups,
+                       hipStream_t s_wide, hipStream_t s_narrow) {
+    if (a.W <= 0) return hipSuccess;
+    switch (waves_per_group) {
+    case 1: return launch_tabu_wpg<1>(a, groups, s_wide, s_narrow);
+    case 2: return launch_tabu_wpg<2>(a, groups, s_wide, s_narrow);
+    case 4: return launch_tabu_wpg<4>(a, groups, s_wide, s_narrow);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_memetic_init(const MemeticLaunchArgs &a, hipStream_t s) {
@@ -354,7 +376,10 @@ hipError_t launch_memetic_init(const MemeticLaunchArgs &a, hipStream_t s) {
 
 hipError_t launch_memetic_advance(const MemeticLaunchArgs &a, hipStream_t s) {
     if (a.n_slots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(memetic_advance_kernel, dim3((unsigned)a.n_slots), dim3(64), 0, s, a);
+    if (a.classes & 1)
+        hipLaunchKernelGGL(memetic_advance_kernel<1>, dim3((unsigned)a.n_slots), dim3(64), 0, s, a);
+    if (a.classes & 2)
+        hipLaunchKernelGGL(memetic_advance_kernel<2>, dim3((unsigned)a.n_slots), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

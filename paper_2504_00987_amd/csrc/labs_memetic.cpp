@@ -130,6 +130,8 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
     a.rule = rule;
     a.st = st;
     a.any_hit = d_flag;
+    a.classes = 0;
+    for (int i = 0; i < pops; ++i) a.classes |= (ns_host ? ns_host[i] : n_uniform) > 64 ? 2 : 1;
     if ((e = launch_fill_u32(d_flag, 0u, 1, s)) != hipSuccess) return hip_fail(h, e, "fill");
     if ((e = launch_memetic_init(a, s)) != hipSuccess) return hip_fail(h, e, "memetic init");
 

@@ -121,6 +121,9 @@ int labs_server::iterate(std::unique_lock<std::mutex> &lk) {
     bool any = false;
     for (int s = 0; s < max_slots; ++s) any |= owner[s] >= 0;
     if (!any) return 0;  // idle
+    int classes = 0;
+    for (int s = 0; s < max_slots; ++s)
+        if (owner[s] >= 0) classes |= h_slots[s].n > 64 ? 2 : 1;
     const int n_init = (int)fresh.size();
     for (int i = 0; i < n_init; ++i) h_init[i] = h_slots[fresh[i]];
     lk.unlock();
@@ -148,6 +151,7 @@ int labs_server::iterate(std::unique_lock<std::mutex> &lk) {
     a.slots = d_slots;
     a.n_slots = max_slots;
     a.gens = params.chunk;
+    a.classes = classes;
     if (e == hipSuccess) e = launch_memetic_advance(a, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(h_bestE, st.bestE, max_slots * 4, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(h_gen, st.gen, max_slots * 8, hipMemcpyDeviceToHost, stream);
