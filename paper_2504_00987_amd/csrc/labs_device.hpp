@@ -91,6 +91,13 @@ __device__ __forceinline__ uint32_t readlane_u(uint32_t v, int l) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
 }
 
+// A wave-uniform 64-bit value, read from the first lane into scalar registers.
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Orders this wavefront's LDS accesses across lanes.
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -235,13 +242,20 @@ __device__ __forceinline__ int s_popc(uint64_t a) { return __popcll(a); }
 __device__ __forceinline__ uint32_t s_low(uint32_t, int n) { return (1u << n) - 1u; }
 __device__ __forceinline__ uint64_t s_low(uint64_t, int n) { return (1ull << n) - 1ull; }
 
-// popcount(big & plane) + popcount(small & low half of plane).
-__device__ __forceinline__ int plane_count(uint64_t big, uint32_t small, uint64_t P) {
-    return __popc((uint32_t)big & (uint32_t)P) + __popc((uint32_t)(big >> 32) & (uint32_t)(P >> 32)) +
-           __popc(small & (uint32_t)P);
+// acc + popcount(big & plane) + popcount(small & low half of plane), as a
+// chain of popcount-accumulate operations.
+__device__ __forceinline__ int plane_count(uint64_t big, uint32_t small, uint64_t P, int acc) {
+    acc = __popc(small & (uint32_t)P) + acc;
+    acc = __popc((uint32_t)(big >> 32) & (uint32_t)(P >> 32)) + acc;
+    return __popc((uint32_t)big & (uint32_t)P) + acc;
 }
-__device__ __forceinline__ int plane_count(M128 big, uint64_t small, M128 P) {
-    return __popcll(big.lo & P.lo) + __popcll(big.hi & P.hi) + __popcll(small & P.lo);
+__device__ __forceinline__ int plane_count(M128 big, uint64_t small, M128 P, int acc) {
+    acc = __popc((uint32_t)small & (uint32_t)P.lo) + acc;
+    acc = __popc((uint32_t)(small >> 32) & (uint32_t)(P.lo >> 32)) + acc;
+    acc = __popc((uint32_t)big.hi & (uint32_t)P.hi) + acc;
+    acc = __popc((uint32_t)(big.hi >> 32) & (uint32_t)(P.hi >> 32)) + acc;
+    acc = __popc((uint32_t)(big.lo >> 32) & (uint32_t)(P.lo >> 32)) + acc;
+    return __popc((uint32_t)big.lo & (uint32_t)P.lo) + acc;
 }
 
 template <int NW>
@@ -321,15 +335,19 @@ __device__ __forceinline__ typename MaskOf<NW>::type plane(const int (&C)[NW], i
     return make_mask<NW>(lo, hi);
 }
 
-// Number q of planes needed: every C_k lies in [-2^(q-1), 2^(q-1)), so planes
-// q-1..7 all equal the sign plane and C_k = sum_{p<q-1} 2^p bit_p(C_k)
-// - 2^(q-1) bit_(q-1)(C_k).
+// Number q of planes needed: every C_k lies in [-2^(q-1), 2^(q-1)), so the
+// offset values C_k + 2^(q-1) are q-bit unsigned numbers.
 template <int NW>
 __device__ __forceinline__ int planes_needed(const int (&C)[NW]) {
     int x = C[0] ^ (C[0] >> 31);
     if constexpr (NW == 2) x |= C[1] ^ (C[1] >> 31);
     const int o = wave_or(x);
     return o == 0 ? 1 : 33 - __clz(o);
+}
+
+// Lane l receives bit l of a wave-uniform 64-bit mask.
+__device__ __forceinline__ bool lane_bit(uint64_t mask) {
+    return __builtin_amdgcn_inverse_ballot_w64(mask);
 }
 
 // Runs one walk of sch.T steps from mask M0 (bits >= N must be clear).
@@ -345,7 +363,9 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N, const typename 
     using Mask = typename MaskOf<NW>::type;
     using Small = typename SmallOf<NW>::type;
     const int lane = lane_id();
-    Mask M = M0;
+    // The sequence is wave-uniform; pinning it to scalar registers keeps the
+    // per-move mask arithmetic on the scalar unit.
+    Mask M = make_mask<NW>(uniform64(mask_lo(M0)), uniform64(mask_hi(M0)));
 
     // Reversed sequence: bit i of Mr is bit N-1-i of M.
     Mask Mr;
@@ -417,18 +437,24 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N, const typename 
             small[w] = low_half(right_big ? L : R);
             bs[w] = 0;
         }
+        // Offset-binary planes: with D_k = C_k + 2^(q-1) in [0, 2^q),
+        // sum_k x_k C_k = sum_p 2^p popc(x & plane_p(D)) - 2^(q-1) popc(x).
         const int q = planes_needed<NW>(C);
+        const int off = 1 << (q - 1);
+        int D[NW];
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
+        for (int w = 0; w < NW; ++w) D[w] = C[w] + off;
+#pragma unroll
+        for (int p = 7; p >= 0; --p) {  // Horner: bs = 2 bs + count_p
             if (p < q) {
-                const Mask P = plane<NW>(C, p);
+                const Mask P = plane<NW>(D, p);
 #pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    const int cnt = plane_count(big[w], small[w], P);
-                    bs[w] += (p == q - 1) ? -(cnt << p) : (cnt << p);  // sum_k (bR_k + bL_k) C_k
-                }
+                for (int w = 0; w < NW; ++w) bs[w] = plane_count(big[w], small[w], P, 2 * bs[w]);
             }
         }
+#pragma unroll
+        for (int w = 0; w < NW; ++w)  // bs = sum_k (bR_k + bL_k) C_k
+            bs[w] -= off * (m_popc(big[w]) + s_popc(small[w]));
         int key[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
@@ -457,11 +483,11 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N, const typename 
         int r = (int)below(u0, (uint32_t)c);
         int pick;
         if (r < c0) {
-            const uint64_t sel = ballot(((T0 >> lane) & 1ull) && rank_below(T0) == r);
+            const uint64_t sel = ballot(lane_bit(T0) && rank_below(T0) == r);
             pick = __builtin_ctzll(sel);
         } else {
             r -= c0;
-            const uint64_t sel = ballot(((T1 >> lane) & 1ull) && rank_below(T1) == r);
+            const uint64_t sel = ballot(lane_bit(T1) && rank_below(T1) == r);
             pick = 64 + __builtin_ctzll(sel);
         }
 
@@ -479,15 +505,25 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N, const typename 
         }
         if (trace != nullptr) trace[t - 1] = (int16_t)pick;  // uniform store
 
-        // C_k -= 2 s_pick t_pick,k for every lag (lane-parallel).
+        // C_k -= 2 s_pick t_pick,k for every lag (lane-parallel).  The
+        // windows of the flipped index are wave-uniform: lag k (bit k-1) of
+        // Rn / Ln says s_{pick+k} / s_{pick-k} = -1, of Rp / Lp that it is +1
+        // (both clear past the ends, so lags >= N keep C_k = 0).
+        {
+            const Mask Rn = m_shr(M, pick + 1);
+            const Mask Ln = m_shr(Mr, N - pick);
+            const Mask Rp = m_and(m_low(M, N - 1 - pick), m_not(Rn));
+            const Mask Lp = m_and(m_low(M, pick), m_not(Ln));
+            const int k2 = -2 * sm;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            const int k = lane + 1 + 64 * w;
-            if (k < N) {
-                const int a = pick + k, b = pick - k;
-                const int sa = a < N ? 1 - 2 * m_bit(M, a) : 0;
-                const int sb = b >= 0 ? 1 - 2 * m_bit(M, b) : 0;
-                C[w] -= 2 * sm * (sa + sb);
+            for (int w = 0; w < NW; ++w) {
+                const uint64_t rn = w == 0 ? mask_lo(Rn) : mask_hi(Rn);
+                const uint64_t ln = w == 0 ? mask_lo(Ln) : mask_hi(Ln);
+                const uint64_t rp = w == 0 ? mask_lo(Rp) : mask_hi(Rp);
+                const uint64_t lp = w == 0 ? mask_lo(Lp) : mask_hi(Lp);
+                const int sa = lane_bit(rn) ? -1 : (lane_bit(rp) ? 1 : 0);
+                const int sb = lane_bit(ln) ? -1 : (lane_bit(lp) ? 1 : 0);
+                C[w] += k2 * (sa + sb);
             }
         }
     }
