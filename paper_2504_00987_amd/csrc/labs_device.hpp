@@ -1,25 +1,27 @@
 // Device building blocks of liblabs (gfx950): counter-based RNG, wavefront
-// primitives, 128-bit sequence masks and the bit-sliced tabu walk.
+// primitives, 128-bit sequence masks and the tabu walk.
 //
 // One tabu walk (Alg. 2 / Alg. 4 of arXiv:2504.00987) runs on one 64-lane
 // wavefront.  The sequence is a wave-uniform bit mask (bit i set <=> s_i = -1)
 // held in scalar registers; lane l owns neighbour j = l (and j = l + 64 when
-// N > 64) and lag k = l + 1 (and k = l + 65).  The autocorrelation table C_k
-// (Eq. 1) lives one entry per lane and is exposed to every lane as eight
-// wave-uniform bit planes (two's complement, built with ballots), so the
-// score of neighbour j,
+// N > 64) and lag k = l + 1 (and k = l + 65).  The score of neighbour j is
 //
 //     dE_j = 4 * ( sum_k t_jk^2  -  s_j * sum_k t_jk C_k ),
 //     t_jk = s_{j+k} + s_{j-k}   (terms outside the sequence are 0),
 //
-// is evaluated with AND + popcount over 64-bit words instead of one
-// multiply-add per lag: sum_k t_jk C_k = PS(N-1-j) + PS(j)
-// - 2 * sum_p w_p * popcount((R_j | L_j) & plane_p), with R_j / L_j the
-// neighbour's right / left windows of set bits, PS the prefix sums of C and
-// w_p the plane weights.  Planes that only repeat the sign bit are skipped.
-// The flip of s_j changes C_k by -2 s_j t_jk (the paper's O(N) "one row and
-// column" update of Sec. III.C), applied lane-parallel.  All arithmetic is
-// exact int32.
+// (flipping s_j changes C_k of Eq. 1 by -2 s_j t_jk).  The sequence lives in
+// LDS twice as int8 +-1 with zeros past its ends -- forwards (P) and reversed
+// (Q) -- in 16 copies shifted by one byte each, so that every lane's right
+// window s_{j+1..} and left window s_{j-1..} (reversed) start on a 16-byte
+// boundary of some copy.  C_k is kept per lane in registers and mirrored in
+// LDS as int8 (|C_k| <= N-k <= 127).  A neighbour's sums are then packed
+// 4-way int8 dot products of 16-byte window chunks against C chunks:
+// sum_k t_jk C_k = <right, C> + <left, C>, sum_k s_{j+k} s_{j-k} =
+// <right, left> over the shorter window.  Each neighbour reads its longer
+// window over the full lag range and its shorter one over half of it.  After
+// a move, C_k is updated lane-parallel (the paper's O(N) update of one "row
+// and column", Sec. III.C) and one byte per copy is rewritten.  All
+// arithmetic is exact int32.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -77,12 +79,6 @@ __device__ __forceinline__ uint64_t ballot(bool p) {
     return __builtin_amdgcn_ballot_w64(p);
 }
 
-// Number of set bits of `mask` below this lane.
-__device__ __forceinline__ int rank_below(uint64_t mask) {
-    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
 __device__ __forceinline__ int readlane(int v, int l) {
     return __builtin_amdgcn_readlane(v, l);
 }
@@ -108,29 +104,21 @@ __device__ __forceinline__ void wave_sync() {
 // DPP controls (GFX9 encoding).
 #define LABS_DPP_QUAD_1032 0xB1
 #define LABS_DPP_QUAD_2301 0x4E
-#define LABS_DPP_ROW_SHR(n) (0x110 + (n))
 #define LABS_DPP_ROW_MIRROR 0x140
 #define LABS_DPP_ROW_HALF_MIRROR 0x141
 #define LABS_DPP_ROW_BCAST15 0x142
 #define LABS_DPP_ROW_BCAST31 0x143
 
-// Minimum over the 64 lanes, returned wave-uniform.
+// Minimum over the 64 lanes, returned wave-uniform: row minima by DPP, then
+// rows combined with the row broadcasts (lane 63 ends with the total).
 __device__ __forceinline__ int wave_min(int v) {
     v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, LABS_DPP_QUAD_1032, 0xf, 0xf, false));
     v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, LABS_DPP_QUAD_2301, 0xf, 0xf, false));
     v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, LABS_DPP_ROW_HALF_MIRROR, 0xf, 0xf, false));
     v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, LABS_DPP_ROW_MIRROR, 0xf, 0xf, false));
-    const int a = readlane(v, 0), b = readlane(v, 16), c = readlane(v, 32), d = readlane(v, 48);
-    return min(min(a, b), min(c, d));
-}
-
-// Bitwise OR over the 64 lanes, returned wave-uniform.
-__device__ __forceinline__ int wave_or(int v) {
-    v |= __builtin_amdgcn_update_dpp(0, v, LABS_DPP_QUAD_1032, 0xf, 0xf, false);
-    v |= __builtin_amdgcn_update_dpp(0, v, LABS_DPP_QUAD_2301, 0xf, 0xf, false);
-    v |= __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_HALF_MIRROR, 0xf, 0xf, false);
-    v |= __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_MIRROR, 0xf, 0xf, false);
-    return readlane(v, 0) | readlane(v, 16) | readlane(v, 32) | readlane(v, 48);
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, LABS_DPP_ROW_BCAST15, 0xa, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, LABS_DPP_ROW_BCAST31, 0xc, 0xf, false));
+    return readlane(v, 63);
 }
 
 // Sum over the 64 lanes, returned wave-uniform.
@@ -140,17 +128,6 @@ __device__ __forceinline__ int wave_sum(int v) {
     v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_HALF_MIRROR, 0xf, 0xf, false);
     v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_MIRROR, 0xf, 0xf, false);
     return readlane(v, 0) + readlane(v, 16) + readlane(v, 32) + readlane(v, 48);
-}
-
-// Inclusive prefix sum over lanes 0..63 (lane l receives v_0 + ... + v_l).
-__device__ __forceinline__ int wave_scan(int v) {
-    v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_SHR(1), 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_SHR(2), 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_SHR(4), 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_SHR(8), 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_BCAST15, 0xa, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, LABS_DPP_ROW_BCAST31, 0xc, 0xf, false);
-    return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -229,35 +206,6 @@ __device__ __forceinline__ uint64_t mask_hi(uint64_t) { return 0ull; }
 __device__ __forceinline__ uint64_t mask_lo(M128 a) { return a.lo; }
 __device__ __forceinline__ uint64_t mask_hi(M128 a) { return a.hi; }
 
-// Half-width companion of a mask (the shorter window of a neighbour).
-template <int NW> struct SmallOf;
-template <> struct SmallOf<1> { using type = uint32_t; };
-template <> struct SmallOf<2> { using type = uint64_t; };
-
-__device__ __forceinline__ uint32_t low_half(uint64_t a) { return (uint32_t)a; }
-__device__ __forceinline__ uint64_t low_half(M128 a) { return a.lo; }
-__device__ __forceinline__ int s_popc(uint32_t a) { return __popc(a); }
-__device__ __forceinline__ int s_popc(uint64_t a) { return __popcll(a); }
-// Bits [0, n) of a half-width word, 0 <= n < its width.
-__device__ __forceinline__ uint32_t s_low(uint32_t, int n) { return (1u << n) - 1u; }
-__device__ __forceinline__ uint64_t s_low(uint64_t, int n) { return (1ull << n) - 1ull; }
-
-// acc + popcount(big & plane) + popcount(small & low half of plane), as a
-// chain of popcount-accumulate operations.
-__device__ __forceinline__ int plane_count(uint64_t big, uint32_t small, uint64_t P, int acc) {
-    acc = __popc(small & (uint32_t)P) + acc;
-    acc = __popc((uint32_t)(big >> 32) & (uint32_t)(P >> 32)) + acc;
-    return __popc((uint32_t)big & (uint32_t)P) + acc;
-}
-__device__ __forceinline__ int plane_count(M128 big, uint64_t small, M128 P, int acc) {
-    acc = __popc((uint32_t)small & (uint32_t)P.lo) + acc;
-    acc = __popc((uint32_t)(small >> 32) & (uint32_t)(P.lo >> 32)) + acc;
-    acc = __popc((uint32_t)big.hi & (uint32_t)P.hi) + acc;
-    acc = __popc((uint32_t)(big.hi >> 32) & (uint32_t)(P.hi >> 32)) + acc;
-    acc = __popc((uint32_t)(big.lo >> 32) & (uint32_t)(P.lo >> 32)) + acc;
-    return __popc((uint32_t)big.lo & (uint32_t)P.lo) + acc;
-}
-
 template <int NW>
 __device__ __forceinline__ typename MaskOf<NW>::type make_mask(uint64_t lo, uint64_t hi) {
     if constexpr (NW == 1) {
@@ -325,24 +273,22 @@ struct WalkResult {
     int final_e;
 };
 
-// Bit plane p of the lane-held table C (two's complement): bit k-1 is bit p
-// of C_k.
+// LDS layout of one walk: P copies, Q copies, C bytes.
+//   copy c of P holds P[i + c] at byte i, P[x] = s_x (x < N), 0 otherwise;
+//   Q is the reversed sequence, Q[x] = s_{N-1-x};
+//   CB[k-1] = C_k as int8.
+// LEN covers the farthest byte a window reads; STRIDE is an odd multiple of
+// 16 so that the copies start in different LDS banks.
+template <int NW> struct WalkLds;
+template <> struct WalkLds<1> {
+    static constexpr int LEN = 128, STRIDE = 144, CLEN = 64, NBIG = 4, NSMALL = 2;
+};
+template <> struct WalkLds<2> {
+    static constexpr int LEN = 256, STRIDE = 272, CLEN = 128, NBIG = 8, NSMALL = 4;
+};
 template <int NW>
-__device__ __forceinline__ typename MaskOf<NW>::type plane(const int (&C)[NW], int p) {
-    const uint64_t lo = ballot(((C[0] >> p) & 1) != 0);
-    uint64_t hi = 0ull;
-    if constexpr (NW == 2) hi = ballot(((C[1] >> p) & 1) != 0);
-    return make_mask<NW>(lo, hi);
-}
-
-// Number q of planes needed: every C_k lies in [-2^(q-1), 2^(q-1)), so the
-// offset values C_k + 2^(q-1) are q-bit unsigned numbers.
-template <int NW>
-__device__ __forceinline__ int planes_needed(const int (&C)[NW]) {
-    int x = C[0] ^ (C[0] >> 31);
-    if constexpr (NW == 2) x |= C[1] ^ (C[1] >> 31);
-    const int o = wave_or(x);
-    return o == 0 ? 1 : 33 - __clz(o);
+constexpr int walk_lds_bytes() {
+    return 2 * 16 * WalkLds<NW>::STRIDE + WalkLds<NW>::CLEN;
 }
 
 // Lane l receives bit l of a wave-uniform 64-bit mask.
@@ -350,19 +296,47 @@ __device__ __forceinline__ bool lane_bit(uint64_t mask) {
     return __builtin_amdgcn_inverse_ballot_w64(mask);
 }
 
+// Four bytes P[x..x+3] of a sequence given as a mask (bit set <=> -1):
+// 0x01 for +1, 0xFF for -1, 0 past the end.
+template <typename Mask>
+__device__ __forceinline__ uint32_t pack4(Mask M, int x, int N) {
+    if (x >= N) return 0u;
+    const uint32_t nib = (uint32_t)mask_lo(m_shr(M, x)) & 0xFu;
+    const int cnt = min(N - x, 4);
+    const uint32_t valid = cnt >= 4 ? 0x01010101u : (0x01010101u & ((1u << (8 * cnt)) - 1u));
+    const uint32_t ones = (nib * 0x00204081u) & 0x01010101u;  // bit b -> byte b
+    return valid | (ones * 0xFEu);
+}
+
+__device__ __forceinline__ int dot16(const uint4 a, const uint4 b, int acc) {
+    acc = __builtin_amdgcn_sdot4((int)a.x, (int)b.x, acc, false);
+    acc = __builtin_amdgcn_sdot4((int)a.y, (int)b.y, acc, false);
+    acc = __builtin_amdgcn_sdot4((int)a.z, (int)b.z, acc, false);
+    return __builtin_amdgcn_sdot4((int)a.w, (int)b.w, acc, false);
+}
+
 // Runs one walk of sch.T steps from mask M0 (bits >= N must be clear).
-//   ps     per-wavefront LDS scratch of 129 ints (prefix sums of C)
-//   trace  optional: trace[t-1] = flipped index (written by lane 0)
+//   lds    per-wavefront LDS scratch of walk_lds_bytes<NW>() bytes, 16-aligned
+//   trace  optional: trace[t-1] = flipped index
 // Every lane of the wavefront must call this with identical uniform inputs.
 template <int NW>
-__device__ __forceinline__ WalkResult<NW> tabu_walk(const int N, const typename MaskOf<NW>::type M0,
-                                    const Schedule sch, const int aspiration,
-                                    const uint32_t k0, const uint32_t k1,
-                                    const uint32_t entity, const uint32_t gen,
-                                    int *__restrict__ ps, int16_t *__restrict__ trace) {
+__device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typename MaskOf<NW>::type M0,
+                                                    const Schedule sch_in, const int aspiration_in,
+                                                    const uint32_t k0, const uint32_t k1,
+                                                    const uint32_t entity, const uint32_t gen,
+                                                    uint8_t *__restrict__ lds,
+                                                    int16_t *__restrict__ trace) {
     using Mask = typename MaskOf<NW>::type;
-    using Small = typename SmallOf<NW>::type;
+    using Cfg = WalkLds<NW>;
     const int lane = lane_id();
+    // Wave-uniform parameters, pinned to scalar registers so that the step
+    // loop is controlled by scalar branches.
+    const int N = __builtin_amdgcn_readfirstlane(N_in);
+    const int aspiration = __builtin_amdgcn_readfirstlane(aspiration_in);
+    Schedule sch;
+    sch.T = __builtin_amdgcn_readfirstlane(sch_in.T);
+    sch.lo = __builtin_amdgcn_readfirstlane(sch_in.lo);
+    sch.hi = __builtin_amdgcn_readfirstlane(sch_in.hi);
     // The sequence is wave-uniform; pinning it to scalar registers keeps the
     // per-move mask arithmetic on the scalar unit.
     Mask M = make_mask<NW>(uniform64(mask_lo(M0)), uniform64(mask_hi(M0)));
@@ -376,7 +350,20 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N, const typename 
         Mr = make_mask<NW>(lo, hi);
     }
 
-    // C_k for the lags this lane owns (Eq. 1) and the energy (Eq. 2).
+    uint8_t *const PW = lds;
+    uint8_t *const QW = lds + 16 * Cfg::STRIDE;
+    int8_t *const CB = (int8_t *)(lds + 32 * Cfg::STRIDE);
+
+    // Fill the shifted copies (dword d of copy c holds P[4d + c .. 4d + c + 3]).
+    wave_sync();
+    for (int idx = lane; idx < 16 * (Cfg::LEN / 4); idx += 64) {
+        const int c = idx / (Cfg::LEN / 4), d = idx % (Cfg::LEN / 4);
+        const int x = 4 * d + c;
+        ((uint32_t *)(PW + c * Cfg::STRIDE))[d] = pack4(M, x, N);
+        ((uint32_t *)(QW + c * Cfg::STRIDE))[d] = pack4(Mr, x, N);
+    }
+
+    // C_k for the lags this lane owns (Eq. 1), its int8 mirror, the energy.
     int C[NW];
     int sq = 0;
 #pragma unroll
@@ -384,16 +371,32 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N, const typename 
         const int k = lane + 1 + 64 * w;
         C[w] = k < N ? lag_corr(M, N, k) : 0;
         sq += C[w] * C[w];
+        CB[lane + 64 * w] = (int8_t)C[w];
     }
     int E = wave_sum(sq);
+
+    // Per-lane window addresses (fixed for the walk).  Neighbour j's right
+    // window starts at P[j+1], its left window at Q[N-j]; the longer of the
+    // two is read over all lags, the shorter over the first half.
+    const uint8_t *big[NW];
+    const uint8_t *small[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const int j = lane + 64 * w;
+        const int xr = j + 1;
+        const int xl = j < N ? N - j : 0;
+        const uint8_t *right = PW + (xr & 15) * Cfg::STRIDE + (xr & ~15);
+        const uint8_t *left = QW + (xl & 15) * Cfg::STRIDE + (xl & ~15);
+        const bool right_big = N - 1 - j >= j;
+        big[w] = right_big ? right : left;
+        small[w] = right_big ? left : right;
+    }
 
     int tabu[NW];
 #pragma unroll
     for (int w = 0; w < NW; ++w) tabu[w] = 0;
     Mask best = M;
     int bestE = E;
-
-    ps[0] = 0;  // every lane stores the same value
     uint32_t dr0 = 0u, dr1 = 0u;
 
     for (int t = 1; t <= sch.T; ++t) {
@@ -404,72 +407,38 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N, const typename 
             dr0 = d.w0;
             dr1 = d.w1;
         }
+        wave_sync();  // the previous move's LDS writes are visible
 
-        // Prefix sums PS(x) = sum_{k<=x} C_k, x = 0..N-1, into LDS.
-        wave_sync();
-        {
-            const int s0 = wave_scan(C[0]);
-            ps[1 + lane] = s0;
-            if constexpr (NW == 2) {
-                const int s1 = wave_scan(C[1]) + readlane(s0, 63);
-                ps[65 + lane] = s1;
-            }
-        }
-        wave_sync();
+        uint4 cc[Cfg::NBIG];  // C_1 .. C_{16 NBIG} (wave-uniform)
+#pragma unroll
+        for (int r = 0; r < Cfg::NBIG; ++r) cc[r] = ((const uint4 *)CB)[r];
 
-        // Score the neighbours this lane owns.  Neighbour j's right window
-        // has N-1-j meaningful bits and its left window j; the longer one
-        // ("big") needs the full mask width, the shorter ("small") at most
-        // half of it, so each plane costs 3 (N <= 64) or 6 (N <= 128) words.
-        // Lanes past the sequence compute on empty windows and are masked
-        // out at the end, so the loop has no lane-dependent branch.
-        Mask big[NW];
-        Small small[NW];
-        int bs[NW];
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            const int j = lane + 64 * w;
-            const bool in = j < N;
-            const Mask R = m_shr(M, j + 1);                  // bit k-1: s_{j+k} = -1
-            const Mask L = m_shr(Mr, in ? N - j : 64 * NW);  // bit k-1: s_{j-k} = -1
-            const bool right_big = N - 1 - j >= j;
-            big[w] = right_big ? R : L;
-            small[w] = low_half(right_big ? L : R);
-            bs[w] = 0;
-        }
-        // Offset-binary planes: with D_k = C_k + 2^(q-1) in [0, 2^q),
-        // sum_k x_k C_k = sum_p 2^p popc(x & plane_p(D)) - 2^(q-1) popc(x).
-        const int q = planes_needed<NW>(C);
-        const int off = 1 << (q - 1);
-        int D[NW];
-#pragma unroll
-        for (int w = 0; w < NW; ++w) D[w] = C[w] + off;
-#pragma unroll
-        for (int p = 7; p >= 0; --p) {  // Horner: bs = 2 bs + count_p
-            if (p < q) {
-                const Mask P = plane<NW>(D, p);
-#pragma unroll
-                for (int w = 0; w < NW; ++w) bs[w] = plane_count(big[w], small[w], P, 2 * bs[w]);
-            }
-        }
-#pragma unroll
-        for (int w = 0; w < NW; ++w)  // bs = sum_k (bR_k + bL_k) C_k
-            bs[w] -= off * (m_popc(big[w]) + s_popc(small[w]));
+        // Score the neighbours this lane owns.
         int key[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             const int j = lane + 64 * w;
-            const bool in = j < N;
-            const int nb = in ? min(N - 1 - j, j) : 0;  // lags with both sides inside
-            const int u = nb - 2 * s_popc((low_half(big[w]) ^ small[w]) & s_low(small[w], nb));
-            const int v = ps[in ? N - 1 - j : 0] + ps[in ? j : 0] - 2 * bs[w];
-            const int sj = 1 - 2 * m_bit(M, in ? j : 0);
-            const int cand = E + 4 * (N - 1 + 2 * u - sj * v);
+            int v = 0;  // sum_k t_jk C_k
+            int u = 0;  // sum_k s_{j+k} s_{j-k}
+#pragma unroll
+            for (int r = 0; r < Cfg::NBIG; ++r) {
+                const uint4 b = ((const uint4 *)big[w])[r];
+                v = dot16(b, cc[r], v);
+                if (r < Cfg::NSMALL) {
+                    const uint4 sm4 = ((const uint4 *)small[w])[r];
+                    v = dot16(sm4, cc[r], v);
+                    u = dot16(b, sm4, u);
+                }
+            }
+            const uint64_t mw = w == 0 ? mask_lo(M) : mask_hi(M);
+            const int sv = lane_bit(mw) ? -v : v;  // s_j * v
+            const int cand = E + 4 * (N - 1 + 2 * u - sv);
             const bool admissible = tabu[w] < t || (aspiration && cand < bestE);
-            key[w] = in && admissible ? cand : INT_MAX;
+            key[w] = j < N && admissible ? cand : INT_MAX;
         }
 
-        // Admissible minimum, ties broken by the step's draw.
+        // Admissible minimum, ties broken by the step's draw: the r-th
+        // (ascending) of the tied moves, r = (u0 * count) >> 32.
         int kmin = key[0];
         if constexpr (NW == 2) kmin = min(kmin, key[1]);
         const int m = wave_min(kmin);
@@ -477,25 +446,26 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N, const typename 
         uint64_t T1 = 0ull;
         if constexpr (NW == 2) T1 = ballot(key[1] == m);
         const int c0 = __popcll(T0);
-        const int c = c0 + __popcll(T1);
         const uint32_t u0 = readlane_u(dr0, slot);
         const uint32_t u1 = readlane_u(dr1, slot);
-        int r = (int)below(u0, (uint32_t)c);
-        int pick;
-        if (r < c0) {
-            const uint64_t sel = ballot(lane_bit(T0) && rank_below(T0) == r);
-            pick = __builtin_ctzll(sel);
-        } else {
-            r -= c0;
-            const uint64_t sel = ballot(lane_bit(T1) && rank_below(T1) == r);
-            pick = 64 + __builtin_ctzll(sel);
+        int r = (int)below(u0, (uint32_t)(c0 + __popcll(T1)));
+        uint64_t tied = T0;
+        int pick_base = 0;
+        if constexpr (NW == 2) {
+            if (r >= c0) {
+                tied = T1;
+                pick_base = 64;
+                r -= c0;
+            }
         }
+        for (int i = 0; i < r; ++i) tied &= tied - 1ull;  // drop the r lowest
+        const int pick = pick_base + __builtin_ctzll(tied);
 
         // Apply the move: tenure, sequence, energy, best.
         const int tenure = sch.lo + (int)below(u1, (uint32_t)(sch.hi - sch.lo + 1));
-        tabu[0] = pick == lane ? t + tenure : tabu[0];
-        if constexpr (NW == 2) tabu[1] = pick == lane + 64 ? t + tenure : tabu[1];
-        const int sm = 1 - 2 * m_bit(M, pick);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) tabu[w] = pick == lane + 64 * w ? t + tenure : tabu[w];
+        const int sm = 1 - 2 * m_bit(M, pick);  // old s_pick
         M = m_xor(M, m_onebit(M, pick));
         Mr = m_xor(Mr, m_onebit(Mr, N - 1 - pick));
         E = m;
@@ -504,6 +474,15 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N, const typename 
             best = M;
         }
         if (trace != nullptr) trace[t - 1] = (int16_t)pick;  // uniform store
+
+        // New s_pick into every copy: P[pick] sits at byte pick - c of copy c
+        // (lanes 0..15), Q[N-1-pick] at byte N-1-pick-c (lanes 16..31).
+        {
+            const int c = lane & 15;
+            const int pos = (lane < 16 ? pick : N - 1 - pick) - c;
+            uint8_t *base = (lane < 16 ? PW : QW) + c * Cfg::STRIDE;
+            if (lane < 32 && pos >= 0) base[pos] = (uint8_t)(int8_t)(-sm);
+        }
 
         // C_k -= 2 s_pick t_pick,k for every lag (lane-parallel).  The
         // windows of the flipped index are wave-uniform: lag k (bit k-1) of
@@ -524,6 +503,7 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N, const typename 
                 const int sa = lane_bit(rn) ? -1 : (lane_bit(rp) ? 1 : 0);
                 const int sb = lane_bit(ln) ? -1 : (lane_bit(lp) ? 1 : 0);
                 C[w] += k2 * (sa + sb);
+                CB[lane + 64 * w] = (int8_t)C[w];
             }
         }
     }

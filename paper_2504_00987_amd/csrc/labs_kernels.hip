@@ -16,7 +16,6 @@ namespace liblabs {
 
 namespace {
 
-constexpr int kPsInts = 132;  // prefix-sum scratch per wave (needs 129)
 constexpr int kMaxK = 128;
 
 // ---------------------------------------------------------------------------
@@ -54,7 +53,7 @@ __global__ __launch_bounds__(64 * WPG) void energy_kernel(const int8_t *__restri
 // Batched tabu walks.
 // ---------------------------------------------------------------------------
 template <int NW>
-__device__ void run_tabu_item(const TabuLaunchArgs &a, int64_t w, int N, int *ps) {
+__device__ void run_tabu_item(const TabuLaunchArgs &a, int64_t w, int N, uint8_t *lds) {
     using Mask = typename MaskOf<NW>::type;
     const int lane = lane_id();
     uint64_t lo, hi;
@@ -80,7 +79,7 @@ __device__ void run_tabu_item(const TabuLaunchArgs &a, int64_t w, int N, int *ps
     const Schedule sch = make_schedule(a.rule, N, a.k0, a.k1, (uint32_t)w, 0u);
     int16_t *tr = a.trace ? a.trace + w * (int64_t)a.trace_stride : nullptr;
     const WalkResult<NW> r = tabu_walk<NW>(N, M, sch, a.rule.aspiration, a.k0, a.k1,
-                                           (uint32_t)w, 0u, ps, tr);
+                                           (uint32_t)w, 0u, lds, tr);
     int8_t *out = a.best_seq + w * (int64_t)a.out_stride;
     for (int i = lane; i < a.out_stride; i += 64)
         out[i] = i < N ? (m_bit(r.best, i) ? (int8_t)-1 : (int8_t)1) : (int8_t)0;
@@ -106,20 +105,20 @@ __device__ __forceinline__ uint32_t next_work(uint32_t *counter) {
 template <int NW, int WPG, bool PERSIST>
 __global__ __launch_bounds__(64 * WPG) void tabu_kernel(TabuLaunchArgs a, int64_t begin,
                                                         int64_t end) {
-    __shared__ int ps_all[WPG][kPsInts];
+    __shared__ __attribute__((aligned(16))) uint8_t lds_all[WPG][walk_lds_bytes<NW>()];
     const int wave = threadIdx.x >> 6;
-    int *ps = ps_all[wave];
+    uint8_t *lds = lds_all[wave];
     if constexpr (PERSIST) {
         for (int64_t pos = begin + next_work(a.counter); pos < end;
              pos = begin + next_work(a.counter)) {
             const int64_t w = a.order ? (int64_t)a.order[pos] : pos;
-            run_tabu_item<NW>(a, w, a.ns ? a.ns[w] : a.n_uniform, ps);
+            run_tabu_item<NW>(a, w, a.ns ? a.ns[w] : a.n_uniform, lds);
         }
     } else {
         const int64_t pos = begin + (int64_t)blockIdx.x * WPG + wave;
         if (pos < end) {
             const int64_t w = a.order ? (int64_t)a.order[pos] : pos;
-            run_tabu_item<NW>(a, w, a.ns ? a.ns[w] : a.n_uniform, ps);
+            run_tabu_item<NW>(a, w, a.ns ? a.ns[w] : a.n_uniform, lds);
         }
     }
 }
@@ -182,7 +181,7 @@ __global__ __launch_bounds__(64) void memetic_init_kernel(MemeticLaunchArgs a) {
 
 template <int NW>
 __device__ void memetic_replica(const MemeticLaunchArgs &a, const MemeticSlot &sl,
-                                uint64_t (*pop)[2], int *popE, int *ps) {
+                                uint64_t (*pop)[2], int *popE, uint8_t *lds) {
     using Mask = typename MaskOf<NW>::type;
     const int lane = lane_id();
     const int N = sl.n, K = a.K, st = sl.state;
@@ -241,7 +240,7 @@ __device__ void memetic_replica(const MemeticLaunchArgs &a, const MemeticSlot &s
         child = m_xor(child, make_mask<NW>(flo, fhi));
         const Schedule sch = make_schedule(a.rule, N, sl.k0, sl.k1, sl.pop_id, gg);
         const WalkResult<NW> r = tabu_walk<NW>(N, child, sch, a.rule.aspiration, sl.k0, sl.k1,
-                                               sl.pop_id, gg, ps, nullptr);
+                                               sl.pop_id, gg, lds, nullptr);
         if (r.best_e < bestE) {
             bestE = r.best_e;
             best = r.best;
@@ -278,12 +277,12 @@ template <int NW>
 __global__ __launch_bounds__(64) void memetic_advance_kernel(MemeticLaunchArgs a) {
     __shared__ uint64_t pop[kMaxK][2];
     __shared__ int popE[kMaxK];
-    __shared__ int ps[kPsInts];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[walk_lds_bytes<NW>()];
     const int s = blockIdx.x;
     if (s >= a.n_slots) return;
     const MemeticSlot sl = a.slots[s];
     if (sl.state < 0 || (sl.n > 64) != (NW == 2)) return;
-    memetic_replica<NW>(a, sl, pop, popE, ps);
+    memetic_replica<NW>(a, sl, pop, popE, lds);
 }
 
 __global__ void gather_best_kernel(MemeticStateDev st, const int32_t *__restrict__ state_idx,
