@@ -317,9 +317,9 @@ __device__ __forceinline__ int dot16(const uint4 a, const uint4 b, int acc) {
 
 // Runs one walk of sch.T steps from mask M0 (bits >= N must be clear).
 //   lds    per-wavefront LDS scratch of walk_lds_bytes<NW>() bytes, 16-aligned
-//   trace  optional: trace[t-1] = flipped index
+//   trace  with TRACE: trace[t-1] = flipped index
 // Every lane of the wavefront must call this with identical uniform inputs.
-template <int NW>
+template <int NW, bool TRACE = false>
 __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typename MaskOf<NW>::type M0,
                                                     const Schedule sch_in, const int aspiration_in,
                                                     const uint32_t k0, const uint32_t k1,
@@ -399,6 +399,24 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
     int bestE = E;
     uint32_t dr0 = 0u, dr1 = 0u;
 
+    // Window chunks of the current pivot.  With one neighbour per lane they
+    // are requested one step ahead, right after the move's byte update; with
+    // two, at the top of each step (the registers for early loads would cost
+    // occupancy).
+    constexpr bool kPipelineWindows = NW == 1;
+    uint4 wb[NW][Cfg::NBIG];
+    uint4 ws[NW][Cfg::NSMALL];
+    if constexpr (kPipelineWindows) {
+        wave_sync();
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+#pragma unroll
+            for (int r = 0; r < Cfg::NBIG; ++r) wb[w][r] = ((const uint4 *)big[w])[r];
+#pragma unroll
+            for (int r = 0; r < Cfg::NSMALL; ++r) ws[w][r] = ((const uint4 *)small[w])[r];
+        }
+    }
+
     for (int t = 1; t <= sch.T; ++t) {
         const int slot = (t - 1) & 63;
         if (slot == 0) {
@@ -407,29 +425,40 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
             dr0 = d.w0;
             dr1 = d.w1;
         }
-        wave_sync();  // the previous move's LDS writes are visible
+        wave_sync();  // the previous move's C bytes are visible
+        if constexpr (!kPipelineWindows) {
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+#pragma unroll
+                for (int r = 0; r < Cfg::NBIG; ++r) wb[w][r] = ((const uint4 *)big[w])[r];
+#pragma unroll
+                for (int r = 0; r < Cfg::NSMALL; ++r) ws[w][r] = ((const uint4 *)small[w])[r];
+            }
+        }
 
         uint4 cc[Cfg::NBIG];  // C_1 .. C_{16 NBIG} (wave-uniform)
 #pragma unroll
         for (int r = 0; r < Cfg::NBIG; ++r) cc[r] = ((const uint4 *)CB)[r];
 
-        // Score the neighbours this lane owns.
+        // Score the neighbours this lane owns (independent accumulators).
         int key[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             const int j = lane + 64 * w;
-            int v = 0;  // sum_k t_jk C_k
-            int u = 0;  // sum_k s_{j+k} s_{j-k}
+            int vb0 = 0, vb1 = 0, vs = 0;  // sum_k t_jk C_k, split
+            int u = 0;                     // sum_k s_{j+k} s_{j-k}
 #pragma unroll
             for (int r = 0; r < Cfg::NBIG; ++r) {
-                const uint4 b = ((const uint4 *)big[w])[r];
-                v = dot16(b, cc[r], v);
+                if (r & 1)
+                    vb1 = dot16(wb[w][r], cc[r], vb1);
+                else
+                    vb0 = dot16(wb[w][r], cc[r], vb0);
                 if (r < Cfg::NSMALL) {
-                    const uint4 sm4 = ((const uint4 *)small[w])[r];
-                    v = dot16(sm4, cc[r], v);
-                    u = dot16(b, sm4, u);
+                    vs = dot16(ws[w][r], cc[r], vs);
+                    u = dot16(wb[w][r], ws[w][r], u);
                 }
             }
+            const int v = vb0 + vb1 + vs;
             const uint64_t mw = w == 0 ? mask_lo(M) : mask_hi(M);
             const int sv = lane_bit(mw) ? -v : v;  // s_j * v
             const int cand = E + 4 * (N - 1 + 2 * u - sv);
@@ -467,42 +496,44 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
         for (int w = 0; w < NW; ++w) tabu[w] = pick == lane + 64 * w ? t + tenure : tabu[w];
         const int sm = 1 - 2 * m_bit(M, pick);  // old s_pick
         M = m_xor(M, m_onebit(M, pick));
-        Mr = m_xor(Mr, m_onebit(Mr, N - 1 - pick));
         E = m;
         if (E < bestE) {
             bestE = E;
             best = M;
         }
-        if (trace != nullptr) trace[t - 1] = (int16_t)pick;  // uniform store
+        if constexpr (TRACE) trace[t - 1] = (int16_t)pick;  // uniform store
 
         // New s_pick into every copy: P[pick] sits at byte pick - c of copy c
-        // (lanes 0..15), Q[N-1-pick] at byte N-1-pick-c (lanes 16..31).
+        // (lanes 0..15), Q[N-1-pick] at byte N-1-pick-c (lanes 16..31); then
+        // the next step's window chunks are requested at once.
         {
             const int c = lane & 15;
             const int pos = (lane < 16 ? pick : N - 1 - pick) - c;
             uint8_t *base = (lane < 16 ? PW : QW) + c * Cfg::STRIDE;
             if (lane < 32 && pos >= 0) base[pos] = (uint8_t)(int8_t)(-sm);
         }
+        if constexpr (kPipelineWindows) {
+            wave_sync();
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+#pragma unroll
+                for (int r = 0; r < Cfg::NBIG; ++r) wb[w][r] = ((const uint4 *)big[w])[r];
+#pragma unroll
+                for (int r = 0; r < Cfg::NSMALL; ++r) ws[w][r] = ((const uint4 *)small[w])[r];
+            }
+        }
 
-        // C_k -= 2 s_pick t_pick,k for every lag (lane-parallel).  The
-        // windows of the flipped index are wave-uniform: lag k (bit k-1) of
-        // Rn / Ln says s_{pick+k} / s_{pick-k} = -1, of Rp / Lp that it is +1
-        // (both clear past the ends, so lags >= N keep C_k = 0).
+        // C_k -= 2 s_pick t_pick,k for every lag (lane-parallel):
+        // s_{pick+k} = P[pick+k] and s_{pick-k} = Q[N-1-pick+k] are bytes of
+        // copy 0, zero past the ends (position pick itself is not read).
         {
-            const Mask Rn = m_shr(M, pick + 1);
-            const Mask Ln = m_shr(Mr, N - pick);
-            const Mask Rp = m_and(m_low(M, N - 1 - pick), m_not(Rn));
-            const Mask Lp = m_and(m_low(M, pick), m_not(Ln));
             const int k2 = -2 * sm;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
-                const uint64_t rn = w == 0 ? mask_lo(Rn) : mask_hi(Rn);
-                const uint64_t ln = w == 0 ? mask_lo(Ln) : mask_hi(Ln);
-                const uint64_t rp = w == 0 ? mask_lo(Rp) : mask_hi(Rp);
-                const uint64_t lp = w == 0 ? mask_lo(Lp) : mask_hi(Lp);
-                const int sa = lane_bit(rn) ? -1 : (lane_bit(rp) ? 1 : 0);
-                const int sb = lane_bit(ln) ? -1 : (lane_bit(lp) ? 1 : 0);
-                C[w] += k2 * (sa + sb);
+                const int k = lane + 1 + 64 * w;
+                const int t_k = (int)((const int8_t *)PW)[pick + k] +
+                                (int)((const int8_t *)QW)[N - 1 - pick + k];
+                C[w] += k2 * t_k;
                 CB[lane + 64 * w] = (int8_t)C[w];
             }
         }

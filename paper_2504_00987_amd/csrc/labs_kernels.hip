@@ -77,9 +77,13 @@ __device__ void run_tabu_item(const TabuLaunchArgs &a, int64_t w, int N, uint8_t
     }
     const Mask M = make_mask<NW>(lo, hi);
     const Schedule sch = make_schedule(a.rule, N, a.k0, a.k1, (uint32_t)w, 0u);
-    int16_t *tr = a.trace ? a.trace + w * (int64_t)a.trace_stride : nullptr;
-    const WalkResult<NW> r = tabu_walk<NW>(N, M, sch, a.rule.aspiration, a.k0, a.k1,
-                                           (uint32_t)w, 0u, lds, tr);
+    WalkResult<NW> r;
+    if (a.trace != nullptr)
+        r = tabu_walk<NW, true>(N, M, sch, a.rule.aspiration, a.k0, a.k1, (uint32_t)w, 0u, lds,
+                                a.trace + w * (int64_t)a.trace_stride);
+    else
+        r = tabu_walk<NW, false>(N, M, sch, a.rule.aspiration, a.k0, a.k1, (uint32_t)w, 0u, lds,
+                                 nullptr);
     int8_t *out = a.best_seq + w * (int64_t)a.out_stride;
     for (int i = lane; i < a.out_stride; i += 64)
         out[i] = i < N ? (m_bit(r.best, i) ? (int8_t)-1 : (int8_t)1) : (int8_t)0;
