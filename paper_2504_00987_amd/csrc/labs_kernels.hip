@@ -52,7 +52,7 @@ __global__ __launch_bounds__(64 * WPG) void energy_kernel(const int8_t *__restri
 // ---------------------------------------------------------------------------
 // Batched tabu walks.
 // ---------------------------------------------------------------------------
-template <int NW>
+template <int NW, bool TRACE>
 __device__ void run_tabu_item(const TabuLaunchArgs &a, int64_t w, int N, uint8_t *lds) {
     using Mask = typename MaskOf<NW>::type;
     const int lane = lane_id();
@@ -77,13 +77,9 @@ __device__ void run_tabu_item(const TabuLaunchArgs &a, int64_t w, int N, uint8_t
     }
     const Mask M = make_mask<NW>(lo, hi);
     const Schedule sch = make_schedule(a.rule, N, a.k0, a.k1, (uint32_t)w, 0u);
-    WalkResult<NW> r;
-    if (a.trace != nullptr)
-        r = tabu_walk<NW, true>(N, M, sch, a.rule.aspiration, a.k0, a.k1, (uint32_t)w, 0u, lds,
-                                a.trace + w * (int64_t)a.trace_stride);
-    else
-        r = tabu_walk<NW, false>(N, M, sch, a.rule.aspiration, a.k0, a.k1, (uint32_t)w, 0u, lds,
-                                 nullptr);
+    const WalkResult<NW> r =
+        tabu_walk<NW, TRACE>(N, M, sch, a.rule.aspiration, a.k0, a.k1, (uint32_t)w, 0u, lds,
+                             TRACE ? a.trace + w * (int64_t)a.trace_stride : nullptr);
     int8_t *out = a.best_seq + w * (int64_t)a.out_stride;
     for (int i = lane; i < a.out_stride; i += 64)
         out[i] = i < N ? (m_bit(r.best, i) ? (int8_t)-1 : (int8_t)1) : (int8_t)0;
@@ -105,8 +101,10 @@ __device__ __forceinline__ uint32_t next_work(uint32_t *counter) {
 // Walks at positions [begin, end) of the processing order, all with
 // N <= 64 (NW = 1) or all with 64 < N <= 128 (NW = 2).  PERSIST: a grid
 // sized to the device drains the range through the queue head `counter`;
-// otherwise one wave per position.
-template <int NW, int WPG, bool PERSIST>
+// otherwise one wave per position.  TRACE: record every walk's moves (a
+// separate instantiation, so that the untraced kernel does not carry the
+// registers of the traced one).
+template <int NW, int WPG, bool PERSIST, bool TRACE>
 __global__ __launch_bounds__(64 * WPG) void tabu_kernel(TabuLaunchArgs a, int64_t begin,
                                                         int64_t end) {
     __shared__ __attribute__((aligned(16))) uint8_t lds_all[WPG][walk_lds_bytes<NW>()];
@@ -116,13 +114,13 @@ __global__ __launch_bounds__(64 * WPG) void tabu_kernel(TabuLaunchArgs a, int64_
         for (int64_t pos = begin + next_work(a.counter); pos < end;
              pos = begin + next_work(a.counter)) {
             const int64_t w = a.order ? (int64_t)a.order[pos] : pos;
-            run_tabu_item<NW>(a, w, a.ns ? a.ns[w] : a.n_uniform, lds);
+            run_tabu_item<NW, TRACE>(a, w, a.ns ? a.ns[w] : a.n_uniform, lds);
         }
     } else {
         const int64_t pos = begin + (int64_t)blockIdx.x * WPG + wave;
         if (pos < end) {
             const int64_t w = a.order ? (int64_t)a.order[pos] : pos;
-            run_tabu_item<NW>(a, w, a.ns ? a.ns[w] : a.n_uniform, lds);
+            run_tabu_item<NW, TRACE>(a, w, a.ns ? a.ns[w] : a.n_uniform, lds);
         }
     }
 }
@@ -328,22 +326,30 @@ hipError_t launch_energy(const int8_t *seqs, const int32_t *ns, int32_t n_unifor
 
 namespace {
 
-template <int NW, int WPG>
-hipError_t launch_tabu_part(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
-                            hipStream_t s) {
-    if (end <= begin) return hipSuccess;
+template <int NW, int WPG, bool TRACE>
+hipError_t launch_tabu_part_t(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
+                              hipStream_t s) {
     if (groups > 0) {
         hipError_t e = launch_fill_u32(a.counter, 0u, 1, s);
         if (e != hipSuccess) return e;
         const int64_t need = (end - begin + WPG - 1) / WPG;
-        hipLaunchKernelGGL((tabu_kernel<NW, WPG, true>), dim3((unsigned)std::min<int64_t>(groups, need)),
-                           dim3(64 * WPG), 0, s, a, begin, end);
+        hipLaunchKernelGGL((tabu_kernel<NW, WPG, true, TRACE>),
+                           dim3((unsigned)std::min<int64_t>(groups, need)), dim3(64 * WPG), 0, s, a,
+                           begin, end);
     } else {
         const int64_t grid = (end - begin + WPG - 1) / WPG;
-        hipLaunchKernelGGL((tabu_kernel<NW, WPG, false>), dim3((unsigned)grid), dim3(64 * WPG), 0,
-                           s, a, begin, end);
+        hipLaunchKernelGGL((tabu_kernel<NW, WPG, false, TRACE>), dim3((unsigned)grid),
+                           dim3(64 * WPG), 0, s, a, begin, end);
     }
     return hipGetLastError();
+}
+
+template <int NW, int WPG>
+hipError_t launch_tabu_part(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
+                            hipStream_t s) {
+    if (end <= begin) return hipSuccess;
+    return a.trace != nullptr ? launch_tabu_part_t<NW, WPG, true>(a, begin, end, groups, s)
+                              : launch_tabu_part_t<NW, WPG, false>(a, begin, end, groups, s);
 }
 
 template <int WPG>
