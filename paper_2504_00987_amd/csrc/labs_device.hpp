@@ -11,16 +11,16 @@
 //
 // (flipping s_j changes C_k of Eq. 1 by -2 s_j t_jk).  The sequence lives in
 // LDS twice as int8 +-1 with zeros past its ends -- forwards (P) and reversed
-// (Q) -- in 16 copies shifted by one byte each, so that every lane's right
-// window s_{j+1..} and left window s_{j-1..} (reversed) start on a 16-byte
-// boundary of some copy.  C_k is kept per lane in registers and mirrored in
+// (Q) -- as 16-byte records, record x holding bytes x .. x+15, so that every
+// lane's right window s_{j+1..} and left window s_{j-1..} (reversed) is a
+// run of aligned 16-byte reads.  C_k is kept per lane in registers and mirrored in
 // LDS as int8 (|C_k| <= N-k <= 127).  A neighbour's sums are then packed
 // 4-way int8 dot products of 16-byte window chunks against C chunks:
 // sum_k t_jk C_k = <right, C> + <left, C>, sum_k s_{j+k} s_{j-k} =
 // <right, left> over the shorter window.  Each neighbour reads its longer
 // window over the full lag range and its shorter one over half of it.  After
 // a move, C_k is updated lane-parallel (the paper's O(N) update of one "row
-// and column", Sec. III.C) and one byte per copy is rewritten.  All
+// and column", Sec. III.C) and one byte per record is rewritten.  All
 // arithmetic is exact int32.
 #pragma once
 
@@ -273,22 +273,31 @@ struct WalkResult {
     int final_e;
 };
 
-// LDS layout of one walk: P copies, Q copies, C bytes.
-//   copy c of P holds P[i + c] at byte i, P[x] = s_x (x < N), 0 otherwise;
-//   Q is the reversed sequence, Q[x] = s_{N-1-x};
+// LDS layout of one walk: P records, Q records (each run preceded by 15
+// spare records, so that the byte update after a move needs no bounds
+// test), plain P, plain Q, C bytes.
+//   P[x] = s_x for x < N, 0 otherwise; Q is the reversed sequence,
+//   Q[x] = s_{N-1-x} for x < N, 0 otherwise;
+//   record x (16 bytes, at 16 x) holds P[x .. x+15], so a window starting
+//   at any x is the records x, x+16, x+32, ...; lanes that read
+//   consecutive starts touch consecutive 16-byte slots (no bank conflicts);
+//   the plain copies hold P[0 .. LEN) and Q[0 .. LEN) for the C update;
 //   CB[k-1] = C_k as int8.
-// LEN covers the farthest byte a window reads; STRIDE is an odd multiple of
-// 16 so that the copies start in different LDS banks.
+// NREC covers the farthest record a window reads (start <= 64 NW, plus
+// NBIG - 1 chunks); LEN the farthest byte the C update reads.
 template <int NW> struct WalkLds;
 template <> struct WalkLds<1> {
-    static constexpr int LEN = 128, STRIDE = 144, CLEN = 64, NBIG = 4, NSMALL = 2;
+    static constexpr int NBIG = 4, NSMALL = 2, LEN = 128, CLEN = 64;
+    static constexpr int NREC = 64 + 16 * (NBIG - 1) + 1;
 };
 template <> struct WalkLds<2> {
-    static constexpr int LEN = 256, STRIDE = 272, CLEN = 128, NBIG = 8, NSMALL = 4;
+    static constexpr int NBIG = 8, NSMALL = 4, LEN = 256, CLEN = 128;
+    static constexpr int NREC = 128 + 16 * (NBIG - 1) + 1;
 };
+constexpr int kSpareRecords = 15;
 template <int NW>
 constexpr int walk_lds_bytes() {
-    return 2 * 16 * WalkLds<NW>::STRIDE + WalkLds<NW>::CLEN;
+    return 2 * 16 * (kSpareRecords + WalkLds<NW>::NREC) + 2 * WalkLds<NW>::LEN + WalkLds<NW>::CLEN;
 }
 
 // Lane l receives bit l of a wave-uniform 64-bit mask.
@@ -350,17 +359,24 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
         Mr = make_mask<NW>(lo, hi);
     }
 
-    uint8_t *const PW = lds;
-    uint8_t *const QW = lds + 16 * Cfg::STRIDE;
-    int8_t *const CB = (int8_t *)(lds + 32 * Cfg::STRIDE);
+    constexpr int kRunBytes = 16 * (kSpareRecords + Cfg::NREC);
+    uint8_t *const RP = lds + 16 * kSpareRecords;
+    uint8_t *const RQ = RP + kRunBytes;
+    uint8_t *const PP = RP - 16 * kSpareRecords + 2 * kRunBytes;
+    uint8_t *const PQ = PP + Cfg::LEN;
+    int8_t *const CB = (int8_t *)(PQ + Cfg::LEN);
 
-    // Fill the shifted copies (dword d of copy c holds P[4d + c .. 4d + c + 3]).
+    // Fill the records (dword d of record x holds P[x + 4d .. x + 4d + 3])
+    // and the plain copies.
     wave_sync();
-    for (int idx = lane; idx < 16 * (Cfg::LEN / 4); idx += 64) {
-        const int c = idx / (Cfg::LEN / 4), d = idx % (Cfg::LEN / 4);
-        const int x = 4 * d + c;
-        ((uint32_t *)(PW + c * Cfg::STRIDE))[d] = pack4(M, x, N);
-        ((uint32_t *)(QW + c * Cfg::STRIDE))[d] = pack4(Mr, x, N);
+    for (int idx = lane; idx < 4 * Cfg::NREC; idx += 64) {
+        const int pos = (idx >> 2) + 4 * (idx & 3);
+        ((uint32_t *)RP)[idx] = pack4(M, pos, N);
+        ((uint32_t *)RQ)[idx] = pack4(Mr, pos, N);
+    }
+    for (int idx = lane; idx < Cfg::LEN / 4; idx += 64) {
+        ((uint32_t *)PP)[idx] = pack4(M, 4 * idx, N);
+        ((uint32_t *)PQ)[idx] = pack4(Mr, 4 * idx, N);
     }
 
     // C_k for the lags this lane owns (Eq. 1), its int8 mirror, the energy.
@@ -385,8 +401,8 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
         const int j = lane + 64 * w;
         const int xr = j + 1;
         const int xl = j < N ? N - j : 0;
-        const uint8_t *right = PW + (xr & 15) * Cfg::STRIDE + (xr & ~15);
-        const uint8_t *left = QW + (xl & 15) * Cfg::STRIDE + (xl & ~15);
+        const uint8_t *right = RP + 16 * xr;
+        const uint8_t *left = RQ + 16 * xl;
         const bool right_big = N - 1 - j >= j;
         big[w] = right_big ? right : left;
         small[w] = right_big ? left : right;
@@ -411,9 +427,9 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
 #pragma unroll
-            for (int r = 0; r < Cfg::NBIG; ++r) wb[w][r] = ((const uint4 *)big[w])[r];
+            for (int r = 0; r < Cfg::NBIG; ++r) wb[w][r] = ((const uint4 *)big[w])[16 * r];
 #pragma unroll
-            for (int r = 0; r < Cfg::NSMALL; ++r) ws[w][r] = ((const uint4 *)small[w])[r];
+            for (int r = 0; r < Cfg::NSMALL; ++r) ws[w][r] = ((const uint4 *)small[w])[16 * r];
         }
     }
 
@@ -430,9 +446,9 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
 #pragma unroll
-                for (int r = 0; r < Cfg::NBIG; ++r) wb[w][r] = ((const uint4 *)big[w])[r];
+                for (int r = 0; r < Cfg::NBIG; ++r) wb[w][r] = ((const uint4 *)big[w])[16 * r];
 #pragma unroll
-                for (int r = 0; r < Cfg::NSMALL; ++r) ws[w][r] = ((const uint4 *)small[w])[r];
+                for (int r = 0; r < Cfg::NSMALL; ++r) ws[w][r] = ((const uint4 *)small[w])[16 * r];
             }
         }
 
@@ -503,36 +519,41 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
         }
         if constexpr (TRACE) trace[t - 1] = (int16_t)pick;  // uniform store
 
-        // New s_pick into every copy: P[pick] sits at byte pick - c of copy c
-        // (lanes 0..15), Q[N-1-pick] at byte N-1-pick-c (lanes 16..31); then
-        // the next step's window chunks are requested at once.
+        // New s_pick into every record that holds it: P[pick] is byte c of
+        // record pick - c (lanes 0..15), Q[N-1-pick] byte c of record
+        // N-1-pick-c (lanes 16..31); and into the plain copies (lanes 32,
+        // 33).  Then the next step's window chunks are requested at once.
         {
             const int c = lane & 15;
-            const int pos = (lane < 16 ? pick : N - 1 - pick) - c;
-            uint8_t *base = (lane < 16 ? PW : QW) + c * Cfg::STRIDE;
-            if (lane < 32 && pos >= 0) base[pos] = (uint8_t)(int8_t)(-sm);
+            const bool fwd = lane < 16 || lane == 32;
+            const int y = fwd ? pick : N - 1 - pick;
+            // record y - c >= -15 (a spare record when negative), byte c
+            const int rec = (fwd ? 0 : kRunBytes) + 16 * (y - c) + c;
+            const int pln = 2 * kRunBytes - 16 * kSpareRecords + (fwd ? 0 : Cfg::LEN) + y;
+            if (lane < 34) RP[lane < 32 ? rec : pln] = (uint8_t)(int8_t)(-sm);
         }
         if constexpr (kPipelineWindows) {
             wave_sync();
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
 #pragma unroll
-                for (int r = 0; r < Cfg::NBIG; ++r) wb[w][r] = ((const uint4 *)big[w])[r];
+                for (int r = 0; r < Cfg::NBIG; ++r) wb[w][r] = ((const uint4 *)big[w])[16 * r];
 #pragma unroll
-                for (int r = 0; r < Cfg::NSMALL; ++r) ws[w][r] = ((const uint4 *)small[w])[r];
+                for (int r = 0; r < Cfg::NSMALL; ++r) ws[w][r] = ((const uint4 *)small[w])[16 * r];
             }
         }
 
         // C_k -= 2 s_pick t_pick,k for every lag (lane-parallel):
         // s_{pick+k} = P[pick+k] and s_{pick-k} = Q[N-1-pick+k] are bytes of
-        // copy 0, zero past the ends (position pick itself is not read).
+        // the plain copies, zero past the ends (position pick itself is not
+        // read).
         {
             const int k2 = -2 * sm;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
                 const int k = lane + 1 + 64 * w;
-                const int t_k = (int)((const int8_t *)PW)[pick + k] +
-                                (int)((const int8_t *)QW)[N - 1 - pick + k];
+                const int t_k = (int)((const int8_t *)PP)[pick + k] +
+                                (int)((const int8_t *)PQ)[N - 1 - pick + k];
                 C[w] += k2 * t_k;
                 CB[lane + 64 * w] = (int8_t)C[w];
             }
