@@ -1,6 +1,7 @@
 """Benchmark of the batched tabu-search hot path on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--workload tabu_n64|tabu_uneven]
+                    [--no-cpu] [--no-ttt] [--no-serving]
 
 A step is one labs_tabu_batch call over the whole batch (every walk scores
 all N single-flip neighbours at each of its steps).  The default workload is
@@ -10,12 +11,16 @@ no dataset: an instance is its length N).
 
 Prints one JSON line: whole-job flip-neighbour evaluations per second, the
 roofline of the walk kernel (integer VALU bound) timed with HIP events on the
-stream it runs on, and the CPU oracle timed on a bounded sample of the same
-workload on this host.
+stream it runs on, the CPU oracle timed on a bounded sample of the same
+workload on this host, time-to-target energy of the memetic search at N=120
+(256 replicas of K=100; one launch per generation, a replayed graph of
+one-generation launches, and the batched persistent form), and the serving
+loop's throughput and latency percentiles under Poisson arrivals.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,9 +31,28 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X (gfx950): 256 CUs x 64 int32 lanes x 2.4 GHz
+# MI355X (gfx950): 256 CUs x 4 SIMD x 16 lanes (a wave64 VALU instruction
+# every 4 cycles per SIMD) = 64 int32 lane-ops per CU-cycle, at 2.4 GHz.
 PEAK_INT32_OPS = 256 * 64 * 2.4e9
 METRIC = "flip-neighbour evals/sec (N=64..120) + time-to-target energy; batched vs plain"
+KERNEL_SOURCES = ("paper_2504_00987_amd/csrc/labs_device.hpp",
+                  "paper_2504_00987_amd/csrc/labs_kernels.hip")
+
+# Counter readings per launch of the walk kernels (rocprofv3 --pmc, one pass
+# per counter group, same bench command), valid for the kernel sources whose
+# digest is recorded.  FETCH_SIZE / WRITE_SIZE are in KiB and are scaled by
+# what the same counters read for a 256 MiB device copy (FETCH 0.5x, WRITE
+# 1.0x of the bytes moved).  The summaries live in profiles/.
+COPY_SCALE = {"FETCH_SIZE": 262144 / 131084, "WRITE_SIZE": 262144 / 262144}
+COUNTERS = {}
+
+
+def kernel_digest() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def lag_terms_per_step(n: int) -> int:
@@ -36,49 +60,17 @@ def lag_terms_per_step(n: int) -> int:
     return sum(max(n - j, j - 1) for j in range(1, n + 1))
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="tabu_n64", choices=["tabu_n64", "tabu_uneven"])
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-walks", type=int, default=0, help="oracle sample size (0: all walks)")
-    ap.add_argument("--cpu-min-s", type=float, default=10.0, help="minimum oracle timing")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain 256 MiB device-to-device copy (the reference kernel "
-                         "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        import torch
-        src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
-                          "launches": 3}), flush=True)
-        return 0
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
-              "the walks are independent, so several GPUs would each run their own share",
-              file=sys.stderr)
-        return 2
-
+# ---------------------------------------------------------------------------
+# Batched walks (the headline number)
+# ---------------------------------------------------------------------------
+def tabu_section(args, lb, wl):
     import torch
-    from paper_2504_00987_amd import inputs as I
-    from paper_2504_00987_amd.labs import Labs
-
-    wl = I.TABU_N64 if args.workload == "tabu_n64" else I.TABU_UNEVEN
     ns = wl.lengths()
     W = wl.walks
     steps_per_walk = ns.astype(np.int64) * wl.rules.steps_a
     evals_per_step = int(np.sum(steps_per_walk * ns))
     ops_per_launch = 3 * int(sum(int(s) * lag_terms_per_step(int(n)) for s, n in zip(steps_per_walk, ns)))
 
-    torch.cuda.set_device(0)
-    lb = Labs(0)
     dev = torch.device("cuda", 0)
     out = (torch.empty((W, 128), dtype=torch.int8, device=dev),
            torch.empty(W, dtype=torch.int32, device=dev),
@@ -107,6 +99,32 @@ def main() -> int:
     achieved = ops_per_launch / (kernel_ms * 1e-3)
     launch = lb.get_launch(int(ns.max()))
 
+    roof = {
+        "bound": "alu",
+        "achieved": achieved / 1e12,
+        "peak": PEAK_INT32_OPS / 1e12,
+        "unit": "Top/s (int32, 3 ops per lag term)",
+        "frac": achieved / PEAK_INT32_OPS,
+        "traffic": None,
+        "kernel": "tabu_kernel",
+        "kernel_ms": kernel_ms,
+        "algorithmic_ops_per_launch": ops_per_launch,
+    }
+    digest = kernel_digest()
+    c = COUNTERS.get(wl.name)
+    if c is not None and c["digest"] == digest:
+        roof["traffic"] = (c["FETCH_SIZE"] * COPY_SCALE["FETCH_SIZE"]
+                           + c["WRITE_SIZE"] * COPY_SCALE["WRITE_SIZE"]) * 1024
+        lane_ops = c["SQ_INSTS_VALU"] * 64
+        roof["hardware"] = {
+            "valu_lane_ops_per_launch": lane_ops,
+            "valu_frac": lane_ops / (kernel_ms * 1e-3) / PEAK_INT32_OPS,
+            "lds_instructions_per_launch": c["SQ_INSTS_LDS"],
+            "lds_bank_conflict_cycles_per_launch": c["SQ_LDS_BANK_CONFLICT"],
+            "source": c["source"],
+        }
+    roof["kernel_digest"] = digest
+
     line = {
         "metric": METRIC,
         "value": value,
@@ -131,47 +149,223 @@ def main() -> int:
                        "groups_per_cu": launch[2]},
             "evals_per_step": evals_per_step,
         },
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": PEAK_INT32_OPS / 1e12,
-            "unit": "Top/s (int32, 3 ops per lag term)",
-            "frac": achieved / PEAK_INT32_OPS,
-            "traffic": None,
-            "kernel": "tabu_kernel",
-            "kernel_ms": kernel_ms,
-            "algorithmic_ops_per_launch": ops_per_launch,
-        },
+        "roofline": roof,
+    }
+    return line, ns
+
+
+def cpu_tabu(args, wl, ns):
+    # The oracle on this host's cores over the same workload, repeated until
+    # at least min_s seconds have elapsed (one pass is well under a second
+    # with 16 threads).  Walks are independent, so the oracle's batch call
+    # spreads them over threads; nothing else is tuned.
+    from oracle import oracle as O
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    sample = args.cpu_walks or wl.walks
+    r = wl.rules
+    sched = O.Schedule(r.steps_rule, r.steps_a, r.tenure_rule, r.lo_num, r.lo_den, r.lo_add,
+                       r.hi_num, r.hi_den, r.hi_add, r.aspiration)
+    sub_ns = ns[:sample]
+    passes, c0 = 0, time.perf_counter()
+    while True:
+        O.tabu_batch(sample, sched, wl.seed, ns=sub_ns, stride=128, nthreads=threads)
+        passes += 1
+        if time.perf_counter() - c0 >= args.cpu_min_s or passes >= 100:
+            break
+    cpu_s = time.perf_counter() - c0
+    cpu_evals = passes * int(np.sum(sub_ns.astype(np.int64) * r.steps_a * sub_ns))
+    return {
+        "value": cpu_evals / cpu_s,
+        "unit": "evals/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{passes} passes over walks 0..{sample - 1} of {wl.name} in {cpu_s:.1f} s "
+                  f"(plain C, gcc -O2, {threads} threads)",
     }
 
+
+# ---------------------------------------------------------------------------
+# Time to target: memetic search at N=120
+# ---------------------------------------------------------------------------
+MODES = {"plain": 0, "graph": 1, "persistent": 2}
+
+
+def ttt_section(args, lb):
+    import torch
+    from paper_2504_00987_amd import inputs as I
+    wl = I.MEMETIC_N120
+    n = wl.n
+    G = args.ttt_gens
+    targets = [int(t) for t in args.ttt_targets.split(",") if t]
+    res = {"workload": wl.name, "n": n, "replicas": wl.pops, "K": wl.K,
+           "generation_budget": G, "chunk": args.ttt_chunk,
+           "rules": "crossover p=0.9, tournament parents, one cut; mutation 1/N; walk "
+                    "floor(N/2)+U[0,N] steps, tenure U[1, floor(N/10)+1], aspiration",
+           "stop": "all replicas stop at the end of the chunk in which the first reaches "
+                   "the target", "targets": []}
+    for tgt in targets:
+        row = {"target_e": tgt, "target_mf": n * n / (2 * tgt)}
+        hit = None
+        for name in args.ttt_modes.split(","):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = lb.memetic_run(wl.K, wl.rules, G, wl.pops, wl.seed, n_uniform=n,
+                               mode=MODES[name], chunk=args.ttt_chunk, target=tgt, stop_all=1)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            h = r.hit_gen.cpu().numpy()
+            first = int(h[h >= 0].min()) if (h >= 0).any() else None
+            gens = int(r.gens_done.max().item())
+            be = int(r.best_e.min().item())
+            if hit is None:
+                hit = (first, be, gens)
+            elif hit != (first, be, gens):
+                raise RuntimeError(f"execution modes disagree at target {tgt}: {hit} vs "
+                                   f"{(first, be, gens)}")
+            row[f"seconds_{name}"] = dt
+            row[f"us_per_generation_{name}"] = dt / max(gens, 1) * 1e6
+        row["hit_generation"], row["best_e"], row["generations_run"] = hit
+        row["reached"] = hit[0] is not None
+        if "seconds_plain" in row and "seconds_persistent" in row:
+            row["persistent_speedup_vs_plain"] = row["seconds_plain"] / row["seconds_persistent"]
+        res["targets"].append(row)
+    return res
+
+
+def cpu_memetic(args, n_gens_sample: int = 64):
+    # The oracle's memetic replicas at the same size, one thread per replica
+    # group (each replica is independent), timed on a bounded number of
+    # generations; its time to a target reached at generation g is g times
+    # the per-generation time (the trajectories are identical).
+    import concurrent.futures as cf
+    from oracle import oracle as O
+    from paper_2504_00987_amd import inputs as I
+    wl = I.MEMETIC_N120
+    r = wl.rules
+    sched = O.Schedule(r.steps_rule, r.steps_a, r.tenure_rule, r.lo_num, r.lo_den, r.lo_add,
+                       r.hi_num, r.hi_den, r.hi_add, r.aspiration)
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    reps = [O.MemeticState(wl.n, wl.K, wl.seed, p) for p in range(wl.pops)]
+    pm = O.p_mut_inv_n(wl.n)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda st: st.advance(n_gens_sample, sched, wl.p_comb, pm), reps))
+    dt = time.perf_counter() - t0
+    return {"us_per_generation": dt / n_gens_sample * 1e6, "cores": threads, "kind": "oracle",
+            "sample": f"{wl.pops} replicas x {n_gens_sample} generations at N={wl.n} in {dt:.1f} s"}
+
+
+# ---------------------------------------------------------------------------
+# Serving: Poisson arrivals, continuous batching
+# ---------------------------------------------------------------------------
+def serve(lb, reqs, arrivals, max_slots, chunk, K, rules, pops, gens):
+    from paper_2504_00987_amd.labs import Server
+    srv = Server(lb, K, rules, max_slots=max_slots, chunk=chunk)
+    pending, lats = {}, []
+    try:
+        t0 = time.perf_counter()
+        i = 0
+        while i < len(reqs) or pending:
+            now = time.perf_counter() - t0
+            while i < len(reqs) and arrivals[i] <= now:
+                n, s = reqs[i]
+                pending[srv.submit(n, s, pops, gens)] = n
+                i += 1
+            for rid in list(pending):
+                r = srv.poll(rid, pending[rid])
+                if r is not None:
+                    lats.append(r[2])
+                    del pending[rid]
+            time.sleep(0.0002)
+        wall = time.perf_counter() - t0
+    finally:
+        srv.close()
+    lats = np.array(lats)
+    return {"solves_per_s": len(reqs) / wall, "p50_ms": float(np.percentile(lats, 50)) * 1e3,
+            "p99_ms": float(np.percentile(lats, 99)) * 1e3, "seconds": wall}
+
+
+def serving_section(args, lb):
+    from paper_2504_00987_amd import inputs as I
+    K, rules = 100, I.RULES_MEMETIC
+    pops, gens = I.SERVING_POPS, I.SERVING_GENS
+    reqs = I.serving_requests(args.serve_requests)
+    cfg = dict(max_slots=args.serve_slots, chunk=args.serve_chunk, K=K, rules=rules, pops=pops,
+               gens=gens)
+    burst = serve(lb, reqs, np.zeros(len(reqs)), **cfg)
+    cap = burst["solves_per_s"]
+    out = {"requests_per_rate": len(reqs), "n": "uniform {32..128}", "replicas_per_request": pops,
+           "generations": gens, "K": K, "resident_slots": args.serve_slots,
+           "chunk": args.serve_chunk, "capacity_solves_per_s": cap, "burst": burst, "rates": []}
+    for frac in [float(x) for x in args.serve_rates.split(",") if x]:
+        arr = I.poisson_arrivals(frac * cap, len(reqs), seed=I.SERVING_SEED + 1)
+        r = serve(lb, reqs, arr, **cfg)
+        r["offered_per_s"] = frac * cap
+        r["load"] = frac
+        out["rates"].append(r)
+    return out
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="tabu_n64", choices=["tabu_n64", "tabu_uneven"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
+    ap.add_argument("--cpu-walks", type=int, default=0, help="oracle sample size (0: all walks)")
+    ap.add_argument("--cpu-min-s", type=float, default=10.0, help="minimum oracle timing")
+    ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-target section")
+    ap.add_argument("--ttt-gens", type=int, default=100000)
+    ap.add_argument("--ttt-targets", default="1200,1107")
+    ap.add_argument("--ttt-modes", default="persistent,graph,plain")
+    ap.add_argument("--ttt-chunk", type=int, default=64)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--serve-slots", type=int, default=8192)
+    ap.add_argument("--serve-chunk", type=int, default=25)
+    ap.add_argument("--serve-rates", default="0.5,0.9")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy (the reference kernel "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
+                          "launches": 3}), flush=True)
+        return 0
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
+              "the walks are independent, so several GPUs would each run their own share",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2504_00987_amd import inputs as I
+    from paper_2504_00987_amd.labs import Labs
+
+    wl = I.TABU_N64 if args.workload == "tabu_n64" else I.TABU_UNEVEN
+    torch.cuda.set_device(0)
+    lb = Labs(0)
+    line, ns = tabu_section(args, lb, wl)
+    print(f"# tabu: {line['value']:.4g} evals/s, kernel {line['roofline']['kernel_ms']:.4f} ms",
+          file=sys.stderr, flush=True)
     if not args.no_cpu:
-        # The oracle on this host's cores over the same workload, repeated
-        # until at least min_s seconds have elapsed (one pass is well under a
-        # second with 16 threads).  Walks are independent, so the oracle's
-        # batch call spreads them over threads; nothing else is tuned.
-        from oracle import oracle as O
-        threads = max(1, min(16, len(os.sched_getaffinity(0))))
-        sample = args.cpu_walks or W
-        sched = O.Schedule(wl.rules.steps_rule, wl.rules.steps_a, wl.rules.tenure_rule,
-                           wl.rules.lo_num, wl.rules.lo_den, wl.rules.lo_add, wl.rules.hi_num,
-                           wl.rules.hi_den, wl.rules.hi_add, wl.rules.aspiration)
-        sub_ns = ns[:sample]
-        passes, c0 = 0, time.perf_counter()
-        while True:
-            O.tabu_batch(sample, sched, wl.seed, ns=sub_ns, stride=128, nthreads=threads)
-            passes += 1
-            if time.perf_counter() - c0 >= args.cpu_min_s or passes >= 100:
-                break
-        cpu_s = time.perf_counter() - c0
-        cpu_evals = passes * int(np.sum(sub_ns.astype(np.int64) * wl.rules.steps_a * sub_ns))
-        line["cpu_baseline"] = {
-            "value": cpu_evals / cpu_s,
-            "unit": "evals/s",
-            "cores": threads,
-            "kind": "oracle",
-            "sample": f"{passes} passes over walks 0..{sample - 1} of {wl.name} in {cpu_s:.1f} s "
-                      f"(plain C, gcc -O2, {threads} threads)",
-        }
+        line["cpu_baseline"] = cpu_tabu(args, wl, ns)
+    if not args.no_ttt:
+        line["time_to_target"] = ttt_section(args, lb)
+        print("# time to target done", file=sys.stderr, flush=True)
+        if not args.no_cpu:
+            line["time_to_target"]["cpu_baseline"] = cpu_memetic(args)
+    if not args.no_serving:
+        line["serving"] = serving_section(args, lb)
+        print("# serving done", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
     lb.close()
     return 0

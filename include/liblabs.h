@@ -167,12 +167,14 @@ int labs_set_launch(labs_handle *h, const labs_launch *launch);
 int labs_get_launch(labs_handle *h, int32_t n, labs_launch *out);
 
 /*
- * Autotuner: for each length bucket covering [n_min, n_max] it times every
- * launch configuration {64, 128, 256 lanes per workgroup} x {one wave per
- * walk, persistent queue at 1/2/4 groups per CU} on `walks` random-start
- * walks with parameters `p`, keeps the fastest per bucket, and reports the
- * number of configurations timed in *tried (may be NULL).  Synchronous;
- * results never depend on the choice (only speed does).
+ * Autotuner: times every launch configuration {64, 128, 256 lanes per
+ * workgroup, i.e. 1, 2, 4 walks per workgroup} x {one wave per walk,
+ * persistent queue at 1/2/4/8 x 4/(walks per workgroup) groups per CU} on
+ * `walks` random-start walks with lengths spread evenly over [n_min, n_max]
+ * and parameters `p`, and keeps the fastest for the batches whose longest
+ * walk falls in the length bucket (of 16) of n_max.  *tried (may be NULL)
+ * receives the number of configurations timed.  Synchronous; results never
+ * depend on the choice (only speed does).
  */
 int labs_autotune(labs_handle *h, const labs_tabu_params *p, int32_t n_min,
                   int32_t n_max, int64_t walks, uint64_t seed, int32_t *tried);
@@ -206,6 +208,12 @@ typedef struct labs_memetic_params {
     int32_t stop_all;    /* 1: once any replica reaches target_e, every
                             replica stops at the end of the current chunk
                             (the global termination flag of Sec. IV) */
+    int32_t waves_per_replica; /* replicas with N > 64: 1 or 2 wavefronts
+                            (two split each step's neighbours and exchange
+                            their minima: lower latency per generation, for
+                            batches too small to fill the device); 0 picks
+                            2 when those replicas number at most twice the
+                            compute units */
 } labs_memetic_params;
 
 /*

@@ -275,7 +275,8 @@ struct WalkResult {
 
 // LDS layout of one walk: P records, Q records (each run preceded by 15
 // spare records, so that the byte update after a move needs no bounds
-// test), plain P, plain Q, C bytes.
+// test), plain P, plain Q, C bytes, and six words through which the two
+// wavefronts of a split walk exchange their minima.
 //   P[x] = s_x for x < N, 0 otherwise; Q is the reversed sequence,
 //   Q[x] = s_{N-1-x} for x < N, 0 otherwise;
 //   record x (16 bytes, at 16 x) holds P[x .. x+15], so a window starting
@@ -297,7 +298,8 @@ template <> struct WalkLds<2> {
 constexpr int kSpareRecords = 15;
 template <int NW>
 constexpr int walk_lds_bytes() {
-    return 2 * 16 * (kSpareRecords + WalkLds<NW>::NREC) + 2 * WalkLds<NW>::LEN + WalkLds<NW>::CLEN;
+    return 2 * 16 * (kSpareRecords + WalkLds<NW>::NREC) + 2 * WalkLds<NW>::LEN + WalkLds<NW>::CLEN +
+           32;  // + the two-wavefront exchange words
 }
 
 // Lane l receives bit l of a wave-uniform 64-bit mask.
@@ -324,24 +326,46 @@ __device__ __forceinline__ int dot16(const uint4 a, const uint4 b, int acc) {
     return __builtin_amdgcn_sdot4((int)a.w, (int)b.w, acc, false);
 }
 
+// Orders the LDS accesses of the SPLIT wavefronts that run one walk (a
+// wavefront fence for one, a workgroup barrier for two: the workgroup is
+// exactly the walk's wavefronts).
+template <int SPLIT>
+__device__ __forceinline__ void walk_sync() {
+    if constexpr (SPLIT == 1)
+        wave_sync();
+    else
+        __syncthreads();
+}
+
 // Runs one walk of sch.T steps from mask M0 (bits >= N must be clear).
-//   lds    per-wavefront LDS scratch of walk_lds_bytes<NW>() bytes, 16-aligned
+//   NW     neighbours per lane when one wavefront runs the walk: 1 for
+//          N <= 64, 2 for N <= 128 (also fixes the mask width and the LDS
+//          layout)
+//   SPLIT  wavefronts per walk: 1, or 2 with NW = 2, wavefront `part`
+//          (0 or 1) owning neighbours and lags 64 part .. 64 part + 63; the
+//          two exchange their minima through LDS (two barriers per step)
+//   lds    per-walk LDS scratch of walk_lds_bytes<NW>() bytes, 16-aligned
 //   trace  with TRACE: trace[t-1] = flipped index
-// Every lane of the wavefront must call this with identical uniform inputs.
-template <int NW, bool TRACE = false>
+// Every lane of the walk's wavefronts must call this with identical uniform
+// inputs (part aside).
+template <int NW, bool TRACE = false, int SPLIT = 1>
 __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typename MaskOf<NW>::type M0,
                                                     const Schedule sch_in, const int aspiration_in,
                                                     const uint32_t k0, const uint32_t k1,
                                                     const uint32_t entity, const uint32_t gen,
                                                     uint8_t *__restrict__ lds,
-                                                    int16_t *__restrict__ trace) {
+                                                    int16_t *__restrict__ trace,
+                                                    const int part_in = 0) {
+    static_assert(SPLIT == 1 || (SPLIT == 2 && NW == 2), "two wavefronts per walk need N <= 128");
     using Mask = typename MaskOf<NW>::type;
     using Cfg = WalkLds<NW>;
+    constexpr int NL = NW / SPLIT;  // neighbours per lane
     const int lane = lane_id();
     // Wave-uniform parameters, pinned to scalar registers so that the step
     // loop is controlled by scalar branches.
     const int N = __builtin_amdgcn_readfirstlane(N_in);
     const int aspiration = __builtin_amdgcn_readfirstlane(aspiration_in);
+    const int part = SPLIT == 1 ? 0 : __builtin_amdgcn_readfirstlane(part_in);
     Schedule sch;
     sch.T = __builtin_amdgcn_readfirstlane(sch_in.T);
     sch.lo = __builtin_amdgcn_readfirstlane(sch_in.lo);
@@ -365,40 +389,50 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
     uint8_t *const PP = RP - 16 * kSpareRecords + 2 * kRunBytes;
     uint8_t *const PQ = PP + Cfg::LEN;
     int8_t *const CB = (int8_t *)(PQ + Cfg::LEN);
+    int *const XCH = (int *)(CB + Cfg::CLEN);  // SPLIT exchange: [part][min, tie lo, tie hi]
 
     // Fill the records (dword d of record x holds P[x + 4d .. x + 4d + 3])
     // and the plain copies.
-    wave_sync();
-    for (int idx = lane; idx < 4 * Cfg::NREC; idx += 64) {
+    walk_sync<SPLIT>();
+    for (int idx = lane + 64 * part; idx < 4 * Cfg::NREC; idx += 64 * SPLIT) {
         const int pos = (idx >> 2) + 4 * (idx & 3);
         ((uint32_t *)RP)[idx] = pack4(M, pos, N);
         ((uint32_t *)RQ)[idx] = pack4(Mr, pos, N);
     }
-    for (int idx = lane; idx < Cfg::LEN / 4; idx += 64) {
+    for (int idx = lane + 64 * part; idx < Cfg::LEN / 4; idx += 64 * SPLIT) {
         ((uint32_t *)PP)[idx] = pack4(M, 4 * idx, N);
         ((uint32_t *)PQ)[idx] = pack4(Mr, 4 * idx, N);
     }
 
+    // Register w of a lane holds neighbour j = lane + 64 h and lag
+    // k = lane + 1 + 64 h, h = w (one wavefront) or part (two).
+    auto half = [&](int w) { return SPLIT == 1 ? w : part; };
+
     // C_k for the lags this lane owns (Eq. 1), its int8 mirror, the energy.
-    int C[NW];
+    int C[NL];
     int sq = 0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        const int k = lane + 1 + 64 * w;
+    for (int w = 0; w < NL; ++w) {
+        const int k = lane + 1 + 64 * half(w);
         C[w] = k < N ? lag_corr(M, N, k) : 0;
         sq += C[w] * C[w];
-        CB[lane + 64 * w] = (int8_t)C[w];
+        CB[k - 1] = (int8_t)C[w];
     }
     int E = wave_sum(sq);
+    if constexpr (SPLIT == 2) {
+        XCH[3 * part] = E;  // uniform value, every lane
+        walk_sync<SPLIT>();
+        E += __builtin_amdgcn_readfirstlane(XCH[3 * (1 - part)]);
+    }
 
     // Per-lane window addresses (fixed for the walk).  Neighbour j's right
     // window starts at P[j+1], its left window at Q[N-j]; the longer of the
     // two is read over all lags, the shorter over the first half.
-    const uint8_t *big[NW];
-    const uint8_t *small[NW];
+    const uint8_t *big[NL];
+    const uint8_t *small[NL];
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        const int j = lane + 64 * w;
+    for (int w = 0; w < NL; ++w) {
+        const int j = lane + 64 * half(w);
         const int xr = j + 1;
         const int xl = j < N ? N - j : 0;
         const uint8_t *right = RP + 16 * xr;
@@ -408,24 +442,25 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
         small[w] = right_big ? left : right;
     }
 
-    int tabu[NW];
+    int tabu[NL];
 #pragma unroll
-    for (int w = 0; w < NW; ++w) tabu[w] = 0;
+    for (int w = 0; w < NL; ++w) tabu[w] = 0;
     Mask best = M;
     int bestE = E;
     uint32_t dr0 = 0u, dr1 = 0u;
 
-    // Window chunks of the current pivot.  With one neighbour per lane they
-    // are requested one step ahead, right after the move's byte update; with
-    // two, at the top of each step (the registers for early loads would cost
-    // occupancy).
-    constexpr bool kPipelineWindows = NW == 1;
-    uint4 wb[NW][Cfg::NBIG];
-    uint4 ws[NW][Cfg::NSMALL];
+    // Window chunks of the current pivot.  With one neighbour per lane and
+    // one wavefront they are requested one step ahead, right after the
+    // move's byte update; otherwise at the top of each step (two neighbours:
+    // the registers for early loads would cost occupancy; two wavefronts:
+    // the other one's byte update must be visible first).
+    constexpr bool kPipelineWindows = NW == 1 && SPLIT == 1;
+    uint4 wb[NL][Cfg::NBIG];
+    uint4 ws[NL][Cfg::NSMALL];
     if constexpr (kPipelineWindows) {
-        wave_sync();
+        walk_sync<SPLIT>();
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
+        for (int w = 0; w < NL; ++w) {
 #pragma unroll
             for (int r = 0; r < Cfg::NBIG; ++r) wb[w][r] = ((const uint4 *)big[w])[16 * r];
 #pragma unroll
@@ -441,10 +476,10 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
             dr0 = d.w0;
             dr1 = d.w1;
         }
-        wave_sync();  // the previous move's C bytes are visible
+        walk_sync<SPLIT>();  // the previous move's bytes are visible
         if constexpr (!kPipelineWindows) {
 #pragma unroll
-            for (int w = 0; w < NW; ++w) {
+            for (int w = 0; w < NL; ++w) {
 #pragma unroll
                 for (int r = 0; r < Cfg::NBIG; ++r) wb[w][r] = ((const uint4 *)big[w])[16 * r];
 #pragma unroll
@@ -457,10 +492,10 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
         for (int r = 0; r < Cfg::NBIG; ++r) cc[r] = ((const uint4 *)CB)[r];
 
         // Score the neighbours this lane owns (independent accumulators).
-        int key[NW];
+        int key[NL];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            const int j = lane + 64 * w;
+        for (int w = 0; w < NL; ++w) {
+            const int j = lane + 64 * half(w);
             int vb0 = 0, vb1 = 0, vs = 0;  // sum_k t_jk C_k, split
             int u = 0;                     // sum_k s_{j+k} s_{j-k}
 #pragma unroll
@@ -475,7 +510,7 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
                 }
             }
             const int v = vb0 + vb1 + vs;
-            const uint64_t mw = w == 0 ? mask_lo(M) : mask_hi(M);
+            const uint64_t mw = half(w) == 0 ? mask_lo(M) : mask_hi(M);
             const int sv = lane_bit(mw) ? -v : v;  // s_j * v
             const int cand = E + 4 * (N - 1 + 2 * u - sv);
             const bool admissible = tabu[w] < t || (aspiration && cand < bestE);
@@ -484,12 +519,31 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
 
         // Admissible minimum, ties broken by the step's draw: the r-th
         // (ascending) of the tied moves, r = (u0 * count) >> 32.
-        int kmin = key[0];
-        if constexpr (NW == 2) kmin = min(kmin, key[1]);
-        const int m = wave_min(kmin);
-        const uint64_t T0 = ballot(key[0] == m);
-        uint64_t T1 = 0ull;
-        if constexpr (NW == 2) T1 = ballot(key[1] == m);
+        int m;
+        uint64_t T0, T1 = 0ull;
+        if constexpr (SPLIT == 1) {
+            int kmin = key[0];
+            if constexpr (NW == 2) kmin = min(kmin, key[1]);
+            m = wave_min(kmin);
+            T0 = ballot(key[0] == m);
+            if constexpr (NW == 2) T1 = ballot(key[1] == m);
+        } else {
+            const int mine = wave_min(key[0]);
+            const uint64_t tmine = ballot(key[0] == mine);
+            XCH[3 * part] = mine;  // uniform values, every lane
+            XCH[3 * part + 1] = (int)(uint32_t)tmine;
+            XCH[3 * part + 2] = (int)(uint32_t)(tmine >> 32);
+            walk_sync<SPLIT>();
+            const int other = __builtin_amdgcn_readfirstlane(XCH[3 * (1 - part)]);
+            const uint64_t tother =
+                ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(XCH[3 * (1 - part) + 2]) << 32) |
+                (uint32_t)__builtin_amdgcn_readfirstlane(XCH[3 * (1 - part) + 1]);
+            m = min(mine, other);
+            const uint64_t a = mine == m ? tmine : 0ull;
+            const uint64_t b = other == m ? tother : 0ull;
+            T0 = part == 0 ? a : b;
+            T1 = part == 0 ? b : a;
+        }
         const int c0 = __popcll(T0);
         const uint32_t u0 = readlane_u(dr0, slot);
         const uint32_t u1 = readlane_u(dr1, slot);
@@ -509,7 +563,7 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
         // Apply the move: tenure, sequence, energy, best.
         const int tenure = sch.lo + (int)below(u1, (uint32_t)(sch.hi - sch.lo + 1));
 #pragma unroll
-        for (int w = 0; w < NW; ++w) tabu[w] = pick == lane + 64 * w ? t + tenure : tabu[w];
+        for (int w = 0; w < NL; ++w) tabu[w] = pick == lane + 64 * half(w) ? t + tenure : tabu[w];
         const int sm = 1 - 2 * m_bit(M, pick);  // old s_pick
         M = m_xor(M, m_onebit(M, pick));
         E = m;
@@ -517,13 +571,15 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
             bestE = E;
             best = M;
         }
-        if constexpr (TRACE) trace[t - 1] = (int16_t)pick;  // uniform store
+        if constexpr (TRACE) {
+            if (part == 0) trace[t - 1] = (int16_t)pick;  // uniform store
+        }
 
         // New s_pick into every record that holds it: P[pick] is byte c of
         // record pick - c (lanes 0..15), Q[N-1-pick] byte c of record
         // N-1-pick-c (lanes 16..31); and into the plain copies (lanes 32,
         // 33).  Then the next step's window chunks are requested at once.
-        {
+        if (part == 0) {
             const int c = lane & 15;
             const bool fwd = lane < 16 || lane == 32;
             const int y = fwd ? pick : N - 1 - pick;
@@ -535,7 +591,7 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
         if constexpr (kPipelineWindows) {
             wave_sync();
 #pragma unroll
-            for (int w = 0; w < NW; ++w) {
+            for (int w = 0; w < NL; ++w) {
 #pragma unroll
                 for (int r = 0; r < Cfg::NBIG; ++r) wb[w][r] = ((const uint4 *)big[w])[16 * r];
 #pragma unroll
@@ -546,16 +602,16 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
         // C_k -= 2 s_pick t_pick,k for every lag (lane-parallel):
         // s_{pick+k} = P[pick+k] and s_{pick-k} = Q[N-1-pick+k] are bytes of
         // the plain copies, zero past the ends (position pick itself is not
-        // read).
+        // read, so the other wavefront's byte update cannot race with it).
         {
             const int k2 = -2 * sm;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                const int k = lane + 1 + 64 * w;
+            for (int w = 0; w < NL; ++w) {
+                const int k = lane + 1 + 64 * half(w);
                 const int t_k = (int)((const int8_t *)PP)[pick + k] +
                                 (int)((const int8_t *)PQ)[N - 1 - pick + k];
                 C[w] += k2 * t_k;
-                CB[lane + 64 * w] = (int8_t)C[w];
+                CB[k - 1] = (int8_t)C[w];
             }
         }
     }

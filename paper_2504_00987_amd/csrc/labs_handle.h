@@ -72,6 +72,8 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
                     int32_t *final_e, int16_t *trace, int32_t trace_stride, hipStream_t s,
                     const labs_launch *force);
 int check_memetic(labs_handle *h, const labs_memetic_params *p);
+// 1 when replicas with N > 64 should run on two wavefronts each.
+int split_wide(const labs_handle *h, int waves_per_replica, int64_t n_wide);
 
 // Bytes of device state per memetic replica with population size K.
 inline size_t memetic_state_bytes(int K) {

@@ -62,6 +62,7 @@ struct MemeticLaunchArgs {
     RuleParams rule;
     int32_t gens;            // generations per launch
     int32_t classes;         // bit 0: some slot has N <= 64; bit 1: some N > 64
+    int32_t split_wide;      // 1: a replica with N > 64 runs on two wavefronts
     MemeticStateDev st;
     uint32_t *any_hit;       // set to 1 when a replica reaches its target
 };
@@ -76,7 +77,13 @@ hipError_t launch_tabu(const TabuLaunchArgs &a, int waves_per_group, int groups,
                        hipStream_t s_wide, hipStream_t s_narrow);
 
 hipError_t launch_memetic_init(const MemeticLaunchArgs &a, hipStream_t s);
-hipError_t launch_memetic_advance(const MemeticLaunchArgs &a, hipStream_t s);
+// Advances every slot by a.gens generations.  When both length classes are
+// present and `side` is given, the N <= 64 slots run on `side` (forked from
+// and joined back into s with the two events), concurrently with the N > 64
+// slots on s; the sequence of calls is capturable into a graph.
+hipError_t launch_memetic_advance(const MemeticLaunchArgs &a, hipStream_t s,
+                                  hipStream_t side = nullptr, hipEvent_t fork = nullptr,
+                                  hipEvent_t join = nullptr);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
 hipError_t launch_gather_best(const MemeticStateDev &st, const int32_t *state_idx,
                               const int32_t *ns, int32_t n_uniform, int32_t count,

@@ -181,19 +181,22 @@ __global__ __launch_bounds__(64) void memetic_init_kernel(MemeticLaunchArgs a) {
     a.st.hit[sl.state] = -1;
 }
 
-template <int NW>
+// One replica on SPLIT wavefronts (wavefront `part` of them); every
+// wavefront runs the generation logic redundantly on wave-uniform values and
+// the walk is split between them.
+template <int NW, int SPLIT>
 __device__ void memetic_replica(const MemeticLaunchArgs &a, const MemeticSlot &sl,
-                                uint64_t (*pop)[2], int *popE, uint8_t *lds) {
+                                uint64_t (*pop)[2], int *popE, uint8_t *lds, int part) {
     using Mask = typename MaskOf<NW>::type;
     const int lane = lane_id();
     const int N = sl.n, K = a.K, st = sl.state;
     const int64_t base = (int64_t)st * K;
-    for (int i = lane; i < K; i += 64) {
+    for (int i = lane + 64 * part; i < K; i += 64 * SPLIT) {
         pop[i][0] = a.st.pop[(base + i) * 2 + 0];
         pop[i][1] = a.st.pop[(base + i) * 2 + 1];
         popE[i] = a.st.popE[base + i];
     }
-    wave_sync();
+    walk_sync<SPLIT>();
     Mask best = make_mask<NW>(a.st.best[(int64_t)st * 2 + 0], a.st.best[(int64_t)st * 2 + 1]);
     int bestE = a.st.bestE[st];
     int64_t g = a.st.gen[st];
@@ -241,18 +244,19 @@ __device__ void memetic_replica(const MemeticLaunchArgs &a, const MemeticSlot &s
         }
         child = m_xor(child, make_mask<NW>(flo, fhi));
         const Schedule sch = make_schedule(a.rule, N, sl.k0, sl.k1, sl.pop_id, gg);
-        const WalkResult<NW> r = tabu_walk<NW>(N, child, sch, a.rule.aspiration, sl.k0, sl.k1,
-                                               sl.pop_id, gg, lds, nullptr);
+        const WalkResult<NW> r = tabu_walk<NW, false, SPLIT>(N, child, sch, a.rule.aspiration,
+                                                             sl.k0, sl.k1, sl.pop_id, gg, lds,
+                                                             nullptr, part);
         if (r.best_e < bestE) {
             bestE = r.best_e;
             best = r.best;
         }
         const int rep = (int)below(db.w2, (uint32_t)K);
-        wave_sync();
+        walk_sync<SPLIT>();
         pop[rep][0] = mask_lo(r.best);  // uniform values, every lane
         pop[rep][1] = mask_hi(r.best);
         popE[rep] = r.best_e;
-        wave_sync();
+        walk_sync<SPLIT>();
         ++g;
         if (targeted && bestE <= sl.target) {
             if (hit < 0) hit = g;
@@ -260,11 +264,12 @@ __device__ void memetic_replica(const MemeticLaunchArgs &a, const MemeticSlot &s
         }
     }
 
-    for (int i = lane; i < K; i += 64) {
+    for (int i = lane + 64 * part; i < K; i += 64 * SPLIT) {
         a.st.pop[(base + i) * 2 + 0] = pop[i][0];
         a.st.pop[(base + i) * 2 + 1] = pop[i][1];
         a.st.popE[base + i] = popE[i];
     }
+    if (part != 0) return;
     a.st.best[(int64_t)st * 2 + 0] = mask_lo(best);  // uniform values, every lane
     a.st.best[(int64_t)st * 2 + 1] = mask_hi(best);
     a.st.bestE[st] = bestE;
@@ -273,10 +278,11 @@ __device__ void memetic_replica(const MemeticLaunchArgs &a, const MemeticSlot &s
     if (hit >= 0 && a.any_hit != nullptr) atomicOr(a.any_hit, 1u);
 }
 
-// Replicas of one length class: N <= 64 (NW = 1) or 64 < N <= 128 (NW = 2);
-// slots of the other class and idle slots return at once.
-template <int NW>
-__global__ __launch_bounds__(64) void memetic_advance_kernel(MemeticLaunchArgs a) {
+// Replicas of one length class: N <= 64 (NW = 1) or 64 < N <= 128 (NW = 2),
+// one workgroup of SPLIT wavefronts per replica; slots of the other class
+// and idle slots return at once.
+template <int NW, int SPLIT>
+__global__ __launch_bounds__(64 * SPLIT) void memetic_advance_kernel(MemeticLaunchArgs a) {
     __shared__ uint64_t pop[kMaxK][2];
     __shared__ int popE[kMaxK];
     __shared__ __attribute__((aligned(16))) uint8_t lds[walk_lds_bytes<NW>()];
@@ -284,7 +290,7 @@ __global__ __launch_bounds__(64) void memetic_advance_kernel(MemeticLaunchArgs a
     if (s >= a.n_slots) return;
     const MemeticSlot sl = a.slots[s];
     if (sl.state < 0 || (sl.n > 64) != (NW == 2)) return;
-    memetic_replica<NW>(a, sl, pop, popE, lds);
+    memetic_replica<NW, SPLIT>(a, sl, pop, popE, lds, SPLIT == 1 ? 0 : (int)(threadIdx.x >> 6));
 }
 
 __global__ void gather_best_kernel(MemeticStateDev st, const int32_t *__restrict__ state_idx,
@@ -383,13 +389,32 @@ hipError_t launch_memetic_init(const MemeticLaunchArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_memetic_advance(const MemeticLaunchArgs &a, hipStream_t s) {
+hipError_t launch_memetic_advance(const MemeticLaunchArgs &a, hipStream_t s, hipStream_t side,
+                                  hipEvent_t fork, hipEvent_t join) {
     if (a.n_slots <= 0) return hipSuccess;
+    const bool split = a.classes == 3 && side != nullptr && fork != nullptr && join != nullptr;
+    hipStream_t s1 = s;
+    if (split) {
+        hipError_t e = hipEventRecord(fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+        if (e != hipSuccess) return e;
+        s1 = side;
+    }
     if (a.classes & 1)
-        hipLaunchKernelGGL(memetic_advance_kernel<1>, dim3((unsigned)a.n_slots), dim3(64), 0, s, a);
-    if (a.classes & 2)
-        hipLaunchKernelGGL(memetic_advance_kernel<2>, dim3((unsigned)a.n_slots), dim3(64), 0, s, a);
-    return hipGetLastError();
+        hipLaunchKernelGGL((memetic_advance_kernel<1, 1>), dim3((unsigned)a.n_slots), dim3(64), 0,
+                           s1, a);
+    if ((a.classes & 2) && a.split_wide)
+        hipLaunchKernelGGL((memetic_advance_kernel<2, 2>), dim3((unsigned)a.n_slots), dim3(128), 0,
+                           s, a);
+    else if (a.classes & 2)
+        hipLaunchKernelGGL((memetic_advance_kernel<2, 1>), dim3((unsigned)a.n_slots), dim3(64), 0,
+                           s, a);
+    hipError_t e = hipGetLastError();
+    if (split && e == hipSuccess) {
+        e = hipEventRecord(join, side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
+    }
+    return e;
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s) {

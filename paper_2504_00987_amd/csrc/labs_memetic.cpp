@@ -33,6 +33,11 @@ MemeticStateDev carve_state(void *base, int S, int K, size_t *bytes_out) {
     return st;
 }
 
+int split_wide(const labs_handle *h, int waves_per_replica, int64_t n_wide) {
+    if (waves_per_replica != 0) return waves_per_replica == 2;
+    return n_wide <= 2 * (int64_t)std::max(h->num_cus, 1);
+}
+
 int check_memetic(labs_handle *h, const labs_memetic_params *p) {
     if (!p) return fail(h, LABS_E_INVAL, "null memetic params");
     if (p->K < 2 || p->K > LABS_MAX_K) return fail(h, LABS_E_INVAL, "K=%d out of [2, %d]", p->K, LABS_MAX_K);
@@ -44,6 +49,8 @@ int check_memetic(labs_handle *h, const labs_memetic_params *p) {
         return fail(h, LABS_E_INVAL, "unknown mode %d", p->mode);
     if (p->chunk < 1 || p->chunk > (1 << 20)) return fail(h, LABS_E_INVAL, "chunk out of [1, 2^20]");
     if (p->stop_all != 0 && p->stop_all != 1) return fail(h, LABS_E_INVAL, "stop_all must be 0 or 1");
+    if (p->waves_per_replica < 0 || p->waves_per_replica > 2)
+        return fail(h, LABS_E_INVAL, "waves_per_replica must be 0, 1 or 2");
     return LABS_OK;
 }
 
@@ -131,7 +138,13 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
     a.st = st;
     a.any_hit = d_flag;
     a.classes = 0;
-    for (int i = 0; i < pops; ++i) a.classes |= (ns_host ? ns_host[i] : n_uniform) > 64 ? 2 : 1;
+    int64_t n_wide = 0;
+    for (int i = 0; i < pops; ++i) {
+        const bool wide = (ns_host ? ns_host[i] : n_uniform) > 64;
+        a.classes |= wide ? 2 : 1;
+        n_wide += wide;
+    }
+    a.split_wide = split_wide(h, p->waves_per_replica, n_wide);
     if ((e = launch_fill_u32(d_flag, 0u, 1, s)) != hipSuccess) return hip_fail(h, e, "fill");
     if ((e = launch_memetic_init(a, s)) != hipSuccess) return hip_fail(h, e, "memetic init");
 
@@ -147,7 +160,8 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
         const int64_t n_launch = std::min<int64_t>(chunk, G);
         e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(h, e, "hipStreamBeginCapture");
-        for (int64_t i = 0; i < n_launch && e == hipSuccess; ++i) e = launch_memetic_advance(one, s);
+        for (int64_t i = 0; i < n_launch && e == hipSuccess; ++i)
+            e = launch_memetic_advance(one, s, h->side, h->fork_event, h->join_event);
         hipError_t e2 = hipStreamEndCapture(s, &graph);
         if (e != hipSuccess || e2 != hipSuccess) {
             if (graph) hipGraphDestroy(graph);
@@ -166,7 +180,8 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
         if (p->mode == LABS_MODE_PLAIN) {
             MemeticLaunchArgs one = a;
             one.gens = 1;
-            for (int64_t i = 0; i < step && e == hipSuccess; ++i) e = launch_memetic_advance(one, s);
+            for (int64_t i = 0; i < step && e == hipSuccess; ++i)
+                e = launch_memetic_advance(one, s, h->side, h->fork_event, h->join_event);
         } else if (p->mode == LABS_MODE_GRAPH) {
             // Launches beyond a replica's generation limit return at once, so
             // the final replay may safely run past G.
@@ -174,7 +189,7 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
         } else {
             MemeticLaunchArgs many = a;
             many.gens = (int32_t)step;
-            e = launch_memetic_advance(many, s);
+            e = launch_memetic_advance(many, s, h->side, h->fork_event, h->join_event);
         }
         if (e != hipSuccess) {
             rc = hip_fail(h, e, "memetic advance");

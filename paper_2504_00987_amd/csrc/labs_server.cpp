@@ -51,6 +51,8 @@ struct labs_server {
     labs_memetic_params params{};
     int max_slots = 0;
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;  // N <= 64 replicas, concurrent with the rest
+    hipEvent_t fork = nullptr, join = nullptr;
     // device: [slots table][init table][state]
     void *dmem = nullptr;
     MemeticSlot *d_slots = nullptr;
@@ -122,8 +124,12 @@ int labs_server::iterate(std::unique_lock<std::mutex> &lk) {
     for (int s = 0; s < max_slots; ++s) any |= owner[s] >= 0;
     if (!any) return 0;  // idle
     int classes = 0;
+    int64_t n_wide = 0;
     for (int s = 0; s < max_slots; ++s)
-        if (owner[s] >= 0) classes |= h_slots[s].n > 64 ? 2 : 1;
+        if (owner[s] >= 0) {
+            classes |= h_slots[s].n > 64 ? 2 : 1;
+            n_wide += h_slots[s].n > 64;
+        }
     const int n_init = (int)fresh.size();
     for (int i = 0; i < n_init; ++i) h_init[i] = h_slots[fresh[i]];
     lk.unlock();
@@ -152,7 +158,8 @@ int labs_server::iterate(std::unique_lock<std::mutex> &lk) {
     a.n_slots = max_slots;
     a.gens = params.chunk;
     a.classes = classes;
-    if (e == hipSuccess) e = launch_memetic_advance(a, stream);
+    a.split_wide = split_wide(h, params.waves_per_replica, n_wide);
+    if (e == hipSuccess) e = launch_memetic_advance(a, stream, side, fork, join);
     if (e == hipSuccess) e = hipMemcpyAsync(h_bestE, st.bestE, max_slots * 4, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(h_gen, st.gen, max_slots * 8, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(h_hit, st.hit, max_slots * 8, hipMemcpyDeviceToHost, stream);
@@ -230,6 +237,9 @@ extern "C" int labs_server_create(labs_handle *h, const labs_memetic_params *par
     carve_state(nullptr, max_slots, params->K, &state_bytes);
     const size_t tbl = ((size_t)max_slots * sizeof(MemeticSlot) + 255) & ~(size_t)255;
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->join, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc(&s->dmem, 2 * tbl + state_bytes);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_slots, tbl, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_init, tbl, hipHostMallocDefault);
@@ -344,6 +354,9 @@ extern "C" int labs_server_destroy(labs_server *s) {
     if (s->h_gen) hipHostFree(s->h_gen);
     if (s->h_hit) hipHostFree(s->h_hit);
     if (s->h_best) hipHostFree(s->h_best);
+    if (s->fork) hipEventDestroy(s->fork);
+    if (s->join) hipEventDestroy(s->join);
+    if (s->side) hipStreamDestroy(s->side);
     if (s->stream) hipStreamDestroy(s->stream);
     delete s;
     return LABS_OK;

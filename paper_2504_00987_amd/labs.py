@@ -142,9 +142,9 @@ class Labs:
     def memetic_params(K: int, rules: Rules, generations: int, p_comb: int = P_COMB_090,
                        mut_rule: int = MUT_INV_N, p_mut: int = 0, target: int = -1,
                        mode: int = PERSISTENT, chunk: int = 64,
-                       stop_all: int = 0) -> _lib.MemeticParams:
+                       stop_all: int = 0, waves_per_replica: int = 0) -> _lib.MemeticParams:
         return _lib.MemeticParams(K, p_comb, mut_rule, p_mut, tabu_params(rules), generations,
-                                  target, mode, chunk, stop_all)
+                                  target, mode, chunk, stop_all, waves_per_replica)
 
     def memetic_run(self, K: int, rules: Rules, generations: int, pops: int, seed: int,
                     ns=None, n_uniform: int = 0, out_stride: int = 128, stream=None,

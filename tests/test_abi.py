@@ -53,7 +53,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.TabuParams) == 40
     assert ctypes.sizeof(_lib.Launch) == 12
     # K, p_comb, mut_rule, p_mut (16) + tabu (40) + generations (8, aligned at 56) + 4 ints
-    assert ctypes.sizeof(_lib.MemeticParams) == 80
+    assert ctypes.sizeof(_lib.MemeticParams) == 88
 
 
 def test_product_package_never_imports_the_oracle():

@@ -203,12 +203,18 @@ def test_invalid_arguments(lb):
 # Alg. 1 / Alg. 3: memetic replicas
 # ---------------------------------------------------------------------------
 def _oracle_memetic(n_list, K, rules, gens, seed, target=-1, p_comb=I.P_COMB_090):
-    out = []
-    for p, n in enumerate(n_list):
-        st = O.MemeticState(int(n), K, seed, p)
-        st.advance(gens, osched(rules), p_comb, O.p_mut_inv_n(int(n)), target=target)
-        out.append(st)
-    return out
+    # replicas are independent: one oracle replica per worker thread (the
+    # oracle's C code releases the interpreter lock)
+    import concurrent.futures as cf
+
+    def one(p):
+        n = int(n_list[p])
+        st = O.MemeticState(n, K, seed, p)
+        st.advance(gens, osched(rules), p_comb, O.p_mut_inv_n(n), target=target)
+        return st
+
+    with cf.ThreadPoolExecutor(max_workers=16) as ex:
+        return list(ex.map(one, range(len(n_list))))
 
 
 @pytest.mark.parametrize("mode", [0, 1, 2])
@@ -226,11 +232,16 @@ def test_memetic_n20_modes(lb, mode):
         assert res.gens_done[p].item() == wl.generations and res.hit_gen[p].item() == -1
 
 
-def test_memetic_uneven_lengths(lb):
+@pytest.mark.parametrize("mode,waves", [(0, 1), (1, 1), (2, 1), (0, 2), (1, 2), (2, 2)])
+def test_memetic_uneven_lengths(lb, mode, waves):
+    # both length classes: their kernels run on two forked streams (captured
+    # into the graph in mode 1); replicas with N > 64 on one or two
+    # wavefronts each
     ns = np.array([3, 7, 31, 64, 65, 96, 120, 128], dtype=np.int32)
-    say(f"memetic ragged N={list(ns)}, K=24, 12 generations")
+    say(f"memetic ragged N={list(ns)}, K=24, 12 generations, mode {mode}, {waves} waves")
     rules = I.RULES_MEMETIC
-    res = lb.memetic_run(24, rules, 12, len(ns), 77, ns=ns, mode=2, chunk=5)
+    res = lb.memetic_run(24, rules, 12, len(ns), 77, ns=ns, mode=mode, chunk=5,
+                         waves_per_replica=waves)
     ref = _oracle_memetic(ns, 24, rules, 12, 77)
     for p, st in enumerate(ref):
         n = int(ns[p])
@@ -259,15 +270,21 @@ def test_memetic_target_and_stop_all(lb):
         assert g == (st.gen if st.hit >= 0 and st.hit <= stop else stop)
 
 
-def test_memetic_n120_prefix(lb):
+@pytest.mark.parametrize("mode,chunk,waves", [(1, 3, 1), (2, 64, 0)])
+def test_memetic_n120_prefix(lb, mode, chunk, waves):
+    # the N=120 configuration at full width (256 replicas of K=100) for its
+    # first generations; (2, 64, 0) is the launch form the benchmark times
     wl = I.MEMETIC_N120
-    pops, gens = 16, 6
-    say(f"memetic N=120 K=100: {pops} replicas x {gens} generations, graph mode")
-    res = lb.memetic_run(wl.K, wl.rules, gens, pops, wl.seed, n_uniform=wl.n, mode=1, chunk=3)
+    pops, gens = wl.pops, 24
+    say(f"memetic N=120 K=100: {pops} replicas x {gens} generations, mode {mode}, waves {waves}")
+    res = lb.memetic_run(wl.K, wl.rules, gens, pops, wl.seed, n_uniform=wl.n, mode=mode,
+                         chunk=chunk, waves_per_replica=waves)
     ref = _oracle_memetic([wl.n] * pops, wl.K, wl.rules, gens, wl.seed)
+    be = res.best_e.cpu().numpy()
+    bs = res.best_seq.cpu().numpy()
     for p, st in enumerate(ref):
-        assert res.best_e[p].item() == st.bestE
-        assert np.array_equal(res.best_seq[p, :120].cpu().numpy(), st.best)
+        assert be[p] == st.bestE
+        assert np.array_equal(bs[p, :120], st.best)
 
 
 # ---------------------------------------------------------------------------
