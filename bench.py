@@ -43,8 +43,20 @@ KERNEL_SOURCES = ("paper_2504_00987_amd/csrc/labs_device.hpp",
 # digest is recorded.  FETCH_SIZE / WRITE_SIZE are in KiB and are scaled by
 # what the same counters read for a 256 MiB device copy (FETCH 0.5x, WRITE
 # 1.0x of the bytes moved).  The summaries live in profiles/.
-COPY_SCALE = {"FETCH_SIZE": 262144 / 131084, "WRITE_SIZE": 262144 / 262144}
-COUNTERS = {}
+COPY_SCALE = {"FETCH_SIZE": 262144 / 131087, "WRITE_SIZE": 262144 / 262144}
+COUNTERS = {
+    # sums over the kernels of one launch (two for the uneven batch: N > 64
+    # and N <= 64 run concurrently)
+    "tabu_n64": {"digest": "e54bec05ce915136", "FETCH_SIZE": 50, "WRITE_SIZE": 768,
+                 "SQ_INSTS_VALU": 78372864, "SQ_INSTS_LDS": 14745600,
+                 "SQ_LDS_BANK_CONFLICT": 1048576,
+                 "source": "profiles/tabu_kernel_counters.md"},
+    "tabu_uneven": {"digest": "e54bec05ce915136", "FETCH_SIZE": 289 + 159,
+                    "WRITE_SIZE": 1074 + 343, "SQ_INSTS_VALU": 332996916 + 24023612,
+                    "SQ_INSTS_LDS": 68310232 + 4466048,
+                    "SQ_LDS_BANK_CONFLICT": 43530477 + 3506533,
+                    "source": "profiles/tabu_kernel_counters.md"},
+}
 
 
 def kernel_digest() -> str:
@@ -232,7 +244,7 @@ def ttt_section(args, lb):
     return res
 
 
-def cpu_memetic(args, n_gens_sample: int = 64):
+def cpu_memetic(args, n_gens_sample: int = 256):
     # The oracle's memetic replicas at the same size, one thread per replica
     # group (each replica is independent), timed on a bounded number of
     # generations; its time to a target reached at generation g is g times
@@ -317,14 +329,14 @@ def main() -> int:
     ap.add_argument("--cpu-min-s", type=float, default=10.0, help="minimum oracle timing")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-target section")
     ap.add_argument("--ttt-gens", type=int, default=100000)
-    ap.add_argument("--ttt-targets", default="1200,1107")
+    ap.add_argument("--ttt-targets", default="1200,1107,1028")
     ap.add_argument("--ttt-modes", default="persistent,graph,plain")
     ap.add_argument("--ttt-chunk", type=int, default=64)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
-    ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=8192)
     ap.add_argument("--serve-chunk", type=int, default=25)
-    ap.add_argument("--serve-rates", default="0.5,0.9")
+    ap.add_argument("--serve-rates", default="0.1,0.25,0.5,0.75,0.9,1.1")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (the reference kernel "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
