@@ -442,6 +442,31 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
         small[w] = right_big ? left : right;
     }
 
+    // The byte update after a move writes the new s_pick into the 16
+    // records holding P[pick] (lanes 0..15: byte c of record pick - c), the
+    // 16 holding Q[N-1-pick] (lanes 16..31) and the plain copies (lanes 32,
+    // 33): offset from RP = upd_a + upd_b * pick.  Records down to -15 are
+    // spare, so no lane tests bounds.
+    int upd_a, upd_b;
+    {
+        const int c = lane & 15;
+        const int pln = 2 * kRunBytes - 16 * kSpareRecords;  // PP - RP
+        if (lane < 16) {
+            upd_a = -15 * c;
+            upd_b = 16;
+        } else if (lane < 32) {
+            upd_a = kRunBytes + 16 * (N - 1) - 15 * c;
+            upd_b = -16;
+        } else if (lane == 32) {
+            upd_a = pln;
+            upd_b = 1;
+        } else {
+            upd_a = pln + Cfg::LEN + N - 1;
+            upd_b = -1;
+        }
+    }
+    const bool updater = part == 0 && lane < 34;
+
     int tabu[NL];
 #pragma unroll
     for (int w = 0; w < NL; ++w) tabu[w] = 0;
@@ -575,19 +600,9 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
             if (part == 0) trace[t - 1] = (int16_t)pick;  // uniform store
         }
 
-        // New s_pick into every record that holds it: P[pick] is byte c of
-        // record pick - c (lanes 0..15), Q[N-1-pick] byte c of record
-        // N-1-pick-c (lanes 16..31); and into the plain copies (lanes 32,
-        // 33).  Then the next step's window chunks are requested at once.
-        if (part == 0) {
-            const int c = lane & 15;
-            const bool fwd = lane < 16 || lane == 32;
-            const int y = fwd ? pick : N - 1 - pick;
-            // record y - c >= -15 (a spare record when negative), byte c
-            const int rec = (fwd ? 0 : kRunBytes) + 16 * (y - c) + c;
-            const int pln = 2 * kRunBytes - 16 * kSpareRecords + (fwd ? 0 : Cfg::LEN) + y;
-            if (lane < 34) RP[lane < 32 ? rec : pln] = (uint8_t)(int8_t)(-sm);
-        }
+        // New s_pick into every record and plain copy that holds it; then
+        // the next step's window chunks are requested at once.
+        if (updater) RP[upd_a + upd_b * pick] = (uint8_t)(int8_t)(-sm);
         if constexpr (kPipelineWindows) {
             wave_sync();
 #pragma unroll

@@ -280,9 +280,14 @@ __device__ void memetic_replica(const MemeticLaunchArgs &a, const MemeticSlot &s
 
 // Replicas of one length class: N <= 64 (NW = 1) or 64 < N <= 128 (NW = 2),
 // one workgroup of SPLIT wavefronts per replica; slots of the other class
-// and idle slots return at once.
+// and idle slots return at once.  The two-wavefront form only runs when
+// there are at most two replicas per compute unit, so it is compiled for
+// latency (all of a step's LDS reads in flight at once) rather than for
+// occupancy.
 template <int NW, int SPLIT>
-__global__ __launch_bounds__(64 * SPLIT) void memetic_advance_kernel(MemeticLaunchArgs a) {
+__global__ __launch_bounds__(64 * SPLIT)
+__attribute__((amdgpu_waves_per_eu(1, SPLIT == 2 ? 2 : 8))) void memetic_advance_kernel(
+    MemeticLaunchArgs a) {
     __shared__ uint64_t pop[kMaxK][2];
     __shared__ int popE[kMaxK];
     __shared__ __attribute__((aligned(16))) uint8_t lds[walk_lds_bytes<NW>()];
