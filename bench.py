@@ -91,6 +91,30 @@ def tabu_section(args, lb, wl):
     kw = dict(n_uniform=wl.n) if uniform else dict(ns=ns)
     stream = torch.cuda.current_stream()
 
+    def launch_ms(reps):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
+            lb.tabu_batch(wl.rules, W, wl.seed, out=out, stream=stream, **kw)
+            b.record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    tune = None
+    if not args.no_autotune:
+        # the library's autotuner over the workload's length range; the
+        # untuned default is timed first for comparison
+        n_lo, n_hi = int(ns.min()), int(ns.max())
+        default_launch = lb.get_launch(n_hi)
+        launch_ms(2)
+        default_ms = launch_ms(10)
+        t0 = time.perf_counter()
+        tried = lb.autotune(wl.rules, n_lo, n_hi, W, seed=wl.seed + 17)
+        tune = {"range": [n_lo, n_hi], "configurations_timed": tried,
+                "seconds": time.perf_counter() - t0,
+                "default_launch": list(default_launch), "default_kernel_ms": default_ms}
+
     for _ in range(args.warmup):
         lb.tabu_batch(wl.rules, W, wl.seed, out=out, stream=stream, **kw)
     torch.cuda.synchronize()
@@ -163,6 +187,9 @@ def tabu_section(args, lb, wl):
         },
         "roofline": roof,
     }
+    if tune is not None:
+        tune["chosen_launch"] = list(launch)
+        line["config"]["autotune"] = tune
     return line, ns
 
 
@@ -325,6 +352,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="tabu_n64", choices=["tabu_n64", "tabu_uneven"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default launch configuration instead of the tuned one")
     ap.add_argument("--cpu-walks", type=int, default=0, help="oracle sample size (0: all walks)")
     ap.add_argument("--cpu-min-s", type=float, default=10.0, help="minimum oracle timing")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-target section")

@@ -138,6 +138,32 @@ def test_tabu_launch_invariance(lb, launch):
     assert np.array_equal(res.best_seq.cpu().numpy(), best)
 
 
+def test_autotune_then_parity():
+    # the autotuner times every launch configuration and keeps the fastest
+    # for the length bucket of the range's longest walk; results stay
+    # bit-identical under the chosen configuration
+    from paper_2504_00987_amd.labs import Labs
+    say("autotune over N in [48, 120], then parity under the tuned launch")
+    h = Labs(0)
+    try:
+        rules = I.rules_tabu(3)
+        before = h.get_launch(120)
+        tried = h.autotune(rules, 48, 120, 512, seed=3)
+        assert tried == 15
+        wpg, pers, gpc = h.get_launch(120)
+        assert wpg in (1, 2, 4) and pers in (0, 1)
+        assert (not pers and gpc == 0) or (pers and gpc * wpg in (4, 8, 16, 32))
+        assert before == (1, 0, 0)
+        ns = I.uneven_lengths(200, 48, 120, seed=23)
+        res = h.tabu_batch(rules, len(ns), 1002, ns=ns)
+        best, be, fe = O.tabu_batch(len(ns), osched(rules), 1002, ns=ns, stride=128, nthreads=8)
+        assert np.array_equal(res.best_e.cpu().numpy(), be)
+        assert np.array_equal(res.final_e.cpu().numpy(), fe)
+        assert np.array_equal(res.best_seq.cpu().numpy(), best)
+    finally:
+        h.close()
+
+
 def test_tabu_n64_full_size(lb):
     wl = I.TABU_N64
     say(f"tabu: {wl.name} full size W={wl.walks} N={wl.n}, all walks against the oracle")
