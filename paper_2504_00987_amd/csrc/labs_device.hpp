@@ -516,30 +516,29 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
 #pragma unroll
         for (int r = 0; r < Cfg::NBIG; ++r) cc[r] = ((const uint4 *)CB)[r];
 
-        // Score the neighbours this lane owns (independent accumulators).
+        // Score the neighbours this lane owns.  The key is
+        // d_j = 2 u_j - s_j v_j, so that candE_j = E + 4 (N - 1) + 4 d_j;
+        // aspiration (candE_j < bestE) is d_j < thr.  Energies are all
+        // congruent mod 4, so thr is exact.
+        const int thr = ((bestE - E) >> 2) - (N - 1);
         int key[NL];
 #pragma unroll
         for (int w = 0; w < NL; ++w) {
             const int j = lane + 64 * half(w);
-            int vb0 = 0, vb1 = 0, vs = 0;  // sum_k t_jk C_k, split
-            int u = 0;                     // sum_k s_{j+k} s_{j-k}
+            int v = 0;  // sum_k t_jk C_k
+            int u = 0;  // sum_k s_{j+k} s_{j-k}
 #pragma unroll
             for (int r = 0; r < Cfg::NBIG; ++r) {
-                if (r & 1)
-                    vb1 = dot16(wb[w][r], cc[r], vb1);
-                else
-                    vb0 = dot16(wb[w][r], cc[r], vb0);
+                v = dot16(wb[w][r], cc[r], v);
                 if (r < Cfg::NSMALL) {
-                    vs = dot16(ws[w][r], cc[r], vs);
+                    v = dot16(ws[w][r], cc[r], v);
                     u = dot16(wb[w][r], ws[w][r], u);
                 }
             }
-            const int v = vb0 + vb1 + vs;
             const uint64_t mw = half(w) == 0 ? mask_lo(M) : mask_hi(M);
-            const int sv = lane_bit(mw) ? -v : v;  // s_j * v
-            const int cand = E + 4 * (N - 1 + 2 * u - sv);
-            const bool admissible = tabu[w] < t || (aspiration && cand < bestE);
-            key[w] = j < N && admissible ? cand : INT_MAX;
+            const int d = 2 * u + (lane_bit(mw) ? v : -v);  // 2 u_j - s_j v_j
+            const bool admissible = tabu[w] < t || (aspiration && d < thr);
+            key[w] = j < N && admissible ? d : INT_MAX;
         }
 
         // Admissible minimum, ties broken by the step's draw: the r-th
@@ -569,20 +568,33 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
             T0 = part == 0 ? a : b;
             T1 = part == 0 ? b : a;
         }
-        const int c0 = __popcll(T0);
         const uint32_t u0 = readlane_u(dr0, slot);
         const uint32_t u1 = readlane_u(dr1, slot);
-        int r = (int)below(u0, (uint32_t)(c0 + __popcll(T1)));
         uint64_t tied = T0;
         int pick_base = 0;
         if constexpr (NW == 2) {
-            if (r >= c0) {
+            if (T0 == 0ull) {
                 tied = T1;
                 pick_base = 64;
-                r -= c0;
             }
         }
-        for (int i = 0; i < r; ++i) tied &= tied - 1ull;  // drop the r lowest
+        // several tied moves: take the r-th (counts in 32-bit halves keep
+        // the test on the scalar unit)
+        const int c0 = __popc((uint32_t)T0) + __popc((uint32_t)(T0 >> 32));
+        const int count = c0 + __popc((uint32_t)T1) + __popc((uint32_t)(T1 >> 32));
+        if (count > 1) {
+            int r = (int)below(u0, (uint32_t)count);
+            tied = T0;
+            pick_base = 0;
+            if constexpr (NW == 2) {
+                if (r >= c0) {
+                    tied = T1;
+                    pick_base = 64;
+                    r -= c0;
+                }
+            }
+            for (int i = 0; i < r; ++i) tied &= tied - 1ull;  // drop the r lowest
+        }
         const int pick = pick_base + __builtin_ctzll(tied);
 
         // Apply the move: tenure, sequence, energy, best.
@@ -591,7 +603,7 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
         for (int w = 0; w < NL; ++w) tabu[w] = pick == lane + 64 * half(w) ? t + tenure : tabu[w];
         const int sm = 1 - 2 * m_bit(M, pick);  // old s_pick
         M = m_xor(M, m_onebit(M, pick));
-        E = m;
+        E += 4 * (N - 1 + m);
         if (E < bestE) {
             bestE = E;
             best = M;
