@@ -98,20 +98,34 @@ void PinBuf::release() {
 
 // The workspace (ns/order/counter arrays and staging) is shared by calls on
 // any stream: a new user waits for the previous user's completion event.
-int ws_acquire(labs_handle *h, hipStream_t s) {
-    if (h->ws_event_valid) {
-        hipError_t e = hipEventSynchronize(h->ws_event);  // staging is host-visible
-        if (e != hipSuccess) return hip_fail(h, e, "hipEventSynchronize");
-        e = hipStreamWaitEvent(s, h->ws_event, 0);
-        if (e != hipSuccess) return hip_fail(h, e, "hipStreamWaitEvent");
-    }
-    return LABS_OK;
+int ws_acquire(labs_handle *h, hipStream_t s, size_t bytes) {
+    if (!h->ws_event_valid) return h->ws.reserve(h, bytes);
+    hipError_t e = hipSuccess;
+    if (bytes > h->ws.size) e = hipEventSynchronize(h->ws_event);  // about to be freed
+    else e = hipStreamWaitEvent(s, h->ws_event, 0);  // the GPU orders the reuse
+    if (e != hipSuccess) return hip_fail(h, e, "workspace wait");
+    return h->ws.reserve(h, bytes);
 }
 
 int ws_release(labs_handle *h, hipStream_t s) {
     hipError_t e = hipEventRecord(h->ws_event, s);
     if (e != hipSuccess) return hip_fail(h, e, "hipEventRecord");
     h->ws_event_valid = true;
+    return LABS_OK;
+}
+
+int stage_acquire(labs_handle *h, size_t bytes) {
+    if (h->stage_event_valid) {
+        hipError_t e = hipEventSynchronize(h->stage_event);
+        if (e != hipSuccess) return hip_fail(h, e, "staging wait");
+    }
+    return h->pin.reserve(h, bytes);
+}
+
+int stage_release(labs_handle *h, hipStream_t s) {
+    hipError_t e = hipEventRecord(h->stage_event, s);
+    if (e != hipSuccess) return hip_fail(h, e, "hipEventRecord");
+    h->stage_event_valid = true;
     return LABS_OK;
 }
 
@@ -231,9 +245,14 @@ int labs_create(labs_handle **out, int device) {
     h->arch = prop.gcnArchName;
     if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&h->side2, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&h->side3, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&h->ws_event, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->stage_event, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&h->fork_event, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->join_event, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&h->join_event, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->join2_event, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->join3_event, hipEventDisableTiming) != hipSuccess) {
         delete h;
         return LABS_E_HIP;
     }
@@ -250,10 +269,15 @@ int labs_destroy(labs_handle *h) {
     h->mem.release();
     h->pin.release();
     if (h->ws_event) hipEventDestroy(h->ws_event);
+    if (h->stage_event) hipEventDestroy(h->stage_event);
     if (h->fork_event) hipEventDestroy(h->fork_event);
     if (h->join_event) hipEventDestroy(h->join_event);
+    if (h->join2_event) hipEventDestroy(h->join2_event);
+    if (h->join3_event) hipEventDestroy(h->join3_event);
     if (h->stream) hipStreamDestroy(h->stream);
     if (h->side) hipStreamDestroy(h->side);
+    if (h->side2) hipStreamDestroy(h->side2);
+    if (h->side3) hipStreamDestroy(h->side3);
     delete h;
     return LABS_OK;
 }
@@ -370,33 +394,42 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
     const labs_launch L = force ? *force : choose_launch(h, n_max, uneven);
 
     DeviceGuard g(h->device);
-    int rc = ws_acquire(h, s);
+    // Workspace: [queue heads (512 B)] [ns (W int32)] [order (W int32)].
+    // The GPU orders its reuse after the previous call's kernels; the host
+    // only waits for the previous copy out of the pinned staging buffer.
+    constexpr size_t kHeads = 32 * sizeof(uint32_t) * kWalkClasses;
+    const size_t bytes = kHeads + (ns_host ? 2 * (size_t)W * sizeof(int32_t) : 0);
+    int rc = ws_acquire(h, s, bytes);
     if (rc) return rc;
-    // Workspace: [counter (256 B)] [ns (W int32)] [order (W int32)]
-    const size_t bytes = 256 + (ns_host ? 2 * (size_t)W * sizeof(int32_t) : 0);
-    if ((rc = h->ws.reserve(h, bytes))) return rc;
     TabuLaunchArgs a;
     std::memset(&a, 0, sizeof(a));
     a.counter = (uint32_t *)h->ws.ptr;
     if (ns_host) {
-        if ((rc = h->pin.reserve(h, 2 * (size_t)W * sizeof(int32_t)))) return rc;
+        if ((rc = stage_acquire(h, 2 * (size_t)W * sizeof(int32_t)))) return rc;
         int32_t *pn = (int32_t *)h->pin.ptr;
         int32_t *po = pn + W;
         std::memcpy(pn, ns_host, (size_t)W * sizeof(int32_t));
-        // Longest walks first (cost grows like N^3 at fixed steps per N).
-        std::iota(po, po + W, 0);
-        std::stable_sort(po, po + W, [&](int32_t x, int32_t y) { return pn[x] > pn[y]; });
-        int32_t *dn = (int32_t *)((char *)h->ws.ptr + 256);
+        // Longest walks first (cost grows like N^3 at fixed steps per N):
+        // a counting sort by N, stable within equal N.
+        int64_t start[LABS_MAX_N + 2] = {0};
+        for (int64_t i = 0; i < W; ++i) ++start[LABS_MAX_N - ns_host[i] + 1];
+        for (int k = 1; k <= LABS_MAX_N + 1; ++k) start[k] += start[k - 1];
+        for (int64_t i = 0; i < W; ++i) po[start[LABS_MAX_N - ns_host[i]]++] = (int32_t)i;
+        int32_t *dn = (int32_t *)((char *)h->ws.ptr + kHeads);
         hipError_t e = hipMemcpyAsync(dn, pn, 2 * (size_t)W * sizeof(int32_t),
                                       hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(h, e, "hipMemcpyAsync");
+        if ((rc = stage_release(h, s))) return rc;
         a.ns = dn;
         a.order = dn + W;
-        int64_t wide = 0;
-        for (int64_t i = 0; i < W; ++i) wide += ns_host[i] > 64;
-        a.n_wide = wide;
+        // the order is longest first, so the classes are consecutive runs
+        int64_t count[kWalkClasses] = {0, 0, 0, 0};
+        for (int64_t i = 0; i < W; ++i) ++count[walk_class(ns_host[i])];
+        int64_t end = 0;
+        for (int c = 0; c < kWalkClasses; ++c) a.class_end[c] = end += count[c];
     } else {
-        a.n_wide = n_uniform > 64 ? W : 0;
+        const int cls = walk_class(n_uniform);
+        for (int c = 0; c < kWalkClasses; ++c) a.class_end[c] = c >= cls ? W : 0;
     }
     a.starts = starts;
     a.start_stride = start_stride;
@@ -413,22 +446,31 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
     a.trace = trace;
     a.trace_stride = trace_stride;
     const int groups = L.persistent ? persistent_groups(h, L) : 0;
-    // A batch with both length classes runs them concurrently: the narrow
-    // part on the handle's side stream, joined back into `s`.
-    const bool split = a.n_wide > 0 && a.n_wide < W;
-    hipStream_t s2 = split ? h->side : s;
-    if (split) {
-        hipError_t e = hipEventRecord(h->fork_event, s);
-        if (e == hipSuccess) e = hipStreamWaitEvent(s2, h->fork_event, 0);
-        if (e != hipSuccess) return hip_fail(h, e, "fork to side stream");
+    // The length classes present run concurrently: the first on `s`, the
+    // others on the handle's side streams, forked from and joined into `s`.
+    hipStream_t sides[3] = {h->side, h->side2, h->side3};
+    hipEvent_t joins[3] = {h->join_event, h->join2_event, h->join3_event};
+    hipStream_t streams[kWalkClasses];
+    int n_sides = 0;
+    for (int c = 0, used = 0; c < kWalkClasses; ++c) {
+        const int64_t begin = c ? a.class_end[c - 1] : 0;
+        streams[c] = s;
+        if (a.class_end[c] > begin && used++ > 0) streams[c] = sides[n_sides++];
     }
-    hipError_t e = launch_tabu(a, L.waves_per_group, groups, s, s2);
+    hipError_t e = hipSuccess;
+    if (n_sides > 0) {
+        e = hipEventRecord(h->fork_event, s);
+        for (int i = 0; i < n_sides && e == hipSuccess; ++i)
+            e = hipStreamWaitEvent(sides[i], h->fork_event, 0);
+        if (e != hipSuccess) return hip_fail(h, e, "fork to side streams");
+    }
+    e = launch_tabu(a, L.waves_per_group, groups, streams);
     if (e != hipSuccess) return hip_fail(h, e, "tabu kernel launch");
-    if (split) {
-        e = hipEventRecord(h->join_event, s2);
-        if (e == hipSuccess) e = hipStreamWaitEvent(s, h->join_event, 0);
-        if (e != hipSuccess) return hip_fail(h, e, "join from side stream");
+    for (int i = 0; i < n_sides && e == hipSuccess; ++i) {
+        e = hipEventRecord(joins[i], sides[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, joins[i], 0);
     }
+    if (e != hipSuccess) return hip_fail(h, e, "join from side streams");
     return ws_release(h, s);
 }
 

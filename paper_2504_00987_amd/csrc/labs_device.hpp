@@ -288,11 +288,11 @@ struct WalkResult {
 // NBIG - 1 chunks); LEN the farthest byte the C update reads.
 template <int NW> struct WalkLds;
 template <> struct WalkLds<1> {
-    static constexpr int NBIG = 4, NSMALL = 2, LEN = 128, CLEN = 64;
+    static constexpr int NBIG = 4, LEN = 128, CLEN = 64;
     static constexpr int NREC = 64 + 16 * (NBIG - 1) + 1;
 };
 template <> struct WalkLds<2> {
-    static constexpr int NBIG = 8, NSMALL = 4, LEN = 256, CLEN = 128;
+    static constexpr int NBIG = 8, LEN = 256, CLEN = 128;
     static constexpr int NREC = 128 + 16 * (NBIG - 1) + 1;
 };
 constexpr int kSpareRecords = 15;
@@ -348,7 +348,7 @@ __device__ __forceinline__ void walk_sync() {
 //   trace  with TRACE: trace[t-1] = flipped index
 // Every lane of the walk's wavefronts must call this with identical uniform
 // inputs (part aside).
-template <int NW, bool TRACE = false, int SPLIT = 1>
+template <int NW, bool TRACE = false, int SPLIT = 1, int NB = WalkLds<NW>::NBIG>
 __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typename MaskOf<NW>::type M0,
                                                     const Schedule sch_in, const int aspiration_in,
                                                     const uint32_t k0, const uint32_t k1,
@@ -357,6 +357,8 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
                                                     int16_t *__restrict__ trace,
                                                     const int part_in = 0) {
     static_assert(SPLIT == 1 || (SPLIT == 2 && NW == 2), "two wavefronts per walk need N <= 128");
+    static_assert(NB >= 1 && NB <= WalkLds<NW>::NBIG, "chunk count beyond the layout");
+    constexpr int NS = (NB + 1) / 2;  // chunks of the shorter window (N - 1 <= 16 NB)
     using Mask = typename MaskOf<NW>::type;
     using Cfg = WalkLds<NW>;
     constexpr int NL = NW / SPLIT;  // neighbours per lane
@@ -480,16 +482,16 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
     // the registers for early loads would cost occupancy; two wavefronts:
     // the other one's byte update must be visible first).
     constexpr bool kPipelineWindows = NW == 1 && SPLIT == 1;
-    uint4 wb[NL][Cfg::NBIG];
-    uint4 ws[NL][Cfg::NSMALL];
+    uint4 wb[NL][NB];
+    uint4 ws[NL][NS];
     if constexpr (kPipelineWindows) {
         walk_sync<SPLIT>();
 #pragma unroll
         for (int w = 0; w < NL; ++w) {
 #pragma unroll
-            for (int r = 0; r < Cfg::NBIG; ++r) wb[w][r] = ((const uint4 *)big[w])[16 * r];
+            for (int r = 0; r < NB; ++r) wb[w][r] = ((const uint4 *)big[w])[16 * r];
 #pragma unroll
-            for (int r = 0; r < Cfg::NSMALL; ++r) ws[w][r] = ((const uint4 *)small[w])[16 * r];
+            for (int r = 0; r < NS; ++r) ws[w][r] = ((const uint4 *)small[w])[16 * r];
         }
     }
 
@@ -506,15 +508,15 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
 #pragma unroll
             for (int w = 0; w < NL; ++w) {
 #pragma unroll
-                for (int r = 0; r < Cfg::NBIG; ++r) wb[w][r] = ((const uint4 *)big[w])[16 * r];
+                for (int r = 0; r < NB; ++r) wb[w][r] = ((const uint4 *)big[w])[16 * r];
 #pragma unroll
-                for (int r = 0; r < Cfg::NSMALL; ++r) ws[w][r] = ((const uint4 *)small[w])[16 * r];
+                for (int r = 0; r < NS; ++r) ws[w][r] = ((const uint4 *)small[w])[16 * r];
             }
         }
 
-        uint4 cc[Cfg::NBIG];  // C_1 .. C_{16 NBIG} (wave-uniform)
+        uint4 cc[NB];  // C_1 .. C_{16 NB} (wave-uniform)
 #pragma unroll
-        for (int r = 0; r < Cfg::NBIG; ++r) cc[r] = ((const uint4 *)CB)[r];
+        for (int r = 0; r < NB; ++r) cc[r] = ((const uint4 *)CB)[r];
 
         // Score the neighbours this lane owns.  The key is
         // d_j = 2 u_j - s_j v_j, so that candE_j = E + 4 (N - 1) + 4 d_j;
@@ -528,9 +530,9 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
             int v = 0;  // sum_k t_jk C_k
             int u = 0;  // sum_k s_{j+k} s_{j-k}
 #pragma unroll
-            for (int r = 0; r < Cfg::NBIG; ++r) {
+            for (int r = 0; r < NB; ++r) {
                 v = dot16(wb[w][r], cc[r], v);
-                if (r < Cfg::NSMALL) {
+                if (r < NS) {
                     v = dot16(ws[w][r], cc[r], v);
                     u = dot16(wb[w][r], ws[w][r], u);
                 }
@@ -620,9 +622,9 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
 #pragma unroll
             for (int w = 0; w < NL; ++w) {
 #pragma unroll
-                for (int r = 0; r < Cfg::NBIG; ++r) wb[w][r] = ((const uint4 *)big[w])[16 * r];
+                for (int r = 0; r < NB; ++r) wb[w][r] = ((const uint4 *)big[w])[16 * r];
 #pragma unroll
-                for (int r = 0; r < Cfg::NSMALL; ++r) ws[w][r] = ((const uint4 *)small[w])[16 * r];
+                for (int r = 0; r < NS; ++r) ws[w][r] = ((const uint4 *)small[w])[16 * r];
             }
         }
 

@@ -44,10 +44,16 @@ struct labs_handle {
     std::string last_error;
     hipStream_t stream = nullptr;      // internal stream (default priority)
     hipStream_t side = nullptr;        // second stream for the narrow part of a mixed batch
-    hipEvent_t ws_event = nullptr;     // completion of the last workspace user
+    hipStream_t side2 = nullptr;       // third and fourth streams: further length classes
+    hipStream_t side3 = nullptr;
+    hipEvent_t ws_event = nullptr;     // completion of the last device-workspace user
+    hipEvent_t stage_event = nullptr;  // completion of the last copy out of `pin`
     hipEvent_t fork_event = nullptr;
     hipEvent_t join_event = nullptr;
+    hipEvent_t join2_event = nullptr;
+    hipEvent_t join3_event = nullptr;
     bool ws_event_valid = false;
+    bool stage_event_valid = false;
     liblabs::DevBuf ws;                   // tabu workspace: queue head, ns, order
     liblabs::DevBuf mem;                  // memetic state and slot table
     liblabs::PinBuf pin;                  // pinned staging
@@ -60,8 +66,14 @@ namespace liblabs {
 
 int fail(labs_handle *h, int code, const char *fmt, ...);
 int hip_fail(labs_handle *h, hipError_t e, const char *where);
-int ws_acquire(labs_handle *h, hipStream_t s);
+// Device workspace `ws` of at least `bytes`, its reuse ordered after the
+// previous user on the GPU (the host waits only when it must grow).
+int ws_acquire(labs_handle *h, hipStream_t s, size_t bytes);
 int ws_release(labs_handle *h, hipStream_t s);
+// Pinned staging `pin` of at least `bytes`, once the previous copy out of it
+// has completed; stage_release marks a copy out of it on stream s.
+int stage_acquire(labs_handle *h, size_t bytes);
+int stage_release(labs_handle *h, hipStream_t s);
 int check_rule(labs_handle *h, const RuleParams &r, int n);
 long long max_steps(const RuleParams &r, int n);
 RuleParams to_rule(const labs_tabu_params &p);

@@ -21,7 +21,8 @@ struct TabuLaunchArgs {
     int32_t n_max;            // longest walk in the batch
     const int32_t *order;     // device [W] walk ids in processing order, or null
     int64_t W;
-    int64_t n_wide;           // leading positions of the order with N > 64
+    int64_t class_end[4];     // processing-order positions [class_end[c-1], class_end[c])
+                              // hold the walks of length class c (kWalkClasses)
     uint32_t k0, k1;
     RuleParams rule;
     int8_t *best_seq;
@@ -30,8 +31,14 @@ struct TabuLaunchArgs {
     int32_t *final_e;
     int16_t *trace;
     int32_t trace_stride;
-    uint32_t *counter;        // persistent queue head (device), zeroed by the launcher
+    uint32_t *counter;        // device, 32 words per class: persistent queue heads
 };
+
+// Length classes of stand-alone walks, longest first: a class fixes the
+// neighbours per lane (NW) and how many 16-lag chunks a window spans (NB).
+constexpr int kWalkClasses = 4;
+constexpr int kClassMaxN[kWalkClasses] = {128, 97, 64, 49};
+inline int walk_class(int n) { return n > 97 ? 0 : n > 64 ? 1 : n > 49 ? 2 : 3; }
 
 // Device layout of a memetic replica's state (structure of arrays).
 struct MemeticStateDev {
@@ -71,10 +78,10 @@ hipError_t launch_energy(const int8_t *seqs, const int32_t *ns, int32_t n_unifor
                          int32_t stride, int64_t count, int32_t *out, hipStream_t s);
 
 // waves_per_group in {1,2,4}; persistent grid = groups (0: one wave per walk).
-// Walks with N > 64 run on s_wide, the others on s_narrow (may be the same).
-// a.counter must point at 64 writable uint32 (two queue heads).
+// Length class c runs on streams[c] (entries may coincide); a.counter must
+// point at 32 * kWalkClasses writable uint32 (one queue head per class).
 hipError_t launch_tabu(const TabuLaunchArgs &a, int waves_per_group, int groups,
-                       hipStream_t s_wide, hipStream_t s_narrow);
+                       const hipStream_t *streams);
 
 hipError_t launch_memetic_init(const MemeticLaunchArgs &a, hipStream_t s);
 // Advances every slot by a.gens generations.  When both length classes are

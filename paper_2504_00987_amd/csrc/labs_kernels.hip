@@ -52,7 +52,7 @@ __global__ __launch_bounds__(64 * WPG) void energy_kernel(const int8_t *__restri
 // ---------------------------------------------------------------------------
 // Batched tabu walks.
 // ---------------------------------------------------------------------------
-template <int NW, bool TRACE>
+template <int NW, int NB, bool TRACE>
 __device__ void run_tabu_item(const TabuLaunchArgs &a, int64_t w, int N, uint8_t *lds) {
     using Mask = typename MaskOf<NW>::type;
     const int lane = lane_id();
@@ -78,8 +78,8 @@ __device__ void run_tabu_item(const TabuLaunchArgs &a, int64_t w, int N, uint8_t
     const Mask M = make_mask<NW>(lo, hi);
     const Schedule sch = make_schedule(a.rule, N, a.k0, a.k1, (uint32_t)w, 0u);
     const WalkResult<NW> r =
-        tabu_walk<NW, TRACE>(N, M, sch, a.rule.aspiration, a.k0, a.k1, (uint32_t)w, 0u, lds,
-                             TRACE ? a.trace + w * (int64_t)a.trace_stride : nullptr);
+        tabu_walk<NW, TRACE, 1, NB>(N, M, sch, a.rule.aspiration, a.k0, a.k1, (uint32_t)w, 0u, lds,
+                                    TRACE ? a.trace + w * (int64_t)a.trace_stride : nullptr);
     int8_t *out = a.best_seq + w * (int64_t)a.out_stride;
     for (int i = lane; i < a.out_stride; i += 64)
         out[i] = i < N ? (m_bit(r.best, i) ? (int8_t)-1 : (int8_t)1) : (int8_t)0;
@@ -98,29 +98,29 @@ __device__ __forceinline__ uint32_t next_work(uint32_t *counter) {
     return readlane_u(v, 0);
 }
 
-// Walks at positions [begin, end) of the processing order, all with
-// N <= 64 (NW = 1) or all with 64 < N <= 128 (NW = 2).  PERSIST: a grid
-// sized to the device drains the range through the queue head `counter`;
-// otherwise one wave per position.  TRACE: record every walk's moves (a
-// separate instantiation, so that the untraced kernel does not carry the
-// registers of the traced one).
-template <int NW, int WPG, bool PERSIST, bool TRACE>
+// Walks at positions [begin, end) of the processing order, all of one length
+// class: NW neighbours per lane (N <= 64 NW) and windows of NB chunks
+// (N - 1 <= 16 NB).  PERSIST: a grid sized to the device drains the range
+// through the queue head `counter`; otherwise one wave per position.
+// TRACE: record every walk's moves (a separate instantiation, so that the
+// untraced kernel does not carry the registers of the traced one).
+template <int NW, int NB, int WPG, bool PERSIST, bool TRACE>
 __global__ __launch_bounds__(64 * WPG) void tabu_kernel(TabuLaunchArgs a, int64_t begin,
-                                                        int64_t end) {
+                                                        int64_t end, uint32_t *counter) {
     __shared__ __attribute__((aligned(16))) uint8_t lds_all[WPG][walk_lds_bytes<NW>()];
     const int wave = threadIdx.x >> 6;
     uint8_t *lds = lds_all[wave];
     if constexpr (PERSIST) {
-        for (int64_t pos = begin + next_work(a.counter); pos < end;
-             pos = begin + next_work(a.counter)) {
+        for (int64_t pos = begin + next_work(counter); pos < end;
+             pos = begin + next_work(counter)) {
             const int64_t w = a.order ? (int64_t)a.order[pos] : pos;
-            run_tabu_item<NW, TRACE>(a, w, a.ns ? a.ns[w] : a.n_uniform, lds);
+            run_tabu_item<NW, NB, TRACE>(a, w, a.ns ? a.ns[w] : a.n_uniform, lds);
         }
     } else {
         const int64_t pos = begin + (int64_t)blockIdx.x * WPG + wave;
         if (pos < end) {
             const int64_t w = a.order ? (int64_t)a.order[pos] : pos;
-            run_tabu_item<NW, TRACE>(a, w, a.ns ? a.ns[w] : a.n_uniform, lds);
+            run_tabu_item<NW, NB, TRACE>(a, w, a.ns ? a.ns[w] : a.n_uniform, lds);
         }
     }
 }
@@ -337,53 +337,55 @@ hipError_t launch_energy(const int8_t *seqs, const int32_t *ns, int32_t n_unifor
 
 namespace {
 
-template <int NW, int WPG, bool TRACE>
+template <int NW, int NB, int WPG, bool TRACE>
 hipError_t launch_tabu_part_t(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
-                              hipStream_t s) {
+                              uint32_t *counter, hipStream_t s) {
     if (groups > 0) {
-        hipError_t e = launch_fill_u32(a.counter, 0u, 1, s);
+        hipError_t e = launch_fill_u32(counter, 0u, 1, s);
         if (e != hipSuccess) return e;
         const int64_t need = (end - begin + WPG - 1) / WPG;
-        hipLaunchKernelGGL((tabu_kernel<NW, WPG, true, TRACE>),
+        hipLaunchKernelGGL((tabu_kernel<NW, NB, WPG, true, TRACE>),
                            dim3((unsigned)std::min<int64_t>(groups, need)), dim3(64 * WPG), 0, s, a,
-                           begin, end);
+                           begin, end, counter);
     } else {
         const int64_t grid = (end - begin + WPG - 1) / WPG;
-        hipLaunchKernelGGL((tabu_kernel<NW, WPG, false, TRACE>), dim3((unsigned)grid),
-                           dim3(64 * WPG), 0, s, a, begin, end);
+        hipLaunchKernelGGL((tabu_kernel<NW, NB, WPG, false, TRACE>), dim3((unsigned)grid),
+                           dim3(64 * WPG), 0, s, a, begin, end, counter);
     }
     return hipGetLastError();
 }
 
-template <int NW, int WPG>
+template <int NW, int NB, int WPG>
 hipError_t launch_tabu_part(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
-                            hipStream_t s) {
+                            uint32_t *counter, hipStream_t s) {
     if (end <= begin) return hipSuccess;
-    return a.trace != nullptr ? launch_tabu_part_t<NW, WPG, true>(a, begin, end, groups, s)
-                              : launch_tabu_part_t<NW, WPG, false>(a, begin, end, groups, s);
+    return a.trace != nullptr
+               ? launch_tabu_part_t<NW, NB, WPG, true>(a, begin, end, groups, counter, s)
+               : launch_tabu_part_t<NW, NB, WPG, false>(a, begin, end, groups, counter, s);
 }
 
+// One launch per non-empty length class, each on its own stream with its
+// own queue head (32 words apart).
 template <int WPG>
-hipError_t launch_tabu_wpg(const TabuLaunchArgs &a, int groups, hipStream_t s_wide,
-                           hipStream_t s_narrow) {
-    // positions [0, n_wide) hold the walks with N > 64; each part has its
-    // own queue head (counter[0] and counter[32])
-    TabuLaunchArgs narrow = a;
-    narrow.counter = a.counter + 32;
-    hipError_t e = launch_tabu_part<2, WPG>(a, 0, a.n_wide, groups, s_wide);
-    if (e != hipSuccess) return e;
-    return launch_tabu_part<1, WPG>(narrow, a.n_wide, a.W, groups, s_narrow);
+hipError_t launch_tabu_wpg(const TabuLaunchArgs &a, int groups, const hipStream_t *st) {
+    static_assert(kWalkClasses == 4, "one launcher per class below");
+    const int64_t *ce = a.class_end;
+    hipError_t e = launch_tabu_part<2, 8, WPG>(a, 0, ce[0], groups, a.counter, st[0]);
+    if (e == hipSuccess) e = launch_tabu_part<2, 6, WPG>(a, ce[0], ce[1], groups, a.counter + 32, st[1]);
+    if (e == hipSuccess) e = launch_tabu_part<1, 4, WPG>(a, ce[1], ce[2], groups, a.counter + 64, st[2]);
+    if (e == hipSuccess) e = launch_tabu_part<1, 3, WPG>(a, ce[2], ce[3], groups, a.counter + 96, st[3]);
+    return e;
 }
 
 }  // namespace
 
 hipError_t launch_tabu(const TabuLaunchArgs &a, int waves_per_group, int groups,
-                       hipStream_t s_wide, hipStream_t s_narrow) {
+                       const hipStream_t *streams) {
     if (a.W <= 0) return hipSuccess;
     switch (waves_per_group) {
-    case 1: return launch_tabu_wpg<1>(a, groups, s_wide, s_narrow);
-    case 2: return launch_tabu_wpg<2>(a, groups, s_wide, s_narrow);
-    case 4: return launch_tabu_wpg<4>(a, groups, s_wide, s_narrow);
+    case 1: return launch_tabu_wpg<1>(a, groups, streams);
+    case 2: return launch_tabu_wpg<2>(a, groups, streams);
+    case 4: return launch_tabu_wpg<4>(a, groups, streams);
     default: return hipErrorInvalidValue;
     }
 }

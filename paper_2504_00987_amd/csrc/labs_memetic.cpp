@@ -105,8 +105,7 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
     MemeticStateDev st = carve_state(base + off_state, pops, p->K, nullptr);
 
     const size_t stage = off_flag;  // slots + ns
-    if ((rc = h->pin.reserve(h, stage))) return rc;
-    if (h->ws_event_valid) hipEventSynchronize(h->ws_event);
+    if ((rc = stage_acquire(h, stage))) return rc;
     std::memset(h->pin.ptr, 0, stage);
     MemeticSlot *hs = (MemeticSlot *)h->pin.ptr;
     int32_t *hn = (int32_t *)((char *)h->pin.ptr + off_ns);
@@ -124,7 +123,7 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
     }
     e = hipMemcpyAsync(base, h->pin.ptr, stage, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(h, e, "hipMemcpyAsync(slots)");
-    if ((rc = ws_release(h, s))) return rc;  // the staging copy is in flight
+    if ((rc = stage_release(h, s))) return rc;  // the staging copy is in flight
 
     MemeticLaunchArgs a;
     std::memset(&a, 0, sizeof(a));
