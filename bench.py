@@ -45,16 +45,18 @@ KERNEL_SOURCES = ("paper_2504_00987_amd/csrc/labs_device.hpp",
 # 1.0x of the bytes moved).  The summaries live in profiles/.
 COPY_SCALE = {"FETCH_SIZE": 262144 / 131087, "WRITE_SIZE": 262144 / 262144}
 COUNTERS = {
-    # sums over the kernels of one launch (two for the uneven batch: N > 64
-    # and N <= 64 run concurrently)
-    "tabu_n64": {"digest": "e54bec05ce915136", "FETCH_SIZE": 50, "WRITE_SIZE": 768,
-                 "SQ_INSTS_VALU": 78372864, "SQ_INSTS_LDS": 14745600,
+    # per launch in the default launch configuration (four walks per
+    # workgroup); sums over the kernels of one call (the uneven batch runs
+    # one kernel per length class, concurrently)
+    "tabu_n64": {"digest": "9286a4b529551e30", "FETCH_SIZE": 47, "WRITE_SIZE": 576,
+                 "SQ_INSTS_VALU": 67005662, "SQ_INSTS_LDS": 14745600,
                  "SQ_LDS_BANK_CONFLICT": 1048576,
                  "source": "profiles/tabu_kernel_counters.md"},
-    "tabu_uneven": {"digest": "e54bec05ce915136", "FETCH_SIZE": 289 + 159,
-                    "WRITE_SIZE": 1074 + 343, "SQ_INSTS_VALU": 332996916 + 24023612,
-                    "SQ_INSTS_LDS": 68310232 + 4466048,
-                    "SQ_LDS_BANK_CONFLICT": 43530477 + 3506533,
+    "tabu_uneven": {"digest": "9286a4b529551e30", "FETCH_SIZE": 197 + 230 + 139 + 65,
+                    "WRITE_SIZE": 452 + 661 + 300 + 43,
+                    "SQ_INSTS_VALU": 143507584 + 128937064 + 18380242 + 2080190,
+                    "SQ_INSTS_LDS": 32546042 + 28460822 + 3989164 + 409056,
+                    "SQ_LDS_BANK_CONFLICT": 22137471 + 16248306 + 2932512 + 471931,
                     "source": "profiles/tabu_kernel_counters.md"},
 }
 
@@ -101,23 +103,23 @@ def tabu_section(args, lb, wl):
         torch.cuda.synchronize()
         return float(np.mean([a.elapsed_time(b) for a, b in ev]))
 
+    for _ in range(args.warmup):
+        lb.tabu_batch(wl.rules, W, wl.seed, out=out, stream=stream, **kw)
+    torch.cuda.synchronize()
+
     tune = None
     if not args.no_autotune:
         # the library's autotuner over the workload's length range; the
-        # untuned default is timed first for comparison
+        # untuned default is timed first (after the warm-up) for comparison
         n_lo, n_hi = int(ns.min()), int(ns.max())
         default_launch = lb.get_launch(n_hi)
-        launch_ms(2)
         default_ms = launch_ms(10)
         t0 = time.perf_counter()
         tried = lb.autotune(wl.rules, n_lo, n_hi, W, seed=wl.seed + 17)
         tune = {"range": [n_lo, n_hi], "configurations_timed": tried,
                 "seconds": time.perf_counter() - t0,
                 "default_launch": list(default_launch), "default_kernel_ms": default_ms}
-
-    for _ in range(args.warmup):
-        lb.tabu_batch(wl.rules, W, wl.seed, out=out, stream=stream, **kw)
-    torch.cuda.synchronize()
+        launch_ms(2)
 
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
@@ -349,7 +351,7 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="tabu_n64", choices=["tabu_n64", "tabu_uneven"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
     ap.add_argument("--no-autotune", action="store_true",

@@ -97,7 +97,7 @@ typedef struct labs_launch {
                                 longest-first work queue; 0: one wavefront
                                 per walk */
     int32_t groups_per_cu;   /* persistent grid = groups_per_cu x CUs (0: auto) */
-} labs_launch;
+} labs_launch;               /* default (untuned): {4, 0, 0} */
 
 typedef struct labs_handle labs_handle;
 

@@ -187,9 +187,13 @@ RuleParams to_rule(const labs_tabu_params &p) {
 
 int bucket_of(int n) { return std::min(7, std::max(0, (n - 1) / 16)); }
 
+// Four walks per workgroup, one workgroup per four walks: the four
+// wavefronts land on the four SIMDs of a CU, and the results of neighbouring
+// walks are written by one workgroup (the autotuner's choice on the N=64 and
+// uneven batches).
 labs_launch default_launch(labs_handle *h, bool uneven) {
     labs_launch l;
-    l.waves_per_group = 1;
+    l.waves_per_group = 4;
     l.persistent = 0;
     l.groups_per_cu = 0;
     (void)h;
