@@ -228,15 +228,16 @@ def test_invalid_arguments(lb):
 # ---------------------------------------------------------------------------
 # Alg. 1 / Alg. 3: memetic replicas
 # ---------------------------------------------------------------------------
-def _oracle_memetic(n_list, K, rules, gens, seed, target=-1, p_comb=I.P_COMB_090):
+def _oracle_memetic(n_list, K, rules, gens, seed, target=-1, p_comb=I.P_COMB_090, p_mut=None):
     # replicas are independent: one oracle replica per worker thread (the
-    # oracle's C code releases the interpreter lock)
+    # oracle's C code releases the interpreter lock); p_mut None: 1/N
     import concurrent.futures as cf
 
     def one(p):
         n = int(n_list[p])
         st = O.MemeticState(n, K, seed, p)
-        st.advance(gens, osched(rules), p_comb, O.p_mut_inv_n(n), target=target)
+        thr = O.p_mut_inv_n(n) if p_mut is None else p_mut
+        st.advance(gens, osched(rules), p_comb, thr, target=target)
         return st
 
     with cf.ThreadPoolExecutor(max_workers=16) as ex:
@@ -273,6 +274,27 @@ def test_memetic_uneven_lengths(lb, mode, waves):
         n = int(ns[p])
         assert res.best_e[p].item() == st.bestE
         assert np.array_equal(res.best_seq[p, :n].cpu().numpy(), st.best)
+
+
+@pytest.mark.parametrize("K,p_comb,p_mut", [(2, I.P_COMB_090, None), (128, 0, None),
+                                             (37, 1 << 31, 0x30000000)])
+def test_memetic_edge_parameters(lb, K, p_comb, p_mut):
+    # smallest and largest population, sampling only (no crossover), a fixed
+    # mutation threshold; lengths at the class edges, both wavefront forms
+    from paper_2504_00987_amd.labs import MUT_FIXED, MUT_INV_N
+    ns = np.array([3, 4, 64, 65, 127, 128], dtype=np.int32)
+    rules = I.RULES_MEMETIC
+    say(f"memetic edges K={K} p_comb={p_comb} p_mut={p_mut} N={list(ns)}")
+    ref = _oracle_memetic(ns, K, rules, 7, 555, p_comb=p_comb, p_mut=p_mut)
+    for waves in (1, 2):
+        kw = dict(mut_rule=MUT_INV_N) if p_mut is None else dict(mut_rule=MUT_FIXED, p_mut=p_mut)
+        res = lb.memetic_run(K, rules, 7, len(ns), 555, ns=ns, mode=2, chunk=3, p_comb=p_comb,
+                             waves_per_replica=waves, **kw)
+        for p, st in enumerate(ref):
+            n = int(ns[p])
+            assert res.best_e[p].item() == st.bestE
+            assert np.array_equal(res.best_seq[p, :n].cpu().numpy(), st.best)
+            assert res.gens_done[p].item() == 7
 
 
 def test_memetic_target_and_stop_all(lb):
@@ -351,3 +373,40 @@ def test_server_alone_equals_mix(lb):
     ref = _oracle_memetic([n] * pops, K, rules, gens, s)
     rid = [r for r, nn, ss in ids if (nn, ss) == (n, s)][0]
     assert results[rid][1] == min(st.bestE for st in ref)
+
+
+def test_server_cancel_and_errors(lb):
+    import time
+    from paper_2504_00987_amd import _lib
+    from paper_2504_00987_amd.labs import Server
+    say("server: cancel, unknown ids, invalid requests, counters")
+    srv = Server(lb, 16, I.RULES_MEMETIC, max_slots=4, chunk=2)
+    try:
+        with pytest.raises(_lib.LabsError):
+            srv.submit(2, 1, 2, 4)           # N below 3
+        with pytest.raises(_lib.LabsError):
+            srv.submit(40, 1, 5, 4)          # more replicas than slots
+        keep = srv.submit(40, 11, 2, 30)
+        drop = srv.submit(41, 12, 4, 10**6)  # queued behind `keep`, then cancelled
+        srv.cancel(drop)
+        with pytest.raises(_lib.LabsError) as err:
+            srv.poll(999999, 40)
+        assert err.value.code == _lib.LABS_E_NOTFOUND
+        t0 = time.time()
+        got = None
+        while got is None and time.time() - t0 < 60:
+            got = srv.poll(keep, 40)
+            time.sleep(0.005)
+        assert got is not None
+        with pytest.raises(_lib.LabsError) as err:
+            srv.poll(drop, 41)
+        assert err.value.code == _lib.LABS_E_CANCELLED
+        t0 = time.time()
+        while srv.stats()[3] != 0 and time.time() - t0 < 30:  # cancelled slots are freed
+            time.sleep(0.005)
+        waiting, running, done, resident = srv.stats()
+        assert done >= 1 and waiting == 0 and running == 0 and resident == 0
+    finally:
+        srv.close()
+    alone = lb.memetic_run(16, I.RULES_MEMETIC, 30, 2, 11, n_uniform=40, mode=2, chunk=30)
+    assert got[1] == int(alone.best_e.min().item())
