@@ -133,6 +133,23 @@ int labs_energy_batch(labs_handle *h, const int8_t *seqs, const int32_t *ns,
                       int32_t *energies, void *stream);
 
 /*
+ * Exhaustive minimum of Eq. (2) over all 2^n sequences of length n
+ * (3 <= n <= LABS_MAX_BRUTE_N), the reference targets for time-to-solution
+ * at small n.  E is invariant under negation (Sec. II.B), so the 2^(n-1)
+ * sequences with s_0 = +1 are enumerated.
+ *   min_e   HOST int32: the minimum energy
+ *   count   HOST int64 (or NULL): how many of the 2^n sequences attain it
+ *   argmin  HOST int8 [n] (or NULL): of the minima with s_0 = +1, the one
+ *           whose bit pattern (bit i set <=> s_i = -1) is the smallest
+ *           integer
+ * Synchronous (on the handle's stream).  Work grows like 2^n n: n = 36
+ * takes about a second, n = 40 about fifteen.
+ */
+#define LABS_MAX_BRUTE_N 40
+int labs_bruteforce_min(labs_handle *h, int32_t n, int32_t *min_e, int64_t *count,
+                        int8_t *argmin);
+
+/*
  * Independent tabu walks (Alg. 2; the thread-parallel form of Alg. 4, one
  * walk per 64-lane wavefront).  Walk w (0 <= w < walks) starts from row w
  * of `starts`, or -- when starts == NULL -- from the 128-bit draw

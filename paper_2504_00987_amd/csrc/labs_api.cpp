@@ -310,6 +310,49 @@ int labs_energy_batch(labs_handle *h, const int8_t *seqs, const int32_t *ns, int
     return LABS_OK;
 }
 
+int labs_bruteforce_min(labs_handle *h, int32_t n, int32_t *min_e, int64_t *count,
+                        int8_t *argmin) {
+    if (!h) return LABS_E_INVAL;
+    h->last_error.clear();
+    if (n < LABS_MIN_N || n > LABS_MAX_BRUTE_N)
+        return fail(h, LABS_E_INVAL, "n=%d out of [%d, %d]", n, LABS_MIN_N, LABS_MAX_BRUTE_N);
+    if (!min_e) return fail(h, LABS_E_INVAL, "null min_e");
+    DeviceGuard g(h->device);
+    hipStream_t s = h->stream;
+    const int64_t waves = brute_waves(n);
+    // Workspace: [out e | out count | out code (256 B)] [part e] [part count] [part code]
+    const size_t off_e = 256, off_c = off_e + 8 * (size_t)waves, off_k = off_c + 8 * (size_t)waves;
+    int rc = ws_acquire(h, s, off_k + 8 * (size_t)waves);
+    if (rc) return rc;
+    char *base = (char *)h->ws.ptr;
+    BruteParts p;
+    p.out_e = (int32_t *)base;
+    p.out_count = (int64_t *)(base + 8);
+    p.out_code = (uint64_t *)(base + 16);
+    p.part_e = (int32_t *)(base + off_e);
+    p.part_count = (int64_t *)(base + off_c);
+    p.part_code = (uint64_t *)(base + off_k);
+    hipError_t e = launch_bruteforce(n, p, s);
+    if (e != hipSuccess) return hip_fail(h, e, "exhaustive search launch");
+    if ((rc = stage_acquire(h, 24))) return rc;
+    e = hipMemcpyAsync(h->pin.ptr, base, 24, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "exhaustive search results");
+    if ((rc = ws_release(h, s))) return rc;
+    const char *r = (const char *)h->pin.ptr;
+    int32_t me;
+    int64_t cnt;
+    uint64_t code;
+    std::memcpy(&me, r, 4);
+    std::memcpy(&cnt, r + 8, 8);
+    std::memcpy(&code, r + 16, 8);
+    *min_e = me;
+    if (count) *count = cnt;
+    if (argmin)
+        for (int i = 0; i < n; ++i) argmin[i] = ((code >> i) & 1ull) ? (int8_t)-1 : (int8_t)1;
+    return LABS_OK;
+}
+
 int labs_set_launch(labs_handle *h, const labs_launch *launch) {
     if (!h) return LABS_E_INVAL;
     h->last_error.clear();

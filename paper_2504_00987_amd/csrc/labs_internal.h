@@ -77,6 +77,21 @@ struct MemeticLaunchArgs {
 hipError_t launch_energy(const int8_t *seqs, const int32_t *ns, int32_t n_uniform,
                          int32_t stride, int64_t count, int32_t *out, hipStream_t s);
 
+// Exhaustive minimum over the 2^(n-1) codes with s_0 = +1.  `waves`
+// wavefronts each write (min E, count, smallest code attaining it) to
+// part_e/part_count/part_code; a second kernel reduces them into out_e,
+// out_count (over all 2^n sequences) and out_code.
+struct BruteParts {
+    int32_t *part_e;
+    int64_t *part_count;
+    uint64_t *part_code;
+    int32_t *out_e;
+    int64_t *out_count;
+    uint64_t *out_code;
+};
+int64_t brute_waves(int n);
+hipError_t launch_bruteforce(int n, const BruteParts &p, hipStream_t s);
+
 // waves_per_group in {1,2,4}; persistent grid = groups (0: one wave per walk).
 // Length class c runs on streams[c] (entries may coincide); a.counter must
 // point at 32 * kWalkClasses writable uint32 (one queue head per class).

@@ -89,6 +89,17 @@ class Labs:
         return out
 
     # -- Alg. 2 / Alg. 4 -----------------------------------------------------
+    def bruteforce_min(self, n: int):
+        """Exhaustive minimum energy at length n: (E_min, how many of the 2^n
+        sequences attain it, the attaining int8 sequence with s_0 = +1 whose
+        bit pattern is smallest)."""
+        e = ctypes.c_int32(0)
+        cnt = ctypes.c_int64(0)
+        seq = np.zeros(n, dtype=np.int8)
+        self._check(self.L.labs_bruteforce_min(self.h, n, ctypes.byref(e), ctypes.byref(cnt),
+                                               seq.ctypes.data_as(ctypes.c_void_p)))
+        return e.value, cnt.value, seq
+
     def tabu_batch(self, rules: Rules, walks: int, seed: int, ns=None, n_uniform: int = 0,
                    starts: torch.Tensor | None = None, out_stride: int = 128,
                    trace_stride: int = 0, out=None, stream=None) -> TabuResult:

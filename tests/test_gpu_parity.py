@@ -68,6 +68,30 @@ def test_energy_closed_forms_and_edges(lb):
     assert empty.numel() == 0
 
 
+def test_bruteforce_min(lb):
+    say("exhaustive minimum: oracle enumeration for n <= 22, properties beyond")
+    for n in [3, 4, 5, 7, 8, 11, 13, 16, 20, 22]:
+        e, cnt, seq = lb.bruteforce_min(n)
+        oe, oc = O.bruteforce_min(n)
+        assert (e, cnt) == (oe, oc), n
+        assert seq[0] == 1 and O.energy(seq) == e
+        if n <= 14:  # the smallest attaining bit pattern with s_0 = +1
+            codes = np.arange(0, 1 << n, 2, dtype=np.int64)
+            bits = ((codes[:, None] >> np.arange(n)) & 1).astype(np.int8)
+            seqs = 1 - 2 * bits
+            E = np.array([O.energy(r) for r in seqs])
+            first = int(codes[np.argmax(E == e)])
+            assert np.array_equal(seq, 1 - 2 * ((first >> np.arange(n)) & 1)), n
+    # 32-bit and 64-bit enumeration paths at their boundary
+    for n in (31, 32, 33, 34):
+        e, cnt, seq = lb.bruteforce_min(n)
+        assert seq[0] == 1 and O.energy(seq) == e
+        assert e % 4 == (n // 2) % 4 and cnt >= 2 and cnt % 2 == 0
+    from paper_2504_00987_amd._lib import LabsError
+    with pytest.raises(LabsError):
+        lb.bruteforce_min(41)
+
+
 # ---------------------------------------------------------------------------
 # Alg. 2 / Alg. 4: batched walks
 # ---------------------------------------------------------------------------
