@@ -622,3 +622,88 @@ int64_t orc_memetic_advance(int n, int K, uint32_t p_comb, uint32_t p_mut,
     }
     return done;
 }
+
+/*
+ * Batched-generation variant (a documented departure from Alg. 1, which is
+ * steady state: one child per loop pass).  Generation g produces B children
+ * from the population as it stands at the start of g; only then are they
+ * merged, in the order b = 0..B-1, each exactly as Alg. 1 merges its one
+ * child (strict best update, then replacement of a random member, a later
+ * child overwriting an earlier one on the same slot).  Child b draws its
+ * words from (pop_id, g, 2b | 2b+1, TAG_GEN), its mutation words from
+ * (pop_id, g, 32 b + i/4, TAG_MUT), and walks as generation g*B + b.  With
+ * B = 1 every draw and every step coincides with orc_memetic_advance.  The
+ * target is checked once per generation, after the merge; *hit_gen counts
+ * generations.  Returns the generations executed or -1.
+ */
+int64_t orc_memetic_advance_batched(int n, int K, int B, uint32_t p_comb, uint32_t p_mut,
+                                    int steps_rule, int steps_a, int tenure_rule,
+                                    int lo_num, int lo_den, int lo_add,
+                                    int hi_num, int hi_den, int hi_add, int aspiration,
+                                    uint64_t seed, uint32_t pop_id, int64_t g0,
+                                    int64_t n_gens, int64_t target,
+                                    int8_t *pop, int64_t *popE, int8_t *best,
+                                    int64_t *best_e, int64_t *hit_gen)
+{
+    int8_t child[128], kids[8][128];
+    int64_t kid_e[8];
+    int kid_slot[8];
+    if (B < 1 || B > 8)
+        return -1;
+    int64_t done = 0;
+    for (int64_t g = g0; g < g0 + n_gens; ++g) {
+        if (target >= 0 && *best_e <= target) {
+            if (*hit_gen < 0)
+                *hit_gen = g;
+            break;
+        }
+        /* every child of this generation sees the same population */
+        for (int b = 0; b < B; ++b) {
+            uint32_t wa[4], wb[4];
+            draw(seed, pop_id, (uint32_t)g, (uint32_t)(2 * b), ORC_TAG_GEN, wa);
+            draw(seed, pop_id, (uint32_t)g, (uint32_t)(2 * b + 1), ORC_TAG_GEN, wb);
+            if (wa[0] < p_comb) {
+                int pa = tournament(popE, K, wa[1], wa[2]);
+                int pb = tournament(popE, K, wa[3], wb[0]);
+                int cut = 1 + (int)uniform_below(wb[1], (uint32_t)(n - 1));
+                for (int i = 0; i < n; ++i)
+                    child[i] = i < cut ? pop[(int64_t)pa * n + i] : pop[(int64_t)pb * n + i];
+            } else {
+                int c = (int)uniform_below(wa[1], (uint32_t)K);
+                memcpy(child, pop + (int64_t)c * n, (size_t)n);
+            }
+            for (int i = 0; i < n; ++i) {
+                uint32_t wm[4];
+                draw(seed, pop_id, (uint32_t)g, (uint32_t)(32 * b + (i >> 2)), ORC_TAG_MUT, wm);
+                if (wm[i & 3] < p_mut)
+                    child[i] = (int8_t)-child[i];
+            }
+            const uint32_t walk_gen = (uint32_t)(g * B + b);
+            int steps, lo, hi;
+            if (orc_walk_schedule(n, steps_rule, steps_a, tenure_rule, lo_num, lo_den,
+                                  lo_add, hi_num, hi_den, hi_add, seed, pop_id, walk_gen,
+                                  &steps, &lo, &hi))
+                return -1;
+            int64_t fe;
+            if (orc_tabu_walk(n, child, seed, pop_id, walk_gen, steps, lo, hi, aspiration, 0,
+                              kids[b], &kid_e[b], &fe, NULL, NULL))
+                return -1;
+            kid_slot[b] = (int)uniform_below(wb[2], (uint32_t)K);
+        }
+        for (int b = 0; b < B; ++b) {
+            if (kid_e[b] < *best_e) {
+                *best_e = kid_e[b];
+                memcpy(best, kids[b], (size_t)n);
+            }
+            memcpy(pop + (int64_t)kid_slot[b] * n, kids[b], (size_t)n);
+            popE[kid_slot[b]] = kid_e[b];
+        }
+        ++done;
+        if (target >= 0 && *best_e <= target) {
+            if (*hit_gen < 0)
+                *hit_gen = g + 1;
+            break;
+        }
+    }
+    return done;
+}

@@ -65,6 +65,10 @@ def lib():
         L.orc_memetic_advance.argtypes = [ctypes.c_int, ctypes.c_int, u32, u32] + \
             [ctypes.c_int] * 10 + [u64, u32, i64, i64, i64, P, P, P, P, P]
         L.orc_memetic_advance.restype = i64
+        L.orc_memetic_advance_batched.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, u32,
+                                                  u32] + [ctypes.c_int] * 10 + \
+            [u64, u32, i64, i64, i64, P, P, P, P, P]
+        L.orc_memetic_advance_batched.restype = i64
         _lib = L
     return _lib
 
@@ -218,11 +222,20 @@ class MemeticState:
                                _p(self.best), _p(self.best_e))
 
     def advance(self, n_gens: int, sched: Schedule, p_comb: int, p_mut: int,
-                target: int = -1) -> int:
-        done = lib().orc_memetic_advance(
-            self.n, self.K, p_comb, p_mut, *sched.rule_args(), sched.aspiration,
-            self.seed, self.pop_id, self.gen, n_gens, target, _p(self.pop),
-            _p(self.popE), _p(self.best), _p(self.best_e), _p(self.hit_gen))
+                target: int = -1, children: int = 0) -> int:
+        """Alg. 1 generations (children == 0), or the batched-generation
+        variant with `children` children per generation (1 reproduces Alg. 1
+        through the batched code)."""
+        if children == 0:
+            done = lib().orc_memetic_advance(
+                self.n, self.K, p_comb, p_mut, *sched.rule_args(), sched.aspiration,
+                self.seed, self.pop_id, self.gen, n_gens, target, _p(self.pop),
+                _p(self.popE), _p(self.best), _p(self.best_e), _p(self.hit_gen))
+        else:
+            done = lib().orc_memetic_advance_batched(
+                self.n, self.K, children, p_comb, p_mut, *sched.rule_args(), sched.aspiration,
+                self.seed, self.pop_id, self.gen, n_gens, target, _p(self.pop),
+                _p(self.popE), _p(self.best), _p(self.best_e), _p(self.hit_gen))
         if done < 0:
             raise ValueError("memetic advance failed")
         self.gen += int(done)

@@ -113,3 +113,78 @@ def test_target_stops_at_first_hit():
     st = base.copy()
     assert st.advance(10, MEM, O.P_COMB_090, O.p_mut_inv_n(n), target=base.bestE) == 0
     assert st.hit == 0
+
+
+# ---------------------------------------------------------------------------
+# Batched-generation variant: B children per generation from one snapshot.
+# ---------------------------------------------------------------------------
+def test_batched_one_child_is_alg1():
+    # B = 1 takes every draw and step of Alg. 1
+    for n, K, target in [(20, 100, -1), (33, 17, -1), (65, 24, -1), (26, 40, 120)]:
+        a = O.MemeticState(n, K, 7, 1)
+        b = a.copy()
+        a.advance(25, MEM, O.P_COMB_090, O.p_mut_inv_n(n), target=target)
+        b.advance(25, MEM, O.P_COMB_090, O.p_mut_inv_n(n), target=target, children=1)
+        assert a.bestE == b.bestE and a.gen == b.gen and a.hit == b.hit
+        assert np.array_equal(a.pop, b.pop) and np.array_equal(a.popE, b.popE)
+        assert np.array_equal(a.best, b.best)
+
+
+def test_batched_snapshot_and_merge_order():
+    # Sampling only, no mutation, empty walks: child b is the snapshot member
+    # (w1 * K) >> 32 of draw (pop, g, 2b, GEN) and replaces member
+    # (w2 * K) >> 32 of draw (pop, g, 2b + 1, GEN), merged in b order.
+    n, K, B, seed, pid = 22, 9, 6, 31, 4
+    zero = O.Schedule(O.STEPS_FIXED, 0, O.TENURE_LINEAR, 0, 1, 0, 0, 1, 0, 1)
+    st = O.MemeticState(n, K, seed, pid)
+    for g in range(5):
+        snap = st.pop.copy()
+        snapE = st.popE.copy()
+        want, wantE = snap.copy(), snapE.copy()
+        for b in range(B):
+            w1 = int(O.draw(seed, pid, g, 2 * b, O.TAG_GEN)[1])
+            w2 = int(O.draw(seed, pid, g, 2 * b + 1, O.TAG_GEN)[2])
+            src, dst = (w1 * K) >> 32, (w2 * K) >> 32
+            want[dst], wantE[dst] = snap[src], snapE[src]
+        st.advance(1, zero, 0, 0, children=B)
+        assert np.array_equal(st.pop, want) and np.array_equal(st.popE, wantE)
+
+
+def test_batched_invariants_and_resume():
+    n, K, B = 40, 50, 4
+    st = O.MemeticState(n, K, 11, 2)
+    full = st.copy()
+    prev = st.bestE
+    for g in range(12):
+        assert st.advance(1, MEM, O.P_COMB_090, O.p_mut_inv_n(n), children=B) == 1
+        assert st.bestE <= prev
+        prev = st.bestE
+        assert npref.energy(st.best) == st.bestE
+        assert list(st.popE) == list(npref.energies_rows(st.pop))
+        assert st.bestE <= st.popE.min()
+    full.advance(12, MEM, O.P_COMB_090, O.p_mut_inv_n(n), children=B)
+    assert full.bestE == st.bestE and np.array_equal(full.pop, st.pop)
+    # mutation words of child b come from index 32 b + i/4: with every
+    # other draw fixed, a different B changes the children after the first
+    other = O.MemeticState(n, K, 11, 2)
+    other.advance(12, MEM, O.P_COMB_090, O.p_mut_inv_n(n), children=B - 1)
+    assert not np.array_equal(other.pop, st.pop)
+
+
+def test_batched_target_counts_generations():
+    n, K, B = 24, 30, 3
+    base = O.MemeticState(n, K, 19, 0)
+    run = base.copy()
+    run.advance(40, MEM, O.P_COMB_090, O.p_mut_inv_n(n), children=B)
+    target = run.bestE
+    # the first generation at which best <= target
+    probe = base.copy()
+    first = None
+    for g in range(40):
+        probe.advance(1, MEM, O.P_COMB_090, O.p_mut_inv_n(n), children=B)
+        if probe.bestE <= target:
+            first = g + 1
+            break
+    stop = base.copy()
+    stop.advance(40, MEM, O.P_COMB_090, O.p_mut_inv_n(n), target=target, children=B)
+    assert stop.hit == first and stop.gen == first and stop.bestE <= target
