@@ -217,7 +217,7 @@ typedef struct labs_memetic_params {
     int32_t mut_rule;    /* labs_mut_rule */
     uint32_t p_mut;      /* threshold for LABS_MUT_FIXED */
     labs_tabu_params tabu;
-    int64_t generations; /* children per replica (one per generation) */
+    int64_t generations; /* generations per replica */
     int32_t target_e;    /* a replica stops once its best energy <= target_e
                             (Alg. 1's loop condition); < 0 disables */
     int32_t mode;        /* labs_exec_mode */
@@ -231,7 +231,20 @@ typedef struct labs_memetic_params {
                             batches too small to fill the device); 0 picks
                             2 when those replicas number at most twice the
                             compute units */
+    int32_t children;    /* children per generation, 1..8 (0 means 1).  1 is
+                            Alg. 1 (steady state).  B > 1 is the batched-
+                            generation variant: B children are made from
+                            the population as it stands at the start of the
+                            generation, walked concurrently (one wavefront
+                            each), then merged in order b = 0..B-1 as Alg. 1
+                            merges its one child; child b draws from
+                            (replica, g, 2b | 2b+1, GEN), mutates with
+                            (replica, g, 32b + i/4, MUT) and walks as
+                            generation g*B + b.  Targets are checked once per
+                            generation; hit_gen counts generations. */
 } labs_memetic_params;
+
+#define LABS_MAX_CHILDREN 8
 
 /*
  * Run `pops` independent memetic replicas (population id = index).

@@ -38,7 +38,8 @@ class MemeticParams(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("p_comb", ctypes.c_uint32), ("mut_rule", ctypes.c_int32),
                 ("p_mut", ctypes.c_uint32), ("tabu", TabuParams), ("generations", ctypes.c_int64),
                 ("target_e", ctypes.c_int32), ("mode", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("stop_all", ctypes.c_int32), ("waves_per_replica", ctypes.c_int32)]
+                ("stop_all", ctypes.c_int32), ("waves_per_replica", ctypes.c_int32),
+                ("children", ctypes.c_int32)]
 
 
 class LabsError(RuntimeError):

@@ -256,7 +256,8 @@ int labs_create(labs_handle **out, int device) {
         hipEventCreateWithFlags(&h->fork_event, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&h->join_event, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&h->join2_event, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->join3_event, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&h->join3_event, hipEventDisableTiming) != hipSuccess ||
+        prepare_memetic_kernels() != hipSuccess) {
         delete h;
         return LABS_E_HIP;
     }

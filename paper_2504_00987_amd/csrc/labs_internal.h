@@ -59,6 +59,8 @@ struct MemeticSlot {
     int32_t state;    // index into MemeticStateDev arrays; < 0 means idle
 };
 
+constexpr int kMaxChildren = 8;  // children per generation (batched variant)
+
 struct MemeticLaunchArgs {
     const MemeticSlot *slots;
     int32_t n_slots;
@@ -70,6 +72,7 @@ struct MemeticLaunchArgs {
     int32_t gens;            // generations per launch
     int32_t classes;         // bit 0: some slot has N <= 64; bit 1: some N > 64
     int32_t split_wide;      // 1: a replica with N > 64 runs on two wavefronts
+    int32_t children;        // children per generation (1: Alg. 1)
     MemeticStateDev st;
     uint32_t *any_hit;       // set to 1 when a replica reaches its target
 };
@@ -99,6 +102,9 @@ hipError_t launch_tabu(const TabuLaunchArgs &a, int waves_per_group, int groups,
                        const hipStream_t *streams);
 
 hipError_t launch_memetic_init(const MemeticLaunchArgs &a, hipStream_t s);
+// Once per device before the first launch: raises the dynamic LDS limit of
+// the batched-generation kernels to what kMaxChildren children need.
+hipError_t prepare_memetic_kernels();
 // Advances every slot by a.gens generations.  When both length classes are
 // present and `side` is given, the N <= 64 slots run on `side` (forked from
 // and joined back into s with the two events), concurrently with the N > 64

@@ -33,6 +33,8 @@ MemeticStateDev carve_state(void *base, int S, int K, size_t *bytes_out) {
     return st;
 }
 
+static_assert(kMaxChildren == LABS_MAX_CHILDREN, "kernel and ABI limits agree");
+
 int split_wide(const labs_handle *h, int waves_per_replica, int64_t n_wide) {
     if (waves_per_replica != 0) return waves_per_replica == 2;
     return n_wide <= 2 * (int64_t)std::max(h->num_cus, 1);
@@ -51,6 +53,8 @@ int check_memetic(labs_handle *h, const labs_memetic_params *p) {
     if (p->stop_all != 0 && p->stop_all != 1) return fail(h, LABS_E_INVAL, "stop_all must be 0 or 1");
     if (p->waves_per_replica < 0 || p->waves_per_replica > 2)
         return fail(h, LABS_E_INVAL, "waves_per_replica must be 0, 1 or 2");
+    if (p->children < 0 || p->children > LABS_MAX_CHILDREN)
+        return fail(h, LABS_E_INVAL, "children must be in [0, %d]", LABS_MAX_CHILDREN);
     return LABS_OK;
 }
 
@@ -144,6 +148,7 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
         n_wide += wide;
     }
     a.split_wide = split_wide(h, p->waves_per_replica, n_wide);
+    a.children = std::max(1, (int)p->children);
     if ((e = launch_fill_u32(d_flag, 0u, 1, s)) != hipSuccess) return hip_fail(h, e, "fill");
     if ((e = launch_memetic_init(a, s)) != hipSuccess) return hip_fail(h, e, "memetic init");
 

@@ -159,6 +159,7 @@ int labs_server::iterate(std::unique_lock<std::mutex> &lk) {
     a.gens = params.chunk;
     a.classes = classes;
     a.split_wide = split_wide(h, params.waves_per_replica, n_wide);
+    a.children = std::max(1, (int)params.children);
     if (e == hipSuccess) e = launch_memetic_advance(a, stream, side, fork, join);
     if (e == hipSuccess) e = hipMemcpyAsync(h_bestE, st.bestE, max_slots * 4, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(h_gen, st.gen, max_slots * 8, hipMemcpyDeviceToHost, stream);

@@ -153,9 +153,10 @@ class Labs:
     def memetic_params(K: int, rules: Rules, generations: int, p_comb: int = P_COMB_090,
                        mut_rule: int = MUT_INV_N, p_mut: int = 0, target: int = -1,
                        mode: int = PERSISTENT, chunk: int = 64,
-                       stop_all: int = 0, waves_per_replica: int = 0) -> _lib.MemeticParams:
+                       stop_all: int = 0, waves_per_replica: int = 0,
+                       children: int = 1) -> _lib.MemeticParams:
         return _lib.MemeticParams(K, p_comb, mut_rule, p_mut, tabu_params(rules), generations,
-                                  target, mode, chunk, stop_all, waves_per_replica)
+                                  target, mode, chunk, stop_all, waves_per_replica, children)
 
     def memetic_run(self, K: int, rules: Rules, generations: int, pops: int, seed: int,
                     ns=None, n_uniform: int = 0, out_stride: int = 128, stream=None,
@@ -182,11 +183,11 @@ class Server:
 
     def __init__(self, labs: Labs, K: int, rules: Rules, max_slots: int, chunk: int = 8,
                  target: int = -1, p_comb: int = P_COMB_090, mut_rule: int = MUT_INV_N,
-                 p_mut: int = 0):
+                 p_mut: int = 0, children: int = 1):
         self.labs = labs
         self.L = labs.L
         p = Labs.memetic_params(K, rules, 0, p_comb=p_comb, mut_rule=mut_rule, p_mut=p_mut,
-                                target=target, chunk=chunk)
+                                target=target, chunk=chunk, children=children)
         s = ctypes.c_void_p()
         _lib.check(self.L.labs_server_create(labs.h, ctypes.byref(p), max_slots, ctypes.byref(s)),
                    labs.h)

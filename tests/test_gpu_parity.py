@@ -252,7 +252,8 @@ def test_invalid_arguments(lb):
 # ---------------------------------------------------------------------------
 # Alg. 1 / Alg. 3: memetic replicas
 # ---------------------------------------------------------------------------
-def _oracle_memetic(n_list, K, rules, gens, seed, target=-1, p_comb=I.P_COMB_090, p_mut=None):
+def _oracle_memetic(n_list, K, rules, gens, seed, target=-1, p_comb=I.P_COMB_090, p_mut=None,
+                    children=0):
     # replicas are independent: one oracle replica per worker thread (the
     # oracle's C code releases the interpreter lock); p_mut None: 1/N
     import concurrent.futures as cf
@@ -261,7 +262,7 @@ def _oracle_memetic(n_list, K, rules, gens, seed, target=-1, p_comb=I.P_COMB_090
         n = int(n_list[p])
         st = O.MemeticState(n, K, seed, p)
         thr = O.p_mut_inv_n(n) if p_mut is None else p_mut
-        st.advance(gens, osched(rules), p_comb, thr, target=target)
+        st.advance(gens, osched(rules), p_comb, thr, target=target, children=children)
         return st
 
     with cf.ThreadPoolExecutor(max_workers=16) as ex:
@@ -359,17 +360,62 @@ def test_memetic_n120_prefix(lb, mode, chunk, waves):
         assert np.array_equal(bs[p, :120], st.best)
 
 
+@pytest.mark.parametrize("B,mode,chunk", [(2, 0, 4), (3, 1, 5), (4, 2, 3), (8, 2, 9), (8, 0, 2)])
+def test_memetic_batched_children(lb, B, mode, chunk):
+    # B children per generation from one snapshot, merged in child order;
+    # B = 8 with N > 64 needs more than 64 KiB of LDS per workgroup
+    ns = np.array([3, 20, 49, 64, 65, 100, 127, 128], dtype=np.int32)
+    rules = I.RULES_MEMETIC
+    G = 9
+    say(f"memetic batched B={B} mode {mode} chunk {chunk} N={list(ns)}")
+    ref = _oracle_memetic(ns, 24, rules, G, 808, children=B)
+    res = lb.memetic_run(24, rules, G, len(ns), 808, ns=ns, mode=mode, chunk=chunk, children=B)
+    for p, st in enumerate(ref):
+        n = int(ns[p])
+        assert res.best_e[p].item() == st.bestE
+        assert np.array_equal(res.best_seq[p, :n].cpu().numpy(), st.best)
+        assert res.gens_done[p].item() == G and res.hit_gen[p].item() == -1
+
+
+def test_memetic_batched_target(lb):
+    # the target test runs after every child; the hit generation counts
+    # generations (B children each), as in the oracle
+    n, K, G, B = 30, 40, 40, 4
+    rules = I.RULES_MEMETIC
+    base = _oracle_memetic([n] * 6, K, rules, G, 91, children=B)
+    target = sorted(st.bestE for st in base)[2]
+    say(f"memetic batched B={B}, target {target}")
+    ref = _oracle_memetic([n] * 6, K, rules, G, 91, target=target, children=B)
+    for mode in (0, 2):
+        res = lb.memetic_run(K, rules, G, 6, 91, n_uniform=n, target=target, mode=mode, chunk=4,
+                             children=B)
+        for p, st in enumerate(ref):
+            assert res.hit_gen[p].item() == st.hit
+            assert res.best_e[p].item() == st.bestE
+            assert res.gens_done[p].item() == st.gen
+
+
+def test_memetic_batched_one_child_is_default(lb):
+    # children = 1 is the one-child-per-generation kernel itself
+    ns = np.array([20, 64, 90], dtype=np.int32)
+    rules = I.RULES_MEMETIC
+    a = lb.memetic_run(16, rules, 6, 3, 5, ns=ns, mode=2, chunk=3, children=1)
+    b = lb.memetic_run(16, rules, 6, 3, 5, ns=ns, mode=2, chunk=3)
+    assert torch.equal(a.best_e, b.best_e) and torch.equal(a.best_seq, b.best_seq)
+
+
 # ---------------------------------------------------------------------------
 # Serving
 # ---------------------------------------------------------------------------
-def test_server_alone_equals_mix(lb):
+@pytest.mark.parametrize("children", [1, 4])
+def test_server_alone_equals_mix(lb, children):
     import time
     from paper_2504_00987_amd.labs import Server
     reqs = I.serving_requests(10, seed=77)
     pops, gens, K = 3, 6, 16
     rules = I.RULES_MEMETIC
     say(f"server: {len(reqs)} requests, N={[n for n, _ in reqs]}")
-    srv = Server(lb, K, rules, max_slots=8, chunk=2)
+    srv = Server(lb, K, rules, max_slots=8, chunk=2, children=children)
     try:
         ids = [(srv.submit(n, s, pops, gens), n, s) for n, s in reqs]
         results = {}
@@ -386,7 +432,8 @@ def test_server_alone_equals_mix(lb):
         srv.close()
     for rid, n, s in ids:
         seq, e, lat = results[rid]
-        alone = lb.memetic_run(K, rules, gens, pops, s, n_uniform=n, mode=2, chunk=gens)
+        alone = lb.memetic_run(K, rules, gens, pops, s, n_uniform=n, mode=2, chunk=gens,
+                               children=children)
         be = alone.best_e.cpu().numpy()
         p = int(np.argmin(be))
         assert e == be[p]
@@ -394,7 +441,7 @@ def test_server_alone_equals_mix(lb):
         assert lat > 0
     # and the smallest request against the oracle
     n, s = min(reqs)
-    ref = _oracle_memetic([n] * pops, K, rules, gens, s)
+    ref = _oracle_memetic([n] * pops, K, rules, gens, s, children=children)
     rid = [r for r, nn, ss in ids if (nn, ss) == (n, s)][0]
     assert results[rid][1] == min(st.bestE for st in ref)
 
