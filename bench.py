@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 PEAK_INT32_OPS = 256 * 64 * 2.4e9
 METRIC = "flip-neighbour evals/sec (N=64..120) + time-to-target energy; batched vs plain"
 KERNEL_SOURCES = ("paper_2504_00987_amd/csrc/labs_device.hpp",
-                  "paper_2504_00987_amd/csrc/labs_kernels.hip")
+                  "paper_2504_00987_amd/csrc/labs_walk.hip")
 
 # Counter readings per launch of the walk kernels (rocprofv3 --pmc, one pass
 # per counter group, same bench command), valid for the kernel sources whose

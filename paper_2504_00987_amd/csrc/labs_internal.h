@@ -1,5 +1,6 @@
-// Internal interface between the C ABI (labs_api.cpp, labs_server.cpp) and
-// the kernels (labs_kernels.hip).  Not installed; not part of the ABI.
+// Internal interface between the C ABI (labs_api.cpp, labs_memetic.cpp,
+// labs_server.cpp) and the kernels (labs_walk.hip, labs_memetic_kernels.hip,
+// labs_brute.hip).  Not installed; not part of the ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>

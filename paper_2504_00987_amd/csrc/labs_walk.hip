@@ -1,0 +1,206 @@
+// Walk kernels of liblabs for gfx950 and their launchers.
+//
+//   energy_kernel   Eq. (2) for a batch of +-1 rows, one row per wave
+//   tabu_kernel     independent tabu walks (Alg. 2 / Alg. 4), one walk per
+//                   wave, either one wave per walk or a persistent grid
+//                   draining a longest-first work queue; one instantiation
+//                   per length class
+//   fill_u32_kernel device-side fill (queue heads, flags), capturable
+#include <algorithm>
+
+#include "labs_device.hpp"
+#include "labs_internal.h"
+
+namespace liblabs {
+
+namespace {
+
+
+// ---------------------------------------------------------------------------
+// Energies.
+// ---------------------------------------------------------------------------
+template <int WPG>
+__global__ __launch_bounds__(64 * WPG) void energy_kernel(const int8_t *__restrict__ seqs,
+                                                          const int32_t *__restrict__ ns,
+                                                          int32_t n_uniform, int32_t stride,
+                                                          int64_t count,
+                                                          int32_t *__restrict__ out) {
+    const int lane = lane_id();
+    const int64_t b = (int64_t)blockIdx.x * WPG + (threadIdx.x >> 6);
+    if (b >= count) return;
+    const int N = ns ? ns[b] : n_uniform;
+    const int8_t *row = seqs + b * (int64_t)stride;
+    bool b0 = false, b1 = false;
+    if (lane < N) b0 = row[lane] < 0;
+    if (lane + 64 < N) b1 = row[lane + 64] < 0;
+    const M128 M{ballot(b0), ballot(b1)};
+    int acc = 0;
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+        const int k = lane + 1 + 64 * w;
+        if (k < N) {
+            const int c = lag_corr(M, N, k);
+            acc += c * c;
+        }
+    }
+    const int E = wave_sum(acc);
+    out[b] = E;  // every lane stores the same value: no lane-0 branch
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched tabu walks.
+// ---------------------------------------------------------------------------
+template <int NW, int NB, bool TRACE>
+__device__ void run_tabu_item(const TabuLaunchArgs &a, int64_t w, int N, uint8_t *lds) {
+    using Mask = typename MaskOf<NW>::type;
+    const int lane = lane_id();
+    uint64_t lo, hi;
+    if (a.starts != nullptr) {
+        const int8_t *row = a.starts + w * (int64_t)a.start_stride;
+        bool b0 = false, b1 = false;
+        if (lane < N) b0 = row[lane] < 0;
+        if (lane + 64 < N) b1 = row[lane + 64] < 0;
+        lo = ballot(b0);
+        hi = ballot(b1);
+    } else {
+        const Draw4 d = philox10((uint32_t)w, 0u, 0u, kTagStart, a.k0, a.k1);
+        lo = (uint64_t)d.w0 | ((uint64_t)d.w1 << 32);
+        hi = (uint64_t)d.w2 | ((uint64_t)d.w3 << 32);
+        if (N < 64) {
+            lo &= (1ull << N) - 1ull;
+            hi = 0ull;
+        } else {
+            hi &= (N >= 128) ? ~0ull : ((1ull << (N - 64)) - 1ull);
+        }
+    }
+    const Mask M = make_mask<NW>(lo, hi);
+    const Schedule sch = make_schedule(a.rule, N, a.k0, a.k1, (uint32_t)w, 0u);
+    const WalkResult<NW> r =
+        tabu_walk<NW, TRACE, 1, NB>(N, M, sch, a.rule.aspiration, a.k0, a.k1, (uint32_t)w, 0u, lds,
+                                    TRACE ? a.trace + w * (int64_t)a.trace_stride : nullptr);
+    int8_t *out = a.best_seq + w * (int64_t)a.out_stride;
+    for (int i = lane; i < a.out_stride; i += 64)
+        out[i] = i < N ? (m_bit(r.best, i) ? (int8_t)-1 : (int8_t)1) : (int8_t)0;
+    a.best_e[w] = r.best_e;  // uniform values, stored by every lane
+    a.final_e[w] = r.final_e;
+}
+
+// Next index of the persistent work queue, wave-uniform.  Every lane executes
+// the atomic (lane 0 adds 1, the others add 0) so that the value read back
+// with readlane is never produced under a lane-dependent branch: a
+// lane-0-only fetch lets the optimiser thread that branch into the loop's
+// other lane-0 branches, and lanes then reach the readlane before lane 0 has
+// fetched, disagreeing on the index.
+__device__ __forceinline__ uint32_t next_work(uint32_t *counter) {
+    const uint32_t v = atomicAdd(counter, lane_id() == 0 ? 1u : 0u);
+    return readlane_u(v, 0);
+}
+
+// Walks at positions [begin, end) of the processing order, all of one length
+// class: NW neighbours per lane (N <= 64 NW) and windows of NB chunks
+// (N - 1 <= 16 NB).  PERSIST: a grid sized to the device drains the range
+// through the queue head `counter`; otherwise one wave per position.
+// TRACE: record every walk's moves (a separate instantiation, so that the
+// untraced kernel does not carry the registers of the traced one).
+template <int NW, int NB, int WPG, bool PERSIST, bool TRACE>
+__global__ __launch_bounds__(64 * WPG) void tabu_kernel(TabuLaunchArgs a, int64_t begin,
+                                                        int64_t end, uint32_t *counter) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds_all[WPG][walk_lds_bytes<NW>()];
+    const int wave = threadIdx.x >> 6;
+    uint8_t *lds = lds_all[wave];
+    if constexpr (PERSIST) {
+        for (int64_t pos = begin + next_work(counter); pos < end;
+             pos = begin + next_work(counter)) {
+            const int64_t w = a.order ? (int64_t)a.order[pos] : pos;
+            run_tabu_item<NW, NB, TRACE>(a, w, a.ns ? a.ns[w] : a.n_uniform, lds);
+        }
+    } else {
+        const int64_t pos = begin + (int64_t)blockIdx.x * WPG + wave;
+        if (pos < end) {
+            const int64_t w = a.order ? (int64_t)a.order[pos] : pos;
+            run_tabu_item<NW, NB, TRACE>(a, w, a.ns ? a.ns[w] : a.n_uniform, lds);
+        }
+    }
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_energy(const int8_t *seqs, const int32_t *ns, int32_t n_uniform,
+                         int32_t stride, int64_t count, int32_t *out, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    constexpr int WPG = 4;
+    const int64_t grid = (count + WPG - 1) / WPG;
+    hipLaunchKernelGGL(energy_kernel<WPG>, dim3((unsigned)grid), dim3(64 * WPG), 0, s, seqs, ns,
+                       n_uniform, stride, count, out);
+    return hipGetLastError();
+}
+
+namespace {
+
+template <int NW, int NB, int WPG, bool TRACE>
+hipError_t launch_tabu_part_t(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
+                              uint32_t *counter, hipStream_t s) {
+    if (groups > 0) {
+        hipError_t e = launch_fill_u32(counter, 0u, 1, s);
+        if (e != hipSuccess) return e;
+        const int64_t need = (end - begin + WPG - 1) / WPG;
+        hipLaunchKernelGGL((tabu_kernel<NW, NB, WPG, true, TRACE>),
+                           dim3((unsigned)std::min<int64_t>(groups, need)), dim3(64 * WPG), 0, s, a,
+                           begin, end, counter);
+    } else {
+        const int64_t grid = (end - begin + WPG - 1) / WPG;
+        hipLaunchKernelGGL((tabu_kernel<NW, NB, WPG, false, TRACE>), dim3((unsigned)grid),
+                           dim3(64 * WPG), 0, s, a, begin, end, counter);
+    }
+    return hipGetLastError();
+}
+
+template <int NW, int NB, int WPG>
+hipError_t launch_tabu_part(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
+                            uint32_t *counter, hipStream_t s) {
+    if (end <= begin) return hipSuccess;
+    return a.trace != nullptr
+               ? launch_tabu_part_t<NW, NB, WPG, true>(a, begin, end, groups, counter, s)
+               : launch_tabu_part_t<NW, NB, WPG, false>(a, begin, end, groups, counter, s);
+}
+
+// One launch per non-empty length class, each on its own stream with its
+// own queue head (32 words apart).
+template <int WPG>
+hipError_t launch_tabu_wpg(const TabuLaunchArgs &a, int groups, const hipStream_t *st) {
+    static_assert(kWalkClasses == 4, "one launcher per class below");
+    const int64_t *ce = a.class_end;
+    hipError_t e = launch_tabu_part<2, 8, WPG>(a, 0, ce[0], groups, a.counter, st[0]);
+    if (e == hipSuccess) e = launch_tabu_part<2, 6, WPG>(a, ce[0], ce[1], groups, a.counter + 32, st[1]);
+    if (e == hipSuccess) e = launch_tabu_part<1, 4, WPG>(a, ce[1], ce[2], groups, a.counter + 64, st[2]);
+    if (e == hipSuccess) e = launch_tabu_part<1, 3, WPG>(a, ce[2], ce[3], groups, a.counter + 96, st[3]);
+    return e;
+}
+
+}  // namespace
+
+hipError_t launch_tabu(const TabuLaunchArgs &a, int waves_per_group, int groups,
+                       const hipStream_t *streams) {
+    if (a.W <= 0) return hipSuccess;
+    switch (waves_per_group) {
+    case 1: return launch_tabu_wpg<1>(a, groups, streams);
+    case 2: return launch_tabu_wpg<2>(a, groups, streams);
+    case 4: return launch_tabu_wpg<4>(a, groups, streams);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int64_t grid = (count + 255) / 256;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)grid), dim3(256), 0, s, p, v, count);
+    return hipGetLastError();
+}
+
+}  // namespace liblabs
