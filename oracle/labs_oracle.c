@@ -33,6 +33,9 @@
 #include <string.h>
 #include <pthread.h>
 
+/* Longest sequence the walk and memetic routines accept. */
+#define ORC_MAX_N 256
+
 /* ------------------------------------------------------------------------- */
 /* Philox4x32-10, from the published definition (SC'11, Sec. 2.3 / Fig. 2).   */
 /* Round: (hi0,lo0) = M0*x0, (hi1,lo1) = M1*x2;                               */
@@ -167,7 +170,9 @@ int orc_bruteforce_min(int n, int64_t *emin, int64_t *count)
  * Eq. (2) (the O(N^3)-per-step route the paper calls prohibitive, Sec. III.C). */
 void orc_neighbour_energies_recompute(const int8_t *s, int n, int64_t *out)
 {
-    int8_t t[256];
+    int8_t t[ORC_MAX_N];
+    if (n < 1 || n > ORC_MAX_N)
+        return;
     memcpy(t, s, (size_t)n);
     for (int i = 0; i < n; ++i) {
         t[i] = (int8_t)-t[i];
@@ -184,8 +189,8 @@ void orc_neighbour_energies_recompute(const int8_t *s, int n, int64_t *out)
  * one "row and column" of products. */
 typedef struct {
     int n;
-    int8_t table[128][128]; /* table[k][i], valid for 1 <= k < n, 0 <= i < n-k */
-    int64_t vec[128];       /* vec[k] = C_k */
+    int8_t table[ORC_MAX_N][ORC_MAX_N]; /* table[k][i], valid for 1 <= k < n, 0 <= i < n-k */
+    int64_t vec[ORC_MAX_N];             /* vec[k] = C_k */
 } tables_t;
 
 static void tables_build(tables_t *T, const int8_t *s, int n)
@@ -235,6 +240,8 @@ static void tables_flip(tables_t *T, int i)
 
 void orc_neighbour_energies_tables(const int8_t *s, int n, int64_t *out)
 {
+    if (n < 1 || n > ORC_MAX_N)
+        return;
     tables_t *T = (tables_t *)malloc(sizeof(tables_t));
     tables_build(T, s, n);
     for (int i = 0; i < n; ++i)
@@ -299,14 +306,17 @@ int orc_walk_schedule(int n, int steps_rule, int steps_a, int tenure_rule,
     return 0;
 }
 
-/* Random start of stand-alone walk `walk`: bit i of the 128-bit draw
- * (walk, 0, 0, TAG_START) -- word i/32, bit i%32 -- set means s_i = -1. */
+/* Random start of stand-alone walk `walk`: s_i = -1 when bit i % 128 of the
+ * 128-bit draw (walk, 0, i / 128, TAG_START) is set, the draw's word
+ * (i % 128) / 32 holding bits 32 w .. 32 w + 31. */
 void orc_random_start(int n, uint64_t seed, uint32_t walk, int8_t *s)
 {
     uint32_t w[4];
-    draw(seed, walk, 0, 0, ORC_TAG_START, w);
-    for (int i = 0; i < n; ++i)
-        s[i] = ((w[i >> 5] >> (i & 31)) & 1u) ? -1 : 1;
+    for (int i = 0; i < n; ++i) {
+        if ((i & 127) == 0)
+            draw(seed, walk, 0, (uint32_t)(i >> 7), ORC_TAG_START, w);
+        s[i] = ((w[(i & 127) >> 5] >> (i & 31)) & 1u) ? -1 : 1;
+    }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -337,11 +347,11 @@ int orc_tabu_walk(int n, const int8_t *start, uint64_t seed, uint32_t entity,
                   int recompute, int8_t *best, int64_t *best_e,
                   int64_t *final_e, int16_t *trace, int64_t *trace_e)
 {
-    int8_t pivot[128];
-    int64_t tabu[128];
-    int64_t cand[128];
-    int ties[128];
-    if (n < 1 || n > 128 || lo < 0 || hi < lo)
+    int8_t pivot[ORC_MAX_N];
+    int64_t tabu[ORC_MAX_N];
+    int64_t cand[ORC_MAX_N];
+    int ties[ORC_MAX_N];
+    if (n < 1 || n > ORC_MAX_N || lo < 0 || hi < lo)
         return -1;
 
     memcpy(pivot, start, (size_t)n);
@@ -431,9 +441,9 @@ typedef struct {
 static int run_one_walk(batch_job_t *J, int64_t w)
 {
     int n = J->ns ? J->ns[w] : J->n_uniform;
-    int8_t start[128];
+    int8_t start[ORC_MAX_N];
     int steps, lo, hi;
-    if (n < 3 || n > 128 || n > J->stride)
+    if (n < 3 || n > ORC_MAX_N || n > J->stride)
         return -1;
     if (orc_walk_schedule(n, J->steps_rule, J->steps_a, J->tenure_rule,
                           J->lo_num, J->lo_den, J->lo_add,
@@ -509,9 +519,9 @@ int orc_tabu_batch(int64_t W, const int32_t *ns, int32_t n_uniform,
 /*
  * Population state of one replica: pop[K][n] (+-1), popE[K], best[n], bestE.
  *
- * Initialisation (Alg. 1, first two lines): member m is the 128-bit draw
- * (pop_id, m, 0, TAG_INIT) read as in orc_random_start; bestSeq is the
- * lowest-index member of minimum energy.
+ * Initialisation (Alg. 1, first two lines): member m is read from the
+ * draws (pop_id, m, i / 128, TAG_INIT) as orc_random_start reads its draws;
+ * bestSeq is the lowest-index member of minimum energy.
  */
 void orc_memetic_init(int n, int K, uint64_t seed, uint32_t pop_id,
                       int8_t *pop, int64_t *popE, int8_t *best, int64_t *best_e)
@@ -519,10 +529,12 @@ void orc_memetic_init(int n, int K, uint64_t seed, uint32_t pop_id,
     int argmin = 0;
     for (int m = 0; m < K; ++m) {
         uint32_t w[4];
-        draw(seed, pop_id, (uint32_t)m, 0, ORC_TAG_INIT, w);
         int8_t *s = pop + (int64_t)m * n;
-        for (int i = 0; i < n; ++i)
-            s[i] = ((w[i >> 5] >> (i & 31)) & 1u) ? -1 : 1;
+        for (int i = 0; i < n; ++i) {
+            if ((i & 127) == 0)
+                draw(seed, pop_id, (uint32_t)m, (uint32_t)(i >> 7), ORC_TAG_INIT, w);
+            s[i] = ((w[(i & 127) >> 5] >> (i & 31)) & 1u) ? -1 : 1;
+        }
         popE[m] = orc_energy(s, n);
         if (popE[m] < popE[argmin])
             argmin = m;
@@ -570,8 +582,10 @@ int64_t orc_memetic_advance(int n, int K, uint32_t p_comb, uint32_t p_mut,
                             int8_t *pop, int64_t *popE, int8_t *best,
                             int64_t *best_e, int64_t *hit_gen)
 {
-    int8_t child[128], child_best[128];
+    int8_t child[ORC_MAX_N], child_best[ORC_MAX_N];
     int64_t done = 0;
+    if (n < 2 || n > ORC_MAX_N || K < 1)
+        return -1;
     for (int64_t g = g0; g < g0 + n_gens; ++g) {
         if (target >= 0 && *best_e <= target) {
             if (*hit_gen < 0)
@@ -631,7 +645,7 @@ int64_t orc_memetic_advance(int n, int K, uint32_t p_comb, uint32_t p_mut,
  * child (strict best update, then replacement of a random member, a later
  * child overwriting an earlier one on the same slot).  Child b draws its
  * words from (pop_id, g, 2b | 2b+1, TAG_GEN), its mutation words from
- * (pop_id, g, 32 b + i/4, TAG_MUT), and walks as generation g*B + b.  With
+ * (pop_id, g, 64 b + i/4, TAG_MUT), and walks as generation g*B + b.  With
  * B = 1 every draw and every step coincides with orc_memetic_advance.  The
  * target is checked once per generation, after the merge; *hit_gen counts
  * generations.  Returns the generations executed or -1.
@@ -645,10 +659,10 @@ int64_t orc_memetic_advance_batched(int n, int K, int B, uint32_t p_comb, uint32
                                     int8_t *pop, int64_t *popE, int8_t *best,
                                     int64_t *best_e, int64_t *hit_gen)
 {
-    int8_t child[128], kids[8][128];
+    int8_t child[ORC_MAX_N], kids[8][ORC_MAX_N];
     int64_t kid_e[8];
     int kid_slot[8];
-    if (B < 1 || B > 8)
+    if (B < 1 || B > 8 || n < 2 || n > ORC_MAX_N || K < 1)
         return -1;
     int64_t done = 0;
     for (int64_t g = g0; g < g0 + n_gens; ++g) {
@@ -674,7 +688,7 @@ int64_t orc_memetic_advance_batched(int n, int K, int B, uint32_t p_comb, uint32
             }
             for (int i = 0; i < n; ++i) {
                 uint32_t wm[4];
-                draw(seed, pop_id, (uint32_t)g, (uint32_t)(32 * b + (i >> 2)), ORC_TAG_MUT, wm);
+                draw(seed, pop_id, (uint32_t)g, (uint32_t)(64 * b + (i >> 2)), ORC_TAG_MUT, wm);
                 if (wm[i & 3] < p_mut)
                     child[i] = (int8_t)-child[i];
             }

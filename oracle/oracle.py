@@ -19,6 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "labs_oracle.c")
 _SO = os.path.join(_HERE, "liboracle.so")
+MAX_N = 256  # longest sequence of the walk and memetic routines
 
 STEPS_FIXED, STEPS_MULT_N, STEPS_PAPER = 0, 1, 2
 TENURE_LINEAR, TENURE_PAPER = 0, 1
@@ -146,6 +147,8 @@ def bruteforce_min(n: int):
 
 def neighbour_energies(s, recompute: bool = True) -> np.ndarray:
     s = _seq(s)
+    if not 1 <= len(s) <= MAX_N:
+        raise ValueError(f"sequence length must be in [1, {MAX_N}]")
     out = np.zeros(len(s), dtype=np.int64)
     f = lib().orc_neighbour_energies_recompute if recompute else lib().orc_neighbour_energies_tables
     f(_p(s), len(s), _p(out))

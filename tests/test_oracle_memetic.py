@@ -25,6 +25,30 @@ def test_init():
     assert list(st.pop[3]) == [1 - 2 * ((int(w[i >> 5]) >> (i & 31)) & 1) for i in range(20)]
 
 
+def test_init_beyond_128():
+    # bits 128.. of member m come from draw (pop, m, 1, TAG_INIT)
+    st = O.MemeticState(200, 5, 1000, 4)
+    assert list(st.popE) == list(npref.energies_rows(st.pop))
+    w0 = O.draw(1000, 4, 2, 0, O.TAG_INIT)
+    w1 = O.draw(1000, 4, 2, 1, O.TAG_INIT)
+    bits = [(int(w0[i >> 5]) >> (i & 31)) & 1 for i in range(128)]
+    bits += [(int(w1[(i - 128) >> 5]) >> (i & 31)) & 1 for i in range(128, 200)]
+    assert list(st.pop[2]) == [1 - 2 * b for b in bits]
+
+
+def test_generation_invariants_long():
+    # N = 200 (four mask words on the GPU): invariants over a few generations
+    n = 200
+    st = O.MemeticState(n, 12, 77, 1)
+    prev = st.bestE
+    for g in range(3):
+        assert st.advance(1, MEM, O.P_COMB_090, O.p_mut_inv_n(n)) == 1
+        assert st.bestE <= prev
+        prev = st.bestE
+        assert npref.energy(st.best) == st.bestE
+        assert list(st.popE) == list(npref.energies_rows(st.pop))
+
+
 def test_generation_invariants():
     n = 20
     st = O.MemeticState(n, 100, 1000, 0)
@@ -148,6 +172,25 @@ def test_batched_snapshot_and_merge_order():
             want[dst], wantE[dst] = snap[src], snapE[src]
         st.advance(1, zero, 0, 0, children=B)
         assert np.array_equal(st.pop, want) and np.array_equal(st.popE, wantE)
+
+
+def test_batched_mutation_words():
+    # K = 1, sampling only, empty walks: every child is member 0 with bit i
+    # flipped when word i%4 of draw (pop, g, 64 b + i/4, MUT) is below the
+    # threshold; the last child (b = B - 1) is what member 0 holds after the
+    # merge.  N = 256 uses all 64 mutation words of a child.
+    n, B, seed, pid, thr = 256, 3, 17, 1, 0x20000000
+    zero = O.Schedule(O.STEPS_FIXED, 0, O.TENURE_LINEAR, 0, 1, 0, 0, 1, 0, 1)
+    st = O.MemeticState(n, 1, seed, pid)
+    for g in range(3):
+        before = st.pop[0].copy()
+        st.advance(1, zero, 0, thr, children=B)
+        b = B - 1
+        flip = [int(O.draw(seed, pid, g, 64 * b + (i >> 2), O.TAG_MUT)[i & 3]) < thr
+                for i in range(n)]
+        want = np.where(flip, -before, before).astype(np.int8)
+        assert np.array_equal(st.pop[0], want)
+        assert st.popE[0] == npref.energy(want)
 
 
 def test_batched_invariants_and_resume():

@@ -84,7 +84,7 @@ def test_paper_n92_pair_is_alternation_image():
     assert O.energy(a) == O.energy(b) == 490
 
 
-@pytest.mark.parametrize("n", [3, 4, 5, 17, 64, 120, 128])
+@pytest.mark.parametrize("n", [3, 4, 5, 17, 64, 120, 128, 129, 200, 256])
 def test_closed_forms(n):
     ones = np.ones(n, dtype=np.int8)
     alt = np.array([(-1) ** i for i in range(n)], dtype=np.int8)

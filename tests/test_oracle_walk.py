@@ -52,13 +52,33 @@ def test_random_start_statistics():
     assert list(S[5]) == [1 - 2 * b for b in bits]
 
 
-@pytest.mark.parametrize("n,asp", [(5, 1), (16, 0), (16, 1), (33, 1), (64, 1), (64, 0), (100, 1), (128, 1)])
+def test_random_start_beyond_128():
+    # bits 128.. of a start come from draw (walk, 0, 1, TAG_START), read like
+    # the first; the first 128 bits do not depend on N
+    n = 256
+    s = O.random_start(n, 1001, 9)
+    w0 = O.draw(1001, 9, 0, 0, O.TAG_START)
+    w1 = O.draw(1001, 9, 0, 1, O.TAG_START)
+    bits = [(int(w0[i >> 5]) >> (i & 31)) & 1 for i in range(128)]
+    bits += [(int(w1[i >> 5]) >> (i & 31)) & 1 for i in range(128)]
+    assert list(s) == [1 - 2 * b for b in bits]
+    assert np.array_equal(O.random_start(200, 1001, 9), s[:200])
+    assert np.array_equal(O.random_start(100, 1001, 9), s[:100])
+    # and the mean energy of uniform starts, N(N-1)/2, at N = 200
+    S = np.stack([O.random_start(200, 1001, w) for w in range(1500)])
+    e = npref.energies_rows(S)
+    assert abs(e.mean() - 200 * 199 / 2) < 4 * e.std() / np.sqrt(len(S))
+
+
+@pytest.mark.parametrize("n,asp", [(5, 1), (16, 0), (16, 1), (33, 1), (64, 1), (64, 0), (100, 1), (128, 1),
+                                   (129, 1), (200, 0), (256, 1)])
 def test_walk_tables_equal_recompute(n, asp):
     lo, hi = max(n // 10, 0), max(n // 5, 1)
-    for w in range(3):
+    steps = 3 * n if n <= 64 else (n if n <= 128 else 12)  # recompute is O(N^3) per step
+    for w in range(3 if n <= 128 else 1):
         s = O.random_start(n, 42, w)
-        a = O.tabu_walk(s, 42, w, 0, 3 * n if n <= 64 else n, lo, hi, asp, recompute=True, want_trace=True)
-        b = O.tabu_walk(s, 42, w, 0, 3 * n if n <= 64 else n, lo, hi, asp, recompute=False, want_trace=True)
+        a = O.tabu_walk(s, 42, w, 0, steps, lo, hi, asp, recompute=True, want_trace=True)
+        b = O.tabu_walk(s, 42, w, 0, steps, lo, hi, asp, recompute=False, want_trace=True)
         assert np.array_equal(a[0], b[0]) and a[1:3] == b[1:3]
         assert np.array_equal(a[3], b[3]) and np.array_equal(a[4], b[4])
 
@@ -100,9 +120,10 @@ def _check_walk_properties(start, steps, lo, hi, asp, best, best_e, final_e, tra
 
 
 @pytest.mark.parametrize("n,asp,lo,hi", [(7, 1, 0, 1), (12, 0, 1, 2), (20, 1, 1, 3), (20, 0, 2, 4),
-                                         (31, 1, 3, 6), (64, 1, 6, 12), (64, 0, 6, 12), (96, 1, 9, 19)])
+                                         (31, 1, 3, 6), (64, 1, 6, 12), (64, 0, 6, 12), (96, 1, 9, 19),
+                                         (160, 1, 16, 32), (256, 0, 25, 51)])
 def test_walk_properties(n, asp, lo, hi):
-    steps = min(3 * n, 150)
+    steps = min(3 * n, 150 if n <= 128 else 40)
     for w in range(2):
         s = O.random_start(n, 7, w)
         best, be, fe, tr, te = O.tabu_walk(s, 7, w, 3, steps, lo, hi, asp, want_trace=True)
