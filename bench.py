@@ -269,6 +269,24 @@ def ttt_section(args, lb):
         row["reached"] = hit[0] is not None
         if "seconds_plain" in row and "seconds_persistent" in row:
             row["persistent_speedup_vs_plain"] = row["seconds_plain"] / row["seconds_persistent"]
+        # batched generations: B children per generation from one snapshot
+        # (another trajectory than one child per generation), persistent
+        # form, the same budget of children
+        for B in [int(b) for b in args.ttt_children.split(",") if b]:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = lb.memetic_run(wl.K, wl.rules, max(G // B, 1), wl.pops, wl.seed, n_uniform=n,
+                               mode=MODES["persistent"], chunk=args.ttt_chunk, target=tgt,
+                               stop_all=1, children=B)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            h = r.hit_gen.cpu().numpy()
+            gens = int(r.gens_done.max().item())
+            row[f"children_{B}"] = {
+                "seconds": dt, "hit_generation": int(h[h >= 0].min()) if (h >= 0).any() else None,
+                "best_e": int(r.best_e.min().item()), "generations_run": gens,
+                "us_per_generation": dt / max(gens, 1) * 1e6,
+                "us_per_child": dt / max(gens * B, 1) * 1e6}
         res["targets"].append(row)
     return res
 
@@ -363,6 +381,8 @@ def main() -> int:
     ap.add_argument("--ttt-targets", default="1200,1107,1028")
     ap.add_argument("--ttt-modes", default="persistent,graph,plain")
     ap.add_argument("--ttt-chunk", type=int, default=64)
+    ap.add_argument("--ttt-children", default="8",
+                    help="children per generation of the batched-generation rows (comma list)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=8192)

@@ -43,7 +43,7 @@ extern "C" {
 #endif
 
 #define LABS_MIN_N 3
-#define LABS_MAX_N 128
+#define LABS_MAX_N 256
 #define LABS_MAX_K 128 /* largest memetic population */
 
 typedef enum labs_status {
@@ -152,8 +152,8 @@ int labs_bruteforce_min(labs_handle *h, int32_t n, int32_t *min_e, int64_t *coun
 /*
  * Independent tabu walks (Alg. 2; the thread-parallel form of Alg. 4, one
  * walk per 64-lane wavefront).  Walk w (0 <= w < walks) starts from row w
- * of `starts`, or -- when starts == NULL -- from the 128-bit draw
- * (w, 0, 0, START): bit i set means s_i = -1.  Each of its maxIter steps
+ * of `starts`, or -- when starts == NULL -- from the 128-bit draws
+ * (w, 0, q, START): bit i % 128 of draw q = i / 128 set means s_i = -1.  Each of its maxIter steps
  * scores all N single-flip neighbours, takes the lowest-energy admissible
  * one (ties: uniform by the step's draw), marks it tabu for a random tenure
  * and keeps the best sequence visited (strict improvement).
@@ -225,7 +225,7 @@ typedef struct labs_memetic_params {
     int32_t stop_all;    /* 1: once any replica reaches target_e, every
                             replica stops at the end of the current chunk
                             (the global termination flag of Sec. IV) */
-    int32_t waves_per_replica; /* replicas with N > 64: 1 or 2 wavefronts
+    int32_t waves_per_replica; /* replicas with 64 < N <= 128: 1 or 2 wavefronts
                             (two split each step's neighbours and exchange
                             their minima: lower latency per generation, for
                             batches too small to fill the device); 0 picks
@@ -239,16 +239,20 @@ typedef struct labs_memetic_params {
                             each), then merged in order b = 0..B-1 as Alg. 1
                             merges its one child; child b draws from
                             (replica, g, 2b | 2b+1, GEN), mutates with
-                            (replica, g, 32b + i/4, MUT) and walks as
+                            (replica, g, 64b + i/4, MUT) and walks as
                             generation g*B + b.  Targets are checked once per
-                            generation; hit_gen counts generations. */
+                            generation; hit_gen counts generations.  For
+                            N > 128 a child's walk takes 17.7 KB of LDS, and
+                            B is further limited to what one workgroup can
+                            hold (LABS_E_INVAL beyond). */
 } labs_memetic_params;
 
 #define LABS_MAX_CHILDREN 8
 
 /*
  * Run `pops` independent memetic replicas (population id = index).
- * Replica p: K members from the draws (p, m, 0, INIT); per generation g,
+ * Replica p: K members from the draws (p, m, q, INIT), bit i of member m
+ * being bit i % 128 of draw q = i / 128 as for walk starts; per generation g,
  * crossover (binary-tournament parents, one-point cut) or sampling, per-bit
  * mutation, a tabu walk with entity p and generation g, strict best update
  * and replacement of a random member -- the order of Alg. 1.
@@ -278,7 +282,7 @@ int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
  * The server runs its own host thread and HIP stream.
  *   params     K, rules, target, chunk (generations/mode are per request)
  *   max_slots  resident replicas (device memory: about
- *              (K*20 + 64) bytes each); admission never exceeds it
+ *              (K*36 + 64) bytes each); admission never exceeds it
  */
 typedef struct labs_server labs_server;
 

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblabs.so")
 
 LABS_OK, LABS_E_INVAL, LABS_E_NOMEM, LABS_E_HIP, LABS_E_CANCELLED, LABS_E_NOTFOUND, LABS_E_AGAIN = range(7)
-MIN_N, MAX_N, MAX_K = 3, 128, 128
+MIN_N, MAX_N, MAX_K = 3, 256, 128
 
 EXPORTED = [
     "labs_create", "labs_destroy", "labs_last_error", "labs_status_name", "labs_version",

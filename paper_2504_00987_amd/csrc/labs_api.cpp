@@ -185,7 +185,7 @@ RuleParams to_rule(const labs_tabu_params &p) {
     return r;
 }
 
-int bucket_of(int n) { return std::min(7, std::max(0, (n - 1) / 16)); }
+int bucket_of(int n) { return std::min(LABS_MAX_N / 16 - 1, std::max(0, (n - 1) / 16)); }
 
 // Four walks per workgroup, one workgroup per four walks: the four
 // wavefronts land on the four SIMDs of a CU, and the results of neighbouring
@@ -247,21 +247,22 @@ int labs_create(labs_handle **out, int device) {
     }
     h->num_cus = prop.multiProcessorCount;
     h->arch = prop.gcnArchName;
-    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&h->side2, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&h->side3, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ws_event, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->stage_event, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->fork_event, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->join_event, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->join2_event, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->join3_event, hipEventDisableTiming) != hipSuccess ||
-        prepare_memetic_kernels() != hipSuccess) {
-        delete h;
+    bool ok = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&h->ws_event, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&h->stage_event, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&h->sides.fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < kSideStreams && ok; ++i)
+        ok = hipStreamCreateWithFlags(&h->sides.s[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&h->sides.join[i], hipEventDisableTiming) == hipSuccess;
+    if (ok) {
+        h->max_children_wide = prepare_memetic_kernels();
+        ok = h->max_children_wide >= 0;
+    }
+    if (!ok) {
+        labs_destroy(h);
         return LABS_E_HIP;
     }
-    h->tuned.assign(8, labs_launch{0, 0, 0});
+    h->tuned.assign(LABS_MAX_N / 16, labs_launch{0, 0, 0});
     *out = h;
     return LABS_OK;
 }
@@ -275,14 +276,12 @@ int labs_destroy(labs_handle *h) {
     h->pin.release();
     if (h->ws_event) hipEventDestroy(h->ws_event);
     if (h->stage_event) hipEventDestroy(h->stage_event);
-    if (h->fork_event) hipEventDestroy(h->fork_event);
-    if (h->join_event) hipEventDestroy(h->join_event);
-    if (h->join2_event) hipEventDestroy(h->join2_event);
-    if (h->join3_event) hipEventDestroy(h->join3_event);
+    if (h->sides.fork) hipEventDestroy(h->sides.fork);
+    for (int i = 0; i < kSideStreams; ++i) {
+        if (h->sides.join[i]) hipEventDestroy(h->sides.join[i]);
+        if (h->sides.s[i]) hipStreamDestroy(h->sides.s[i]);
+    }
     if (h->stream) hipStreamDestroy(h->stream);
-    if (h->side) hipStreamDestroy(h->side);
-    if (h->side2) hipStreamDestroy(h->side2);
-    if (h->side3) hipStreamDestroy(h->side3);
     delete h;
     return LABS_OK;
 }
@@ -442,7 +441,7 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
     const labs_launch L = force ? *force : choose_launch(h, n_max, uneven);
 
     DeviceGuard g(h->device);
-    // Workspace: [queue heads (512 B)] [ns (W int32)] [order (W int32)].
+    // Workspace: [queue heads (32 words per class)] [ns (W int32)] [order (W int32)].
     // The GPU orders its reuse after the previous call's kernels; the host
     // only waits for the previous copy out of the pinned staging buffer.
     constexpr size_t kHeads = 32 * sizeof(uint32_t) * kWalkClasses;
@@ -471,7 +470,7 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
         a.ns = dn;
         a.order = dn + W;
         // the order is longest first, so the classes are consecutive runs
-        int64_t count[kWalkClasses] = {0, 0, 0, 0};
+        int64_t count[kWalkClasses] = {};
         for (int64_t i = 0; i < W; ++i) ++count[walk_class(ns_host[i])];
         int64_t end = 0;
         for (int c = 0; c < kWalkClasses; ++c) a.class_end[c] = end += count[c];
@@ -496,27 +495,26 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
     const int groups = L.persistent ? persistent_groups(h, L) : 0;
     // The length classes present run concurrently: the first on `s`, the
     // others on the handle's side streams, forked from and joined into `s`.
-    hipStream_t sides[3] = {h->side, h->side2, h->side3};
-    hipEvent_t joins[3] = {h->join_event, h->join2_event, h->join3_event};
+    const SideStreams &sides = h->sides;
     hipStream_t streams[kWalkClasses];
     int n_sides = 0;
     for (int c = 0, used = 0; c < kWalkClasses; ++c) {
         const int64_t begin = c ? a.class_end[c - 1] : 0;
         streams[c] = s;
-        if (a.class_end[c] > begin && used++ > 0) streams[c] = sides[n_sides++];
+        if (a.class_end[c] > begin && used++ > 0) streams[c] = sides.s[n_sides++];
     }
     hipError_t e = hipSuccess;
     if (n_sides > 0) {
-        e = hipEventRecord(h->fork_event, s);
+        e = hipEventRecord(sides.fork, s);
         for (int i = 0; i < n_sides && e == hipSuccess; ++i)
-            e = hipStreamWaitEvent(sides[i], h->fork_event, 0);
+            e = hipStreamWaitEvent(sides.s[i], sides.fork, 0);
         if (e != hipSuccess) return hip_fail(h, e, "fork to side streams");
     }
     e = launch_tabu(a, L.waves_per_group, groups, streams);
     if (e != hipSuccess) return hip_fail(h, e, "tabu kernel launch");
     for (int i = 0; i < n_sides && e == hipSuccess; ++i) {
-        e = hipEventRecord(joins[i], sides[i]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(s, joins[i], 0);
+        e = hipEventRecord(sides.join[i], sides.s[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, sides.join[i], 0);
     }
     if (e != hipSuccess) return hip_fail(h, e, "join from side streams");
     return ws_release(h, s);

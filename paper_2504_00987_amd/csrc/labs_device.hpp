@@ -131,7 +131,8 @@ __device__ __forceinline__ int wave_sum(int v) {
 }
 
 // ---------------------------------------------------------------------------
-// Sequence masks: 64-bit for N <= 64, 128-bit for N <= 128.
+// Sequence masks: 64-bit for N <= 64, 128-bit for N <= 128, 256-bit for
+// N <= 256.
 // ---------------------------------------------------------------------------
 struct M128 {
     uint64_t lo, hi;
@@ -195,24 +196,95 @@ __device__ __forceinline__ M128 m_onebit(M128, int i) {
     return r;
 }
 
+// 256-bit masks for N <= 256 (four words, selected by value so that a
+// variable word index never forces the mask out of registers).
+struct M256 {
+    uint64_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ uint64_t m_word(const M256 &a, int i) {
+    return i == 0 ? a.w0 : i == 1 ? a.w1 : i == 2 ? a.w2 : i == 3 ? a.w3 : 0ull;
+}
+__device__ __forceinline__ M256 m_and(M256 a, M256 b) {
+    return {a.w0 & b.w0, a.w1 & b.w1, a.w2 & b.w2, a.w3 & b.w3};
+}
+__device__ __forceinline__ M256 m_or(M256 a, M256 b) {
+    return {a.w0 | b.w0, a.w1 | b.w1, a.w2 | b.w2, a.w3 | b.w3};
+}
+__device__ __forceinline__ M256 m_xor(M256 a, M256 b) {
+    return {a.w0 ^ b.w0, a.w1 ^ b.w1, a.w2 ^ b.w2, a.w3 ^ b.w3};
+}
+__device__ __forceinline__ M256 m_not(M256 a) { return {~a.w0, ~a.w1, ~a.w2, ~a.w3}; }
+__device__ __forceinline__ bool m_eq(M256 a, M256 b) {
+    return a.w0 == b.w0 && a.w1 == b.w1 && a.w2 == b.w2 && a.w3 == b.w3;
+}
+__device__ __forceinline__ int m_popc(M256 a) {
+    return __popcll(a.w0) + __popcll(a.w1) + __popcll(a.w2) + __popcll(a.w3);
+}
+// a >> sh for 0 <= sh <= 256.
+__device__ __forceinline__ M256 m_shr(M256 a, int sh) {
+    const int q = sh >> 6, r = sh & 63;
+    auto out = [&](int i) {
+        const uint64_t lo = m_word(a, i + q);
+        return r == 0 ? lo : (lo >> r) | (m_word(a, i + q + 1) << (64 - r));
+    };
+    return {out(0), out(1), out(2), out(3)};
+}
+__device__ __forceinline__ M256 m_low(M256, int n) {
+    auto word = [&](int i) {
+        const int b = n - 64 * i;
+        return b >= 64 ? ~0ull : b <= 0 ? 0ull : ((1ull << b) - 1ull);
+    };
+    return {word(0), word(1), word(2), word(3)};
+}
+__device__ __forceinline__ int m_bit(M256 a, int i) {
+    return (int)((m_word(a, i >> 6) >> (i & 63)) & 1ull);
+}
+__device__ __forceinline__ M256 m_onebit(M256, int i) {
+    const int q = i >> 6;
+    const uint64_t b = 1ull << (i & 63);
+    return {q == 0 ? b : 0ull, q == 1 ? b : 0ull, q == 2 ? b : 0ull, q == 3 ? b : 0ull};
+}
+
 template <int NW> struct MaskOf;
 template <> struct MaskOf<1> { using type = uint64_t; };
 template <> struct MaskOf<2> { using type = M128; };
+template <> struct MaskOf<4> { using type = M256; };
 
-__device__ __forceinline__ uint64_t mask_from(uint64_t lo, uint64_t) { return lo; }
-__device__ __forceinline__ M128 mask_from(uint64_t lo, uint64_t hi, M128) { return {lo, hi}; }
-__device__ __forceinline__ uint64_t mask_lo(uint64_t a) { return a; }
-__device__ __forceinline__ uint64_t mask_hi(uint64_t) { return 0ull; }
-__device__ __forceinline__ uint64_t mask_lo(M128 a) { return a.lo; }
-__device__ __forceinline__ uint64_t mask_hi(M128 a) { return a.hi; }
+// Word h (0 <= h < 4) of a mask; words past its width are 0.
+__device__ __forceinline__ uint64_t mask_word(uint64_t a, int h) { return h == 0 ? a : 0ull; }
+__device__ __forceinline__ uint64_t mask_word(const M128 &a, int h) {
+    return h == 0 ? a.lo : h == 1 ? a.hi : 0ull;
+}
+__device__ __forceinline__ uint64_t mask_word(const M256 &a, int h) { return m_word(a, h); }
+template <typename Mask>
+__device__ __forceinline__ uint64_t mask_lo(const Mask &a) { return mask_word(a, 0); }
+template <typename Mask>
+__device__ __forceinline__ uint64_t mask_hi(const Mask &a) { return mask_word(a, 1); }
 
+// A mask of NW words from four words (words past NW are ignored).
 template <int NW>
-__device__ __forceinline__ typename MaskOf<NW>::type make_mask(uint64_t lo, uint64_t hi) {
+__device__ __forceinline__ typename MaskOf<NW>::type make_mask(uint64_t w0, uint64_t w1,
+                                                               uint64_t w2 = 0ull,
+                                                               uint64_t w3 = 0ull) {
     if constexpr (NW == 1) {
-        return lo;
+        return w0;
+    } else if constexpr (NW == 2) {
+        return M128{w0, w1};
     } else {
-        return M128{lo, hi};
+        return M256{w0, w1, w2, w3};
     }
+}
+
+// Mask of NW words stored at p[0 .. NW).
+template <int NW>
+__device__ __forceinline__ typename MaskOf<NW>::type load_mask(const uint64_t *p) {
+    return make_mask<NW>(p[0], NW > 1 ? p[1] : 0ull, NW > 2 ? p[2] : 0ull, NW > 2 ? p[3] : 0ull);
+}
+template <int NW, typename Mask>
+__device__ __forceinline__ void store_mask(uint64_t *p, const Mask &m) {
+#pragma unroll
+    for (int h = 0; h < NW; ++h) p[h] = mask_word(m, h);
 }
 
 // ---------------------------------------------------------------------------
@@ -283,7 +355,9 @@ struct WalkResult {
 //   at any x is the records x, x+16, x+32, ...; lanes that read
 //   consecutive starts touch consecutive 16-byte slots (no bank conflicts);
 //   the plain copies hold P[0 .. LEN) and Q[0 .. LEN) for the C update;
-//   CB[k-1] = C_k as int8.
+//   CB[k-1] = C_k as int8 (N <= 128), or C_k >> 1 (N <= 256, where |C_k|
+//   may reach 255; C_k = 2 (C_k >> 1) + ((N - k) & 1) since C_k is a sum of
+//   N - k terms +-1).
 // NREC covers the farthest record a window reads (start <= 64 NW, plus
 // NBIG - 1 chunks); LEN the farthest byte the C update reads.
 template <int NW> struct WalkLds;
@@ -294,6 +368,10 @@ template <> struct WalkLds<1> {
 template <> struct WalkLds<2> {
     static constexpr int NBIG = 8, LEN = 256, CLEN = 128;
     static constexpr int NREC = 128 + 16 * (NBIG - 1) + 1;
+};
+template <> struct WalkLds<4> {
+    static constexpr int NBIG = 16, LEN = 512, CLEN = 256;
+    static constexpr int NREC = 256 + 16 * (NBIG - 1) + 1;
 };
 constexpr int kSpareRecords = 15;
 template <int NW>
@@ -339,8 +417,8 @@ __device__ __forceinline__ void walk_sync() {
 
 // Runs one walk of sch.T steps from mask M0 (bits >= N must be clear).
 //   NW     neighbours per lane when one wavefront runs the walk: 1 for
-//          N <= 64, 2 for N <= 128 (also fixes the mask width and the LDS
-//          layout)
+//          N <= 64, 2 for N <= 128, 4 for N <= 256 (also fixes the mask
+//          width and the LDS layout)
 //   SPLIT  wavefronts per walk: 1, or 2 with NW = 2, wavefront `part`
 //          (0 or 1) owning neighbours and lags 64 part .. 64 part + 63; the
 //          two exchange their minima through LDS (two barriers per step)
@@ -357,6 +435,7 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
                                                     int16_t *__restrict__ trace,
                                                     const int part_in = 0) {
     static_assert(SPLIT == 1 || (SPLIT == 2 && NW == 2), "two wavefronts per walk need N <= 128");
+    static_assert(NW == 1 || NW == 2 || NW == 4, "mask widths of 64, 128 or 256 bits");
     static_assert(NB >= 1 && NB <= WalkLds<NW>::NBIG, "chunk count beyond the layout");
     constexpr int NS = (NB + 1) / 2;  // chunks of the shorter window (N - 1 <= 16 NB)
     using Mask = typename MaskOf<NW>::type;
@@ -374,15 +453,33 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
     sch.hi = __builtin_amdgcn_readfirstlane(sch_in.hi);
     // The sequence is wave-uniform; pinning it to scalar registers keeps the
     // per-move mask arithmetic on the scalar unit.
-    Mask M = make_mask<NW>(uniform64(mask_lo(M0)), uniform64(mask_hi(M0)));
+    Mask M = make_mask<NW>(uniform64(mask_word(M0, 0)), uniform64(mask_word(M0, 1)),
+                           uniform64(mask_word(M0, 2)), uniform64(mask_word(M0, 3)));
 
     // Reversed sequence: bit i of Mr is bit N-1-i of M.
     Mask Mr;
     {
-        const uint64_t lo = ballot(lane < N && m_bit(M, N - 1 - lane));
-        uint64_t hi = 0ull;
-        if constexpr (NW == 2) hi = ballot(lane + 64 < N && m_bit(M, N - 65 - lane));
-        Mr = make_mask<NW>(lo, hi);
+        uint64_t r[4] = {0ull, 0ull, 0ull, 0ull};
+#pragma unroll
+        for (int h = 0; h < NW; ++h) {
+            const int i = lane + 64 * h;
+            r[h] = ballot(i < N && m_bit(M, N - 1 - i));
+        }
+        Mr = make_mask<NW>(r[0], r[1], r[2], r[3]);
+    }
+    // N <= 256 keeps C_k >> 1 in the int8 mirror; the parity part of
+    // sum_k t_jk C_k is then sum_{k: N-k odd} t_jk = S_q - (N odd) s_j with
+    // S_q the sum of s_i over positions i of parity q = (j + N - 1) mod 2
+    // (every i != j in range is j + k or j - k for exactly one k, and
+    // N - k odd <=> i = q mod 2).  S_0, S_1 are wave-uniform.
+    constexpr bool kHalfC = NW == 4;
+    int S0 = 0, S1 = 0;
+    if constexpr (kHalfC) {
+        constexpr uint64_t kEven = 0x5555555555555555ull;
+        const M256 ev{kEven, kEven, kEven, kEven};
+        const int neg0 = m_popc(m_and(M, ev)), neg1 = m_popc(m_and(M, m_not(ev)));
+        S0 = (N + 1) / 2 - 2 * neg0;
+        S1 = N / 2 - 2 * neg1;
     }
 
     constexpr int kRunBytes = 16 * (kSpareRecords + Cfg::NREC);
@@ -418,7 +515,7 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
         const int k = lane + 1 + 64 * half(w);
         C[w] = k < N ? lag_corr(M, N, k) : 0;
         sq += C[w] * C[w];
-        CB[k - 1] = (int8_t)C[w];
+        CB[k - 1] = (int8_t)(kHalfC ? C[w] >> 1 : C[w]);
     }
     int E = wave_sum(sq);
     if constexpr (SPLIT == 2) {
@@ -482,8 +579,12 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
     // the registers for early loads would cost occupancy; two wavefronts:
     // the other one's byte update must be visible first).
     constexpr bool kPipelineWindows = NW == 1 && SPLIT == 1;
-    uint4 wb[NL][NB];
-    uint4 ws[NL][NS];
+    // four neighbours per lane: each neighbour's chunks are read where they
+    // are used (all of them at once would not fit the register file)
+    constexpr bool kPreload = NW != 4;
+    constexpr int NLP = kPreload ? NL : 1;
+    uint4 wb[NLP][NB];
+    uint4 ws[NLP][NS];
     if constexpr (kPipelineWindows) {
         walk_sync<SPLIT>();
 #pragma unroll
@@ -504,7 +605,7 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
             dr1 = d.w1;
         }
         walk_sync<SPLIT>();  // the previous move's bytes are visible
-        if constexpr (!kPipelineWindows) {
+        if constexpr (!kPipelineWindows && kPreload) {
 #pragma unroll
             for (int w = 0; w < NL; ++w) {
 #pragma unroll
@@ -523,22 +624,46 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
         // aspiration (candE_j < bestE) is d_j < thr.  Energies are all
         // congruent mod 4, so thr is exact.
         const int thr = ((bestE - E) >> 2) - (N - 1);
+        // parity part (kHalfC): S_q - (N odd) s_j, q = (j + N - 1) mod 2 is
+        // the same for all of this lane's neighbours
+        const int Sq = ((lane + N - 1) & 1) ? S1 : S0;
         int key[NL];
 #pragma unroll
         for (int w = 0; w < NL; ++w) {
             const int j = lane + 64 * half(w);
-            int v = 0;  // sum_k t_jk C_k
+            int v = 0;  // sum_k t_jk C_k (kHalfC: sum_k t_jk (C_k >> 1))
             int u = 0;  // sum_k s_{j+k} s_{j-k}
+            if constexpr (kPreload) {
 #pragma unroll
-            for (int r = 0; r < NB; ++r) {
-                v = dot16(wb[w][r], cc[r], v);
-                if (r < NS) {
-                    v = dot16(ws[w][r], cc[r], v);
-                    u = dot16(wb[w][r], ws[w][r], u);
+                for (int r = 0; r < NB; ++r) {
+                    v = dot16(wb[w][r], cc[r], v);
+                    if (r < NS) {
+                        v = dot16(ws[w][r], cc[r], v);
+                        u = dot16(wb[w][r], ws[w][r], u);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < NB; ++r) {
+                    const uint4 b = ((const uint4 *)big[w])[16 * r];
+                    v = dot16(b, cc[r], v);
+                    if (r < NS) {
+                        const uint4 sm = ((const uint4 *)small[w])[16 * r];
+                        v = dot16(sm, cc[r], v);
+                        u = dot16(b, sm, u);
+                    }
                 }
             }
-            const uint64_t mw = half(w) == 0 ? mask_lo(M) : mask_hi(M);
-            const int d = 2 * u + (lane_bit(mw) ? v : -v);  // 2 u_j - s_j v_j
+            const bool neg = lane_bit(mask_word(M, half(w)));  // s_j = -1
+            int d;
+            if constexpr (kHalfC) {
+                // v_j = 2 v + S_q - (N odd) s_j, so
+                // 2 u - s_j v_j = 2 u - s_j (2 v + S_q) + (N odd)
+                const int vq = 2 * v + Sq;
+                d = 2 * u + (neg ? vq : -vq) + (N & 1);
+            } else {
+                d = 2 * u + (neg ? v : -v);  // 2 u_j - s_j v_j
+            }
             const bool admissible = tabu[w] < t || (aspiration && d < thr);
             key[w] = j < N && admissible ? d : INT_MAX;
         }
@@ -546,13 +671,18 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
         // Admissible minimum, ties broken by the step's draw: the r-th
         // (ascending) of the tied moves, r = (u0 * count) >> 32.
         int m;
-        uint64_t T0, T1 = 0ull;
+        uint64_t T0, T1 = 0ull, T2 = 0ull, T3 = 0ull;
         if constexpr (SPLIT == 1) {
             int kmin = key[0];
-            if constexpr (NW == 2) kmin = min(kmin, key[1]);
+            if constexpr (NW >= 2) kmin = min(kmin, key[1]);
+            if constexpr (NW == 4) kmin = min(kmin, min(key[2], key[3]));
             m = wave_min(kmin);
             T0 = ballot(key[0] == m);
-            if constexpr (NW == 2) T1 = ballot(key[1] == m);
+            if constexpr (NW >= 2) T1 = ballot(key[1] == m);
+            if constexpr (NW == 4) {
+                T2 = ballot(key[2] == m);
+                T3 = ballot(key[3] == m);
+            }
         } else {
             const int mine = wave_min(key[0]);
             const uint64_t tmine = ballot(key[0] == mine);
@@ -572,32 +702,64 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
         }
         const uint32_t u0 = readlane_u(dr0, slot);
         const uint32_t u1 = readlane_u(dr1, slot);
-        uint64_t tied = T0;
-        int pick_base = 0;
-        if constexpr (NW == 2) {
-            if (T0 == 0ull) {
+        int pick;
+        if constexpr (NW == 4) {
+            // the r-th tied move over the four 64-neighbour words (r = 0
+            // when only one is tied: the first word with a tied move)
+            const int c0 = __popc((uint32_t)T0) + __popc((uint32_t)(T0 >> 32));
+            const int c1 = __popc((uint32_t)T1) + __popc((uint32_t)(T1 >> 32));
+            const int c2 = __popc((uint32_t)T2) + __popc((uint32_t)(T2 >> 32));
+            const int c3 = __popc((uint32_t)T3) + __popc((uint32_t)(T3 >> 32));
+            const int count = c0 + c1 + c2 + c3;
+            int r = count > 1 ? (int)below(u0, (uint32_t)count) : 0;
+            uint64_t tied;
+            int base;
+            if (r < c0) {
+                tied = T0;
+                base = 0;
+            } else if (r < c0 + c1) {
                 tied = T1;
-                pick_base = 64;
-            }
-        }
-        // several tied moves: take the r-th (counts in 32-bit halves keep
-        // the test on the scalar unit)
-        const int c0 = __popc((uint32_t)T0) + __popc((uint32_t)(T0 >> 32));
-        const int count = c0 + __popc((uint32_t)T1) + __popc((uint32_t)(T1 >> 32));
-        if (count > 1) {
-            int r = (int)below(u0, (uint32_t)count);
-            tied = T0;
-            pick_base = 0;
-            if constexpr (NW == 2) {
-                if (r >= c0) {
-                    tied = T1;
-                    pick_base = 64;
-                    r -= c0;
-                }
+                base = 64;
+                r -= c0;
+            } else if (r < c0 + c1 + c2) {
+                tied = T2;
+                base = 128;
+                r -= c0 + c1;
+            } else {
+                tied = T3;
+                base = 192;
+                r -= c0 + c1 + c2;
             }
             for (int i = 0; i < r; ++i) tied &= tied - 1ull;  // drop the r lowest
+            pick = base + __builtin_ctzll(tied);
+        } else {
+            uint64_t tied = T0;
+            int pick_base = 0;
+            if constexpr (NW == 2) {
+                if (T0 == 0ull) {
+                    tied = T1;
+                    pick_base = 64;
+                }
+            }
+            // several tied moves: take the r-th (counts in 32-bit halves keep
+            // the test on the scalar unit)
+            const int c0 = __popc((uint32_t)T0) + __popc((uint32_t)(T0 >> 32));
+            const int count = c0 + __popc((uint32_t)T1) + __popc((uint32_t)(T1 >> 32));
+            if (count > 1) {
+                int r = (int)below(u0, (uint32_t)count);
+                tied = T0;
+                pick_base = 0;
+                if constexpr (NW == 2) {
+                    if (r >= c0) {
+                        tied = T1;
+                        pick_base = 64;
+                        r -= c0;
+                    }
+                }
+                for (int i = 0; i < r; ++i) tied &= tied - 1ull;  // drop the r lowest
+            }
+            pick = pick_base + __builtin_ctzll(tied);
         }
-        const int pick = pick_base + __builtin_ctzll(tied);
 
         // Apply the move: tenure, sequence, energy, best.
         const int tenure = sch.lo + (int)below(u1, (uint32_t)(sch.hi - sch.lo + 1));
@@ -606,6 +768,12 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
         const int sm = 1 - 2 * m_bit(M, pick);  // old s_pick
         M = m_xor(M, m_onebit(M, pick));
         E += 4 * (N - 1 + m);
+        if constexpr (kHalfC) {
+            if (pick & 1)
+                S1 -= 2 * sm;
+            else
+                S0 -= 2 * sm;
+        }
         if (E < bestE) {
             bestE = E;
             best = M;
@@ -640,7 +808,7 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
                 const int t_k = (int)((const int8_t *)PP)[pick + k] +
                                 (int)((const int8_t *)PQ)[N - 1 - pick + k];
                 C[w] += k2 * t_k;
-                CB[k - 1] = (int8_t)C[w];
+                CB[k - 1] = (int8_t)(kHalfC ? C[w] >> 1 : C[w]);
             }
         }
     }

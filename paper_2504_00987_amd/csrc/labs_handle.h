@@ -43,15 +43,10 @@ struct labs_handle {
     std::string arch;
     std::string last_error;
     hipStream_t stream = nullptr;      // internal stream (default priority)
-    hipStream_t side = nullptr;        // second stream for the narrow part of a mixed batch
-    hipStream_t side2 = nullptr;       // third and fourth streams: further length classes
-    hipStream_t side3 = nullptr;
+    liblabs::SideStreams sides{};      // further length classes of a mixed batch
     hipEvent_t ws_event = nullptr;     // completion of the last device-workspace user
     hipEvent_t stage_event = nullptr;  // completion of the last copy out of `pin`
-    hipEvent_t fork_event = nullptr;
-    hipEvent_t join_event = nullptr;
-    hipEvent_t join2_event = nullptr;
-    hipEvent_t join3_event = nullptr;
+    int max_children_wide = 0;         // batched children per generation at N > 128
     bool ws_event_valid = false;
     bool stage_event_valid = false;
     liblabs::DevBuf ws;                   // tabu workspace: queue head, ns, order
@@ -84,13 +79,16 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
                     int32_t *final_e, int16_t *trace, int32_t trace_stride, hipStream_t s,
                     const labs_launch *force);
 int check_memetic(labs_handle *h, const labs_memetic_params *p);
-// 1 when replicas with N > 64 should run on two wavefronts each.
+// Children per generation against what the device fits (classes: bit c set
+// when a replica of memetic_class c is present).
+int check_children(labs_handle *h, int children, int classes);
+// 1 when replicas with 64 < N <= 128 should run on two wavefronts each.
 int split_wide(const labs_handle *h, int waves_per_replica, int64_t n_wide);
 
 // Bytes of device state per memetic replica with population size K.
 inline size_t memetic_state_bytes(int K) {
-    return (size_t)K * (2 * sizeof(uint64_t) + sizeof(int32_t)) + 2 * sizeof(uint64_t) +
-           sizeof(int32_t) + 2 * sizeof(int64_t);
+    return (size_t)K * (kStateWords * sizeof(uint64_t) + sizeof(int32_t)) +
+           kStateWords * sizeof(uint64_t) + sizeof(int32_t) + 2 * sizeof(int64_t);
 }
 
 // Carve a MemeticStateDev for S replicas out of `base` (256-byte aligned parts).

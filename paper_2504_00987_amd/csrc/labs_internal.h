@@ -22,7 +22,7 @@ struct TabuLaunchArgs {
     int32_t n_max;            // longest walk in the batch
     const int32_t *order;     // device [W] walk ids in processing order, or null
     int64_t W;
-    int64_t class_end[4];     // processing-order positions [class_end[c-1], class_end[c])
+    int64_t class_end[6];     // processing-order positions [class_end[c-1], class_end[c])
                               // hold the walks of length class c (kWalkClasses)
     uint32_t k0, k1;
     RuleParams rule;
@@ -37,15 +37,24 @@ struct TabuLaunchArgs {
 
 // Length classes of stand-alone walks, longest first: a class fixes the
 // neighbours per lane (NW) and how many 16-lag chunks a window spans (NB).
-constexpr int kWalkClasses = 4;
-constexpr int kClassMaxN[kWalkClasses] = {128, 97, 64, 49};
-inline int walk_class(int n) { return n > 97 ? 0 : n > 64 ? 1 : n > 49 ? 2 : 3; }
+constexpr int kWalkClasses = 6;
+constexpr int kClassMaxN[kWalkClasses] = {256, 193, 128, 97, 64, 49};
+inline int walk_class(int n) {
+    int c = 0;
+    while (c + 1 < kWalkClasses && n <= kClassMaxN[c + 1]) ++c;
+    return c;
+}
+// Streams besides the caller's one that a batch may fork onto.
+constexpr int kSideStreams = kWalkClasses - 1;
+
+// Words of a sequence mask in the memetic state (N <= 256).
+constexpr int kStateWords = 4;
 
 // Device layout of a memetic replica's state (structure of arrays).
 struct MemeticStateDev {
-    uint64_t *pop;    // [S][K][2] member masks (bit i: s_i = -1)
+    uint64_t *pop;    // [S][K][kStateWords] member masks (bit i: s_i = -1)
     int32_t *popE;    // [S][K]
-    uint64_t *best;   // [S][2]
+    uint64_t *best;   // [S][kStateWords]
     int32_t *bestE;   // [S]
     int64_t *gen;     // [S] generations done
     int64_t *hit;     // [S] hit generation or -1
@@ -62,6 +71,17 @@ struct MemeticSlot {
 
 constexpr int kMaxChildren = 8;  // children per generation (batched variant)
 
+// Length classes of memetic replicas: mask words 1, 2 or 4.
+__host__ __device__ inline int memetic_class(int n) { return n <= 64 ? 0 : n <= 128 ? 1 : 2; }
+
+// Side streams a launch may fork onto (fork recorded on the caller's stream,
+// side i joined back through join[i]).
+struct SideStreams {
+    hipStream_t s[kSideStreams];
+    hipEvent_t join[kSideStreams];
+    hipEvent_t fork;
+};
+
 struct MemeticLaunchArgs {
     const MemeticSlot *slots;
     int32_t n_slots;
@@ -71,7 +91,7 @@ struct MemeticLaunchArgs {
     uint32_t p_mut;
     RuleParams rule;
     int32_t gens;            // generations per launch
-    int32_t classes;         // bit 0: some slot has N <= 64; bit 1: some N > 64
+    int32_t classes;         // bit c set: some slot is of memetic_class c
     int32_t split_wide;      // 1: a replica with N > 64 runs on two wavefronts
     int32_t children;        // children per generation (1: Alg. 1)
     MemeticStateDev st;
@@ -104,15 +124,16 @@ hipError_t launch_tabu(const TabuLaunchArgs &a, int waves_per_group, int groups,
 
 hipError_t launch_memetic_init(const MemeticLaunchArgs &a, hipStream_t s);
 // Once per device before the first launch: raises the dynamic LDS limit of
-// the batched-generation kernels to what kMaxChildren children need.
-hipError_t prepare_memetic_kernels();
-// Advances every slot by a.gens generations.  When both length classes are
-// present and `side` is given, the N <= 64 slots run on `side` (forked from
-// and joined back into s with the two events), concurrently with the N > 64
-// slots on s; the sequence of calls is capturable into a graph.
+// the batched-generation kernels to what kMaxChildren children need (N > 128:
+// as far as the device allows).  Returns the most children per generation
+// the N > 128 kernel can take, or -1 on failure.
+int prepare_memetic_kernels();
+// Advances every slot by a.gens generations.  With several length classes
+// present and `sides` given, the widest class runs on s and the others on
+// side streams forked from and joined back into s, concurrently; the
+// sequence of calls is capturable into a graph.
 hipError_t launch_memetic_advance(const MemeticLaunchArgs &a, hipStream_t s,
-                                  hipStream_t side = nullptr, hipEvent_t fork = nullptr,
-                                  hipEvent_t join = nullptr);
+                                  const SideStreams *sides = nullptr);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
 hipError_t launch_gather_best(const MemeticStateDev &st, const int32_t *state_idx,
                               const int32_t *ns, int32_t n_uniform, int32_t count,

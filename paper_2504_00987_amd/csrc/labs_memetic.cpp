@@ -23,9 +23,9 @@ MemeticStateDev carve_state(void *base, int S, int K, size_t *bytes_out) {
         off += align256(bytes);
         return q;
     };
-    st.pop = (uint64_t *)take((size_t)S * K * 2 * sizeof(uint64_t));
+    st.pop = (uint64_t *)take((size_t)S * K * kStateWords * sizeof(uint64_t));
     st.popE = (int32_t *)take((size_t)S * K * sizeof(int32_t));
-    st.best = (uint64_t *)take((size_t)S * 2 * sizeof(uint64_t));
+    st.best = (uint64_t *)take((size_t)S * kStateWords * sizeof(uint64_t));
     st.bestE = (int32_t *)take((size_t)S * sizeof(int32_t));
     st.gen = (int64_t *)take((size_t)S * sizeof(int64_t));
     st.hit = (int64_t *)take((size_t)S * sizeof(int64_t));
@@ -38,6 +38,13 @@ static_assert(kMaxChildren == LABS_MAX_CHILDREN, "kernel and ABI limits agree");
 int split_wide(const labs_handle *h, int waves_per_replica, int64_t n_wide) {
     if (waves_per_replica != 0) return waves_per_replica == 2;
     return n_wide <= 2 * (int64_t)std::max(h->num_cus, 1);
+}
+
+int check_children(labs_handle *h, int children, int classes) {
+    if (children > 1 && (classes & 4) && children > h->max_children_wide)
+        return fail(h, LABS_E_INVAL, "children=%d: this device fits at most %d per generation "
+                    "for N > 128", children, h->max_children_wide);
+    return LABS_OK;
 }
 
 int check_memetic(labs_handle *h, const labs_memetic_params *p) {
@@ -143,12 +150,13 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
     a.classes = 0;
     int64_t n_wide = 0;
     for (int i = 0; i < pops; ++i) {
-        const bool wide = (ns_host ? ns_host[i] : n_uniform) > 64;
-        a.classes |= wide ? 2 : 1;
-        n_wide += wide;
+        const int c = memetic_class(ns_host ? ns_host[i] : n_uniform);
+        a.classes |= 1 << c;
+        n_wide += c == 1;
     }
     a.split_wide = split_wide(h, p->waves_per_replica, n_wide);
     a.children = std::max(1, (int)p->children);
+    if ((rc = check_children(h, a.children, a.classes))) return rc;
     if ((e = launch_fill_u32(d_flag, 0u, 1, s)) != hipSuccess) return hip_fail(h, e, "fill");
     if ((e = launch_memetic_init(a, s)) != hipSuccess) return hip_fail(h, e, "memetic init");
 
@@ -165,7 +173,7 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
         e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(h, e, "hipStreamBeginCapture");
         for (int64_t i = 0; i < n_launch && e == hipSuccess; ++i)
-            e = launch_memetic_advance(one, s, h->side, h->fork_event, h->join_event);
+            e = launch_memetic_advance(one, s, &h->sides);
         hipError_t e2 = hipStreamEndCapture(s, &graph);
         if (e != hipSuccess || e2 != hipSuccess) {
             if (graph) hipGraphDestroy(graph);
@@ -185,7 +193,7 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
             MemeticLaunchArgs one = a;
             one.gens = 1;
             for (int64_t i = 0; i < step && e == hipSuccess; ++i)
-                e = launch_memetic_advance(one, s, h->side, h->fork_event, h->join_event);
+                e = launch_memetic_advance(one, s, &h->sides);
         } else if (p->mode == LABS_MODE_GRAPH) {
             // Launches beyond a replica's generation limit return at once, so
             // the final replay may safely run past G.
@@ -193,7 +201,7 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
         } else {
             MemeticLaunchArgs many = a;
             many.gens = (int32_t)step;
-            e = launch_memetic_advance(many, s, h->side, h->fork_event, h->join_event);
+            e = launch_memetic_advance(many, s, &h->sides);
         }
         if (e != hipSuccess) {
             rc = hip_fail(h, e, "memetic advance");

@@ -26,6 +26,26 @@ __device__ __forceinline__ uint32_t word_of(const Draw4 &d, int i) {
     return i == 0 ? d.w0 : (i == 1 ? d.w1 : (i == 2 ? d.w2 : d.w3));
 }
 
+// Member m = lane + 64 h of the replica (K <= 128): bits 128 q .. 128 q + 127
+// are the draw (pop, m, q, INIT); its energy is computed lane-serially.
+template <typename Mask>
+__device__ __forceinline__ int init_member(const MemeticLaunchArgs &a, const MemeticSlot &sl,
+                                           int m, uint64_t wd[kStateWords]) {
+    const int N = sl.n;
+#pragma unroll
+    for (int q = 0; q < kStateWords / 2; ++q) {
+        const Draw4 d = philox10(sl.pop_id, (uint32_t)m, (uint32_t)q, kTagInit, sl.k0, sl.k1);
+        wd[2 * q] = (uint64_t)d.w0 | ((uint64_t)d.w1 << 32);
+        wd[2 * q + 1] = (uint64_t)d.w2 | ((uint64_t)d.w3 << 32);
+    }
+#pragma unroll
+    for (int h = 0; h < kStateWords; ++h) {
+        const int b = N - 64 * h;  // bits of word h inside the sequence
+        wd[h] &= b >= 64 ? ~0ull : b <= 0 ? 0ull : ((1ull << b) - 1ull);
+    }
+    return lane_energy<Mask>(make_mask<sizeof(Mask) / 8>(wd[0], wd[1], wd[2], wd[3]), N);
+}
+
 __global__ __launch_bounds__(64) void memetic_init_kernel(MemeticLaunchArgs a) {
     const int s = blockIdx.x;
     if (s >= a.n_slots) return;
@@ -34,26 +54,19 @@ __global__ __launch_bounds__(64) void memetic_init_kernel(MemeticLaunchArgs a) {
     const int lane = lane_id();
     const int N = sl.n, K = a.K;
     const int64_t base = (int64_t)sl.state * K;
-    uint64_t lo[2] = {0ull, 0ull}, hi[2] = {0ull, 0ull};
+    uint64_t wd[2][kStateWords] = {};
     int e[2] = {INT_MAX, INT_MAX};
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int m = lane + 64 * h;
         if (m < K) {
-            const Draw4 d = philox10(sl.pop_id, (uint32_t)m, 0u, kTagInit, sl.k0, sl.k1);
-            uint64_t l = (uint64_t)d.w0 | ((uint64_t)d.w1 << 32);
-            uint64_t u = (uint64_t)d.w2 | ((uint64_t)d.w3 << 32);
-            if (N < 64) {
-                l &= (1ull << N) - 1ull;
-                u = 0ull;
-            } else {
-                u &= (N >= 128) ? ~0ull : ((1ull << (N - 64)) - 1ull);
-            }
-            lo[h] = l;
-            hi[h] = u;
-            e[h] = N <= 64 ? lane_energy<uint64_t>(l, N) : lane_energy<M128>(M128{l, u}, N);
-            a.st.pop[(base + m) * 2 + 0] = l;
-            a.st.pop[(base + m) * 2 + 1] = u;
+            const int c = memetic_class(N);
+            e[h] = c == 0 ? init_member<uint64_t>(a, sl, m, wd[h])
+                 : c == 1 ? init_member<M128>(a, sl, m, wd[h])
+                          : init_member<M256>(a, sl, m, wd[h]);
+#pragma unroll
+            for (int w = 0; w < kStateWords; ++w)
+                a.st.pop[(base + m) * kStateWords + w] = wd[h][w];
             a.st.popE[base + m] = e[h];
         }
     }
@@ -62,17 +75,33 @@ __global__ __launch_bounds__(64) void memetic_init_kernel(MemeticLaunchArgs a) {
     const uint64_t t0 = ballot(e[0] == mn), t1 = ballot(e[1] == mn);
     const int h = t0 ? 0 : 1;
     const int src = t0 ? __builtin_ctzll(t0) : __builtin_ctzll(t1);
-    const uint64_t sel_lo = h == 0 ? lo[0] : lo[1];
-    const uint64_t sel_hi = h == 0 ? hi[0] : hi[1];
-    const uint64_t blo = ((uint64_t)readlane_u((uint32_t)(sel_lo >> 32), src) << 32) |
-                         readlane_u((uint32_t)sel_lo, src);
-    const uint64_t bhi = ((uint64_t)readlane_u((uint32_t)(sel_hi >> 32), src) << 32) |
-                         readlane_u((uint32_t)sel_hi, src);
-    a.st.best[(int64_t)sl.state * 2 + 0] = blo;  // uniform values, every lane
-    a.st.best[(int64_t)sl.state * 2 + 1] = bhi;
+#pragma unroll
+    for (int w = 0; w < kStateWords; ++w) {
+        const uint64_t sel = h == 0 ? wd[0][w] : wd[1][w];
+        const uint64_t v = ((uint64_t)readlane_u((uint32_t)(sel >> 32), src) << 32) |
+                           readlane_u((uint32_t)sel, src);
+        a.st.best[(int64_t)sl.state * kStateWords + w] = v;  // uniform values, every lane
+    }
     a.st.bestE[sl.state] = mn;
     a.st.gen[sl.state] = 0;
     a.st.hit[sl.state] = -1;
+}
+
+// Mutation mask of a child: bit i flips when word i%4 of draw
+// (pop, g, base + i/4, MUT) is below thr.
+template <int NW>
+__device__ __forceinline__ typename MaskOf<NW>::type mutation_mask(const MemeticSlot &sl,
+                                                                   uint32_t gg, uint32_t base,
+                                                                   uint32_t thr) {
+    const int lane = lane_id();
+    uint64_t f[4] = {0ull, 0ull, 0ull, 0ull};
+#pragma unroll
+    for (int h = 0; h < NW; ++h) {
+        const int i = lane + 64 * h;
+        const Draw4 d = philox10(sl.pop_id, gg, base + (uint32_t)(i >> 2), kTagMut, sl.k0, sl.k1);
+        f[h] = ballot(i < sl.n && word_of(d, i & 3) < thr);
+    }
+    return make_mask<NW>(f[0], f[1], f[2], f[3]);
 }
 
 // One replica on SPLIT wavefronts (wavefront `part` of them); every
@@ -80,18 +109,18 @@ __global__ __launch_bounds__(64) void memetic_init_kernel(MemeticLaunchArgs a) {
 // the walk is split between them.
 template <int NW, int SPLIT>
 __device__ void memetic_replica(const MemeticLaunchArgs &a, const MemeticSlot &sl,
-                                uint64_t (*pop)[2], int *popE, uint8_t *lds, int part) {
+                                uint64_t (*pop)[NW], int *popE, uint8_t *lds, int part) {
     using Mask = typename MaskOf<NW>::type;
     const int lane = lane_id();
     const int N = sl.n, K = a.K, st = sl.state;
     const int64_t base = (int64_t)st * K;
     for (int i = lane + 64 * part; i < K; i += 64 * SPLIT) {
-        pop[i][0] = a.st.pop[(base + i) * 2 + 0];
-        pop[i][1] = a.st.pop[(base + i) * 2 + 1];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) pop[i][w] = a.st.pop[(base + i) * kStateWords + w];
         popE[i] = a.st.popE[base + i];
     }
     walk_sync<SPLIT>();
-    Mask best = make_mask<NW>(a.st.best[(int64_t)st * 2 + 0], a.st.best[(int64_t)st * 2 + 1]);
+    Mask best = load_mask<NW>(a.st.best + (int64_t)st * kStateWords);
     int bestE = a.st.bestE[st];
     int64_t g = a.st.gen[st];
     int64_t hit = a.st.hit[st];
@@ -116,27 +145,16 @@ __device__ void memetic_replica(const MemeticLaunchArgs &a, const MemeticSlot &s
             j = (int)below(db.w0, (uint32_t)K);
             const int pb = popE[i] <= popE[j] ? i : j;
             const int cut = 1 + (int)below(db.w1, (uint32_t)(N - 1));
-            const Mask A = make_mask<NW>(pop[pa][0], pop[pa][1]);
-            const Mask B = make_mask<NW>(pop[pb][0], pop[pb][1]);
+            const Mask A = load_mask<NW>(pop[pa]);
+            const Mask B = load_mask<NW>(pop[pb]);
             const Mask lowm = m_low(A, cut);
             child = m_or(m_and(A, lowm), m_and(B, m_not(lowm)));
         } else {
             const int c = (int)below(da.w1, (uint32_t)K);
-            child = make_mask<NW>(pop[c][0], pop[c][1]);
+            child = load_mask<NW>(pop[c]);
         }
         // Mutate: bit i flips when word i%4 of draw (pop, g, i/4, MUT) < thr.
-        uint64_t flo, fhi = 0ull;
-        {
-            const int i0 = lane;
-            const Draw4 d = philox10(sl.pop_id, gg, (uint32_t)(i0 >> 2), kTagMut, sl.k0, sl.k1);
-            flo = ballot(i0 < N && word_of(d, i0 & 3) < thr);
-            if constexpr (NW == 2) {
-                const int i1 = lane + 64;
-                const Draw4 d1 = philox10(sl.pop_id, gg, (uint32_t)(i1 >> 2), kTagMut, sl.k0, sl.k1);
-                fhi = ballot(i1 < N && word_of(d1, i1 & 3) < thr);
-            }
-        }
-        child = m_xor(child, make_mask<NW>(flo, fhi));
+        child = m_xor(child, mutation_mask<NW>(sl, gg, 0u, thr));
         const Schedule sch = make_schedule(a.rule, N, sl.k0, sl.k1, sl.pop_id, gg);
         const WalkResult<NW> r = tabu_walk<NW, false, SPLIT>(N, child, sch, a.rule.aspiration,
                                                              sl.k0, sl.k1, sl.pop_id, gg, lds,
@@ -147,8 +165,7 @@ __device__ void memetic_replica(const MemeticLaunchArgs &a, const MemeticSlot &s
         }
         const int rep = (int)below(db.w2, (uint32_t)K);
         walk_sync<SPLIT>();
-        pop[rep][0] = mask_lo(r.best);  // uniform values, every lane
-        pop[rep][1] = mask_hi(r.best);
+        store_mask<NW>(pop[rep], r.best);  // uniform values, every lane
         popE[rep] = r.best_e;
         walk_sync<SPLIT>();
         ++g;
@@ -159,22 +176,21 @@ __device__ void memetic_replica(const MemeticLaunchArgs &a, const MemeticSlot &s
     }
 
     for (int i = lane + 64 * part; i < K; i += 64 * SPLIT) {
-        a.st.pop[(base + i) * 2 + 0] = pop[i][0];
-        a.st.pop[(base + i) * 2 + 1] = pop[i][1];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) a.st.pop[(base + i) * kStateWords + w] = pop[i][w];
         a.st.popE[base + i] = popE[i];
     }
     if (part != 0) return;
-    a.st.best[(int64_t)st * 2 + 0] = mask_lo(best);  // uniform values, every lane
-    a.st.best[(int64_t)st * 2 + 1] = mask_hi(best);
+    store_mask<NW>(a.st.best + (int64_t)st * kStateWords, best);  // uniform values, every lane
     a.st.bestE[st] = bestE;
     a.st.gen[st] = g;
     a.st.hit[st] = hit;
     if (hit >= 0 && a.any_hit != nullptr) atomicOr(a.any_hit, 1u);
 }
 
-// Replicas of one length class: N <= 64 (NW = 1) or 64 < N <= 128 (NW = 2),
-// one workgroup of SPLIT wavefronts per replica; slots of the other class
-// and idle slots return at once.  The two-wavefront form only runs when
+// Replicas of one length class: N <= 64 (NW = 1), 64 < N <= 128 (NW = 2) or
+// 128 < N <= 256 (NW = 4), one workgroup of SPLIT wavefronts per replica;
+// slots of the other classes and idle slots return at once.  The two-wavefront form only runs when
 // there are at most two replicas per compute unit, so it is compiled for
 // latency (all of a step's LDS reads in flight at once) rather than for
 // occupancy.
@@ -182,13 +198,13 @@ template <int NW, int SPLIT>
 __global__ __launch_bounds__(64 * SPLIT)
 __attribute__((amdgpu_waves_per_eu(1, SPLIT == 2 ? 2 : 8))) void memetic_advance_kernel(
     MemeticLaunchArgs a) {
-    __shared__ uint64_t pop[kMaxK][2];
+    __shared__ uint64_t pop[kMaxK][NW];
     __shared__ int popE[kMaxK];
     __shared__ __attribute__((aligned(16))) uint8_t lds[walk_lds_bytes<NW>()];
     const int s = blockIdx.x;
     if (s >= a.n_slots) return;
     const MemeticSlot sl = a.slots[s];
-    if (sl.state < 0 || (sl.n > 64) != (NW == 2)) return;
+    if (sl.state < 0 || (1 << memetic_class(sl.n)) != NW) return;
     memetic_replica<NW, SPLIT>(a, sl, pop, popE, lds, SPLIT == 1 ? 0 : (int)(threadIdx.x >> 6));
 }
 
@@ -200,33 +216,38 @@ __attribute__((amdgpu_waves_per_eu(1, SPLIT == 2 ? 2 : 8))) void memetic_advance
 // alone writes the replacements (so they land in order); a second barrier
 // publishes them.  All control flow depends only on values every wavefront
 // holds identically, so every wavefront reaches every barrier.
-constexpr int kBatchedHeader = kMaxK * 16 + kMaxK * 4 + kMaxChildren * 32;
+// Dynamic LDS: population [kMaxK][NW] words, energies [kMaxK], per child
+// kResWords words (mask, energy, replaced slot), then the B walk scratches.
+constexpr int kResWords = 8;
+template <int NW>
+constexpr int batched_header() {
+    return kMaxK * 8 * NW + kMaxK * 4 + kMaxChildren * kResWords * 8;
+}
 
 template <int NW>
 __global__ __launch_bounds__(64 * kMaxChildren) void memetic_batched_kernel(
     MemeticLaunchArgs a) {
     using Mask = typename MaskOf<NW>::type;
     extern __shared__ __attribute__((aligned(16))) uint8_t dyn_lds[];
-    uint64_t(*pop)[2] = (uint64_t(*)[2])dyn_lds;
-    int *popE = (int *)(dyn_lds + kMaxK * 16);
-    uint64_t *res = (uint64_t *)(dyn_lds + kMaxK * 20);  // [B][lo, hi, e, slot]
+    uint64_t(*pop)[NW] = (uint64_t(*)[NW])dyn_lds;
+    int *popE = (int *)(dyn_lds + kMaxK * 8 * NW);
+    uint64_t *res = (uint64_t *)(dyn_lds + kMaxK * (8 * NW + 4));  // [B][kResWords]
     const int s = blockIdx.x;
     if (s >= a.n_slots) return;
     const MemeticSlot sl = a.slots[s];
-    if (sl.state < 0 || (sl.n > 64) != (NW == 2)) return;
+    if (sl.state < 0 || (1 << memetic_class(sl.n)) != NW) return;
     const int B = a.children;
     const int b = (int)(threadIdx.x >> 6);
-    uint8_t *lds = dyn_lds + kBatchedHeader + b * walk_lds_bytes<NW>();
-    const int lane = lane_id();
+    uint8_t *lds = dyn_lds + batched_header<NW>() + b * walk_lds_bytes<NW>();
     const int N = sl.n, K = a.K, st = sl.state;
     const int64_t base = (int64_t)st * K;
     for (int i = (int)threadIdx.x; i < K; i += 64 * B) {
-        pop[i][0] = a.st.pop[(base + i) * 2 + 0];
-        pop[i][1] = a.st.pop[(base + i) * 2 + 1];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) pop[i][w] = a.st.pop[(base + i) * kStateWords + w];
         popE[i] = a.st.popE[base + i];
     }
     __syncthreads();
-    Mask best = make_mask<NW>(a.st.best[(int64_t)st * 2 + 0], a.st.best[(int64_t)st * 2 + 1]);
+    Mask best = load_mask<NW>(a.st.best + (int64_t)st * kStateWords);
     int bestE = a.st.bestE[st];
     int64_t g = a.st.gen[st];
     int64_t hit = a.st.hit[st];
@@ -250,49 +271,39 @@ __global__ __launch_bounds__(64 * kMaxChildren) void memetic_batched_kernel(
             j = (int)below(db.w0, (uint32_t)K);
             const int pb = popE[i] <= popE[j] ? i : j;
             const int cut = 1 + (int)below(db.w1, (uint32_t)(N - 1));
-            const Mask A = make_mask<NW>(pop[pa][0], pop[pa][1]);
-            const Mask Bm = make_mask<NW>(pop[pb][0], pop[pb][1]);
+            const Mask A = load_mask<NW>(pop[pa]);
+            const Mask Bm = load_mask<NW>(pop[pb]);
             const Mask lowm = m_low(A, cut);
             child = m_or(m_and(A, lowm), m_and(Bm, m_not(lowm)));
         } else {
             const int c = (int)below(da.w1, (uint32_t)K);
-            child = make_mask<NW>(pop[c][0], pop[c][1]);
+            child = load_mask<NW>(pop[c]);
         }
-        uint64_t flo, fhi = 0ull;
-        {
-            const int i0 = lane;
-            const Draw4 d = philox10(sl.pop_id, gg, (uint32_t)(32 * b + (i0 >> 2)), kTagMut,
-                                     sl.k0, sl.k1);
-            flo = ballot(i0 < N && word_of(d, i0 & 3) < thr);
-            if constexpr (NW == 2) {
-                const int i1 = lane + 64;
-                const Draw4 d1 = philox10(sl.pop_id, gg, (uint32_t)(32 * b + (i1 >> 2)), kTagMut,
-                                          sl.k0, sl.k1);
-                fhi = ballot(i1 < N && word_of(d1, i1 & 3) < thr);
-            }
-        }
-        child = m_xor(child, make_mask<NW>(flo, fhi));
+        // child b's mutation words: (pop, g, 64 b + i/4, MUT)
+        child = m_xor(child, mutation_mask<NW>(sl, gg, (uint32_t)(64 * b), thr));
         const uint32_t wgen = (uint32_t)(g * B + b);
         const Schedule sch = make_schedule(a.rule, N, sl.k0, sl.k1, sl.pop_id, wgen);
         const WalkResult<NW> r = tabu_walk<NW>(N, child, sch, a.rule.aspiration, sl.k0, sl.k1,
                                                sl.pop_id, wgen, lds, nullptr);
-        res[4 * b + 0] = mask_lo(r.best);  // uniform values, every lane of wavefront b
-        res[4 * b + 1] = mask_hi(r.best);
-        res[4 * b + 2] = (uint64_t)(uint32_t)r.best_e;
-        res[4 * b + 3] = (uint64_t)below(db.w2, (uint32_t)K);
+        uint64_t *mine = res + kResWords * b;
+        store_mask<NW>(mine, r.best);  // uniform values, every lane of wavefront b
+        mine[4] = (uint64_t)(uint32_t)r.best_e;
+        mine[5] = (uint64_t)below(db.w2, (uint32_t)K);
         __syncthreads();
         for (int c = 0; c < B; ++c) {
-            const uint64_t lo = uniform64(res[4 * c + 0]);
-            const uint64_t hi = uniform64(res[4 * c + 1]);
-            const int e = __builtin_amdgcn_readfirstlane((int)(uint32_t)res[4 * c + 2]);
-            const int slot = __builtin_amdgcn_readfirstlane((int)(uint32_t)res[4 * c + 3]);
+            const uint64_t *rc = res + kResWords * c;
+            uint64_t wd[4] = {0ull, 0ull, 0ull, 0ull};
+#pragma unroll
+            for (int w = 0; w < NW; ++w) wd[w] = uniform64(rc[w]);
+            const int e = __builtin_amdgcn_readfirstlane((int)(uint32_t)rc[4]);
+            const int slot = __builtin_amdgcn_readfirstlane((int)(uint32_t)rc[5]);
+            const Mask m = make_mask<NW>(wd[0], wd[1], wd[2], wd[3]);
             if (e < bestE) {
                 bestE = e;
-                best = make_mask<NW>(lo, hi);
+                best = m;
             }
             if (b == 0) {
-                pop[slot][0] = lo;  // uniform values, every lane of wavefront 0
-                pop[slot][1] = hi;
+                store_mask<NW>(pop[slot], m);  // uniform values, every lane of wavefront 0
                 popE[slot] = e;
             }
         }
@@ -305,13 +316,12 @@ __global__ __launch_bounds__(64 * kMaxChildren) void memetic_batched_kernel(
     }
 
     for (int i = (int)threadIdx.x; i < K; i += 64 * B) {
-        a.st.pop[(base + i) * 2 + 0] = pop[i][0];
-        a.st.pop[(base + i) * 2 + 1] = pop[i][1];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) a.st.pop[(base + i) * kStateWords + w] = pop[i][w];
         a.st.popE[base + i] = popE[i];
     }
     if (b != 0) return;
-    a.st.best[(int64_t)st * 2 + 0] = mask_lo(best);  // uniform values, every lane
-    a.st.best[(int64_t)st * 2 + 1] = mask_hi(best);
+    store_mask<NW>(a.st.best + (int64_t)st * kStateWords, best);  // uniform values, every lane
     a.st.bestE[st] = bestE;
     a.st.gen[st] = g;
     a.st.hit[st] = hit;
@@ -329,7 +339,7 @@ __global__ void gather_best_kernel(MemeticStateDev st, const int32_t *__restrict
     const int lane = lane_id();
     const int s = state_idx ? state_idx[i] : i;
     const int N = ns ? ns[i] : n_uniform;
-    const M128 b{st.best[(int64_t)s * 2 + 0], st.best[(int64_t)s * 2 + 1]};
+    const M256 b = load_mask<4>(st.best + (int64_t)s * kStateWords);
     int8_t *out = best_seq + (int64_t)i * out_stride;
     for (int k = lane; k < out_stride; k += 64)
         out[k] = k < N ? (m_bit(b, k) ? (int8_t)-1 : (int8_t)1) : (int8_t)0;
@@ -352,7 +362,7 @@ namespace {
 // population plus B walk scratches.
 template <int NW>
 constexpr size_t batched_lds_bytes(int children) {
-    return kBatchedHeader + (size_t)children * walk_lds_bytes<NW>();
+    return batched_header<NW>() + (size_t)children * walk_lds_bytes<NW>();
 }
 
 template <int NW>
@@ -364,9 +374,10 @@ hipError_t launch_batched(const MemeticLaunchArgs &a, hipStream_t s) {
 
 }  // namespace
 
-hipError_t prepare_memetic_kernels() {
-    // eight children of N > 64 take more than the 64 KB of dynamic LDS a
-    // launch gets without the attribute (the CU has 160 KB)
+int prepare_memetic_kernels() {
+    // more than 64 KB of dynamic LDS (eight children of N > 64) needs the
+    // attribute; the CU has 160 KB.  N > 128 takes 17.7 KB per child: the
+    // largest child count the device accepts is returned.
     hipError_t e = hipFuncSetAttribute((const void *)memetic_batched_kernel<1>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)batched_lds_bytes<1>(kMaxChildren));
@@ -374,39 +385,60 @@ hipError_t prepare_memetic_kernels() {
         e = hipFuncSetAttribute((const void *)memetic_batched_kernel<2>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)batched_lds_bytes<2>(kMaxChildren));
-    return e;
+    if (e != hipSuccess) return -1;
+    for (int b = kMaxChildren; b >= 1; --b) {
+        if (hipFuncSetAttribute((const void *)memetic_batched_kernel<4>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)batched_lds_bytes<4>(b)) == hipSuccess)
+            return b;
+        (void)hipGetLastError();  // clear the refusal
+    }
+    return 0;
 }
 
-hipError_t launch_memetic_advance(const MemeticLaunchArgs &a, hipStream_t s, hipStream_t side,
-                                  hipEvent_t fork, hipEvent_t join) {
-    if (a.n_slots <= 0) return hipSuccess;
-    const bool split = a.classes == 3 && side != nullptr && fork != nullptr && join != nullptr;
-    hipStream_t s1 = s;
-    if (split) {
-        hipError_t e = hipEventRecord(fork, s);
-        if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
-        if (e != hipSuccess) return e;
-        s1 = side;
-    }
-    hipError_t e = hipSuccess;
+namespace {
+
+// Kernels of one memetic length class c (mask words 1 << c) on stream s.
+hipError_t launch_memetic_class(const MemeticLaunchArgs &a, int c, hipStream_t s) {
+    const dim3 grid((unsigned)a.n_slots);
     if (a.children > 1) {
-        if (a.classes & 1) e = launch_batched<1>(a, s1);
-        if (e == hipSuccess && (a.classes & 2)) e = launch_batched<2>(a, s);
-    } else {
-        if (a.classes & 1)
-            hipLaunchKernelGGL((memetic_advance_kernel<1, 1>), dim3((unsigned)a.n_slots), dim3(64),
-                               0, s1, a);
-        if ((a.classes & 2) && a.split_wide)
-            hipLaunchKernelGGL((memetic_advance_kernel<2, 2>), dim3((unsigned)a.n_slots),
-                               dim3(128), 0, s, a);
-        else if (a.classes & 2)
-            hipLaunchKernelGGL((memetic_advance_kernel<2, 1>), dim3((unsigned)a.n_slots), dim3(64),
-                               0, s, a);
-        e = hipGetLastError();
+        if (c == 0) return launch_batched<1>(a, s);
+        if (c == 1) return launch_batched<2>(a, s);
+        return launch_batched<4>(a, s);
     }
-    if (split && e == hipSuccess) {
-        e = hipEventRecord(join, side);
-        if (e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
+    if (c == 0)
+        hipLaunchKernelGGL((memetic_advance_kernel<1, 1>), grid, dim3(64), 0, s, a);
+    else if (c == 1 && a.split_wide)
+        hipLaunchKernelGGL((memetic_advance_kernel<2, 2>), grid, dim3(128), 0, s, a);
+    else if (c == 1)
+        hipLaunchKernelGGL((memetic_advance_kernel<2, 1>), grid, dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL((memetic_advance_kernel<4, 1>), grid, dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_memetic_advance(const MemeticLaunchArgs &a, hipStream_t s,
+                                  const SideStreams *sides) {
+    if (a.n_slots <= 0) return hipSuccess;
+    // the widest class present runs on s, each further one on a side stream
+    int present[3], n = 0;
+    for (int c = 2; c >= 0; --c)
+        if (a.classes & (1 << c)) present[n++] = c;
+    const int n_sides = sides != nullptr ? std::min(n - 1, kSideStreams) : 0;
+    hipError_t e = hipSuccess;
+    if (n_sides > 0) {
+        e = hipEventRecord(sides->fork, s);
+        for (int i = 0; i < n_sides && e == hipSuccess; ++i)
+            e = hipStreamWaitEvent(sides->s[i], sides->fork, 0);
+        if (e != hipSuccess) return e;
+    }
+    for (int i = 0; i < n && e == hipSuccess; ++i)
+        e = launch_memetic_class(a, present[i], i > 0 && i <= n_sides ? sides->s[i - 1] : s);
+    for (int i = 0; i < n_sides && e == hipSuccess; ++i) {
+        e = hipEventRecord(sides->join[i], sides->s[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, sides->join[i], 0);
     }
     return e;
 }

@@ -51,8 +51,7 @@ struct labs_server {
     labs_memetic_params params{};
     int max_slots = 0;
     hipStream_t stream = nullptr;
-    hipStream_t side = nullptr;  // N <= 64 replicas, concurrent with the rest
-    hipEvent_t fork = nullptr, join = nullptr;
+    SideStreams sides{};  // further length classes, concurrent with the widest
     // device: [slots table][init table][state]
     void *dmem = nullptr;
     MemeticSlot *d_slots = nullptr;
@@ -127,8 +126,9 @@ int labs_server::iterate(std::unique_lock<std::mutex> &lk) {
     int64_t n_wide = 0;
     for (int s = 0; s < max_slots; ++s)
         if (owner[s] >= 0) {
-            classes |= h_slots[s].n > 64 ? 2 : 1;
-            n_wide += h_slots[s].n > 64;
+            const int c = memetic_class(h_slots[s].n);
+            classes |= 1 << c;
+            n_wide += c == 1;
         }
     const int n_init = (int)fresh.size();
     for (int i = 0; i < n_init; ++i) h_init[i] = h_slots[fresh[i]];
@@ -160,11 +160,11 @@ int labs_server::iterate(std::unique_lock<std::mutex> &lk) {
     a.classes = classes;
     a.split_wide = split_wide(h, params.waves_per_replica, n_wide);
     a.children = std::max(1, (int)params.children);
-    if (e == hipSuccess) e = launch_memetic_advance(a, stream, side, fork, join);
+    if (e == hipSuccess) e = launch_memetic_advance(a, stream, &sides);
     if (e == hipSuccess) e = hipMemcpyAsync(h_bestE, st.bestE, max_slots * 4, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(h_gen, st.gen, max_slots * 8, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(h_hit, st.hit, max_slots * 8, hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(h_best, st.best, max_slots * 16, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_best, st.best, max_slots * kStateWords * 8, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     lk.lock();
     if (e != hipSuccess) {
@@ -190,7 +190,7 @@ int labs_server::iterate(std::unique_lock<std::mutex> &lk) {
         r.best_e = h_bestE[bs];
         r.best.assign(r.n, 0);
         for (int i = 0; i < r.n; ++i) {
-            const uint64_t w = h_best[bs * 2 + (i >> 6)];
+            const uint64_t w = h_best[bs * kStateWords + (i >> 6)];
             r.best[i] = ((w >> (i & 63)) & 1ull) ? -1 : 1;
         }
         for (int s : r.slots) {
@@ -238,16 +238,19 @@ extern "C" int labs_server_create(labs_handle *h, const labs_memetic_params *par
     carve_state(nullptr, max_slots, params->K, &state_bytes);
     const size_t tbl = ((size_t)max_slots * sizeof(MemeticSlot) + 255) & ~(size_t)255;
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->sides.fork, hipEventDisableTiming);
+    for (int i = 0; i < kSideStreams && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&s->sides.s[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->sides.join[i], hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = hipMalloc(&s->dmem, 2 * tbl + state_bytes);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_slots, tbl, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_init, tbl, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_bestE, (size_t)max_slots * 4, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_gen, (size_t)max_slots * 8, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_hit, (size_t)max_slots * 8, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_best, (size_t)max_slots * 16, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_best, (size_t)max_slots * kStateWords * 8,
+                                             hipHostMallocDefault);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         labs_server_destroy(s);
@@ -274,7 +277,10 @@ extern "C" int labs_server_submit(labs_server *s, int32_t n, uint64_t seed, int3
     {
         // the tabu rule must be valid at this length
         labs_handle tmp;
-        if (check_rule(&tmp, to_rule(s->params.tabu), n)) return LABS_E_INVAL;
+        tmp.max_children_wide = s->h->max_children_wide;
+        if (check_rule(&tmp, to_rule(s->params.tabu), n) ||
+            check_children(&tmp, std::max(1, (int)s->params.children), 1 << memetic_class(n)))
+            return LABS_E_INVAL;
     }
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return LABS_E_CANCELLED;
@@ -355,9 +361,11 @@ extern "C" int labs_server_destroy(labs_server *s) {
     if (s->h_gen) hipHostFree(s->h_gen);
     if (s->h_hit) hipHostFree(s->h_hit);
     if (s->h_best) hipHostFree(s->h_best);
-    if (s->fork) hipEventDestroy(s->fork);
-    if (s->join) hipEventDestroy(s->join);
-    if (s->side) hipStreamDestroy(s->side);
+    if (s->sides.fork) hipEventDestroy(s->sides.fork);
+    for (int i = 0; i < kSideStreams; ++i) {
+        if (s->sides.join[i]) hipEventDestroy(s->sides.join[i]);
+        if (s->sides.s[i]) hipStreamDestroy(s->sides.s[i]);
+    }
     if (s->stream) hipStreamDestroy(s->stream);
     delete s;
     return LABS_OK;

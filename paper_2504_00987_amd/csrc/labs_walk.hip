@@ -30,13 +30,16 @@ __global__ __launch_bounds__(64 * WPG) void energy_kernel(const int8_t *__restri
     if (b >= count) return;
     const int N = ns ? ns[b] : n_uniform;
     const int8_t *row = seqs + b * (int64_t)stride;
-    bool b0 = false, b1 = false;
-    if (lane < N) b0 = row[lane] < 0;
-    if (lane + 64 < N) b1 = row[lane + 64] < 0;
-    const M128 M{ballot(b0), ballot(b1)};
+    uint64_t wd[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        const int i = lane + 64 * h;
+        wd[h] = ballot(i < N && row[i] < 0);
+    }
+    const M256 M{wd[0], wd[1], wd[2], wd[3]};
     int acc = 0;
 #pragma unroll
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < 4; ++w) {
         const int k = lane + 1 + 64 * w;
         if (k < N) {
             const int c = lag_corr(M, N, k);
@@ -55,26 +58,29 @@ template <int NW, int NB, bool TRACE>
 __device__ void run_tabu_item(const TabuLaunchArgs &a, int64_t w, int N, uint8_t *lds) {
     using Mask = typename MaskOf<NW>::type;
     const int lane = lane_id();
-    uint64_t lo, hi;
+    uint64_t wd[4] = {0ull, 0ull, 0ull, 0ull};
     if (a.starts != nullptr) {
         const int8_t *row = a.starts + w * (int64_t)a.start_stride;
-        bool b0 = false, b1 = false;
-        if (lane < N) b0 = row[lane] < 0;
-        if (lane + 64 < N) b1 = row[lane + 64] < 0;
-        lo = ballot(b0);
-        hi = ballot(b1);
+#pragma unroll
+        for (int h = 0; h < NW; ++h) {
+            const int i = lane + 64 * h;
+            wd[h] = ballot(i < N && row[i] < 0);
+        }
     } else {
-        const Draw4 d = philox10((uint32_t)w, 0u, 0u, kTagStart, a.k0, a.k1);
-        lo = (uint64_t)d.w0 | ((uint64_t)d.w1 << 32);
-        hi = (uint64_t)d.w2 | ((uint64_t)d.w3 << 32);
-        if (N < 64) {
-            lo &= (1ull << N) - 1ull;
-            hi = 0ull;
-        } else {
-            hi &= (N >= 128) ? ~0ull : ((1ull << (N - 64)) - 1ull);
+        // bits 128 q .. 128 q + 127 are the draw (walk, 0, q, START)
+#pragma unroll
+        for (int q = 0; q < (NW + 1) / 2; ++q) {
+            const Draw4 d = philox10((uint32_t)w, 0u, (uint32_t)q, kTagStart, a.k0, a.k1);
+            wd[2 * q] = (uint64_t)d.w0 | ((uint64_t)d.w1 << 32);
+            if (2 * q + 1 < NW) wd[2 * q + 1] = (uint64_t)d.w2 | ((uint64_t)d.w3 << 32);
+        }
+#pragma unroll
+        for (int h = 0; h < NW; ++h) {
+            const int b = N - 64 * h;  // bits of word h inside the sequence
+            wd[h] &= b >= 64 ? ~0ull : b <= 0 ? 0ull : ((1ull << b) - 1ull);
         }
     }
-    const Mask M = make_mask<NW>(lo, hi);
+    const Mask M = make_mask<NW>(wd[0], wd[1], wd[2], wd[3]);
     const Schedule sch = make_schedule(a.rule, N, a.k0, a.k1, (uint32_t)w, 0u);
     const WalkResult<NW> r =
         tabu_walk<NW, TRACE, 1, NB>(N, M, sch, a.rule.aspiration, a.k0, a.k1, (uint32_t)w, 0u, lds,
@@ -174,12 +180,15 @@ hipError_t launch_tabu_part(const TabuLaunchArgs &a, int64_t begin, int64_t end,
 // own queue head (32 words apart).
 template <int WPG>
 hipError_t launch_tabu_wpg(const TabuLaunchArgs &a, int groups, const hipStream_t *st) {
-    static_assert(kWalkClasses == 4, "one launcher per class below");
+    static_assert(kWalkClasses == 6, "one launcher per class below");
     const int64_t *ce = a.class_end;
-    hipError_t e = launch_tabu_part<2, 8, WPG>(a, 0, ce[0], groups, a.counter, st[0]);
-    if (e == hipSuccess) e = launch_tabu_part<2, 6, WPG>(a, ce[0], ce[1], groups, a.counter + 32, st[1]);
-    if (e == hipSuccess) e = launch_tabu_part<1, 4, WPG>(a, ce[1], ce[2], groups, a.counter + 64, st[2]);
-    if (e == hipSuccess) e = launch_tabu_part<1, 3, WPG>(a, ce[2], ce[3], groups, a.counter + 96, st[3]);
+    uint32_t *q = a.counter;
+    hipError_t e = launch_tabu_part<4, 16, WPG>(a, 0, ce[0], groups, q, st[0]);
+    if (e == hipSuccess) e = launch_tabu_part<4, 12, WPG>(a, ce[0], ce[1], groups, q + 32, st[1]);
+    if (e == hipSuccess) e = launch_tabu_part<2, 8, WPG>(a, ce[1], ce[2], groups, q + 64, st[2]);
+    if (e == hipSuccess) e = launch_tabu_part<2, 6, WPG>(a, ce[2], ce[3], groups, q + 96, st[3]);
+    if (e == hipSuccess) e = launch_tabu_part<1, 4, WPG>(a, ce[3], ce[4], groups, q + 128, st[4]);
+    if (e == hipSuccess) e = launch_tabu_part<1, 3, WPG>(a, ce[4], ce[5], groups, q + 160, st[5]);
     return e;
 }
 

@@ -50,6 +50,12 @@ class MemeticResult:
     gens_done: torch.Tensor  # int64 [P]
 
 
+def _default_stride(ns_arr, n_uniform: int) -> int:
+    """Output row stride: 128, or the longest sequence when that is longer."""
+    n_max = int(ns_arr.max()) if ns_arr is not None and ns_arr.size else n_uniform
+    return max(128, n_max)
+
+
 class Labs:
     """A liblabs handle bound to one GPU."""
 
@@ -101,13 +107,15 @@ class Labs:
         return e.value, cnt.value, seq
 
     def tabu_batch(self, rules: Rules, walks: int, seed: int, ns=None, n_uniform: int = 0,
-                   starts: torch.Tensor | None = None, out_stride: int = 128,
+                   starts: torch.Tensor | None = None, out_stride: int | None = None,
                    trace_stride: int = 0, out=None, stream=None) -> TabuResult:
         dev = torch.device("cuda", self.device)
         ns_arr = None
         if ns is not None:
             ns_arr = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
             assert ns_arr.shape == (walks,)
+        if out_stride is None:
+            out_stride = _default_stride(ns_arr, n_uniform)
         if starts is not None:
             assert starts.is_cuda and starts.dtype == torch.int8 and starts.is_contiguous()
             assert starts.shape[0] == walks
@@ -159,13 +167,15 @@ class Labs:
                                   target, mode, chunk, stop_all, waves_per_replica, children)
 
     def memetic_run(self, K: int, rules: Rules, generations: int, pops: int, seed: int,
-                    ns=None, n_uniform: int = 0, out_stride: int = 128, stream=None,
+                    ns=None, n_uniform: int = 0, out_stride: int | None = None, stream=None,
                     **kw) -> MemeticResult:
         dev = torch.device("cuda", self.device)
         ns_arr = None
         if ns is not None:
             ns_arr = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
             assert ns_arr.shape == (pops,)
+        if out_stride is None:
+            out_stride = _default_stride(ns_arr, n_uniform)
         best = torch.empty((pops, out_stride), dtype=torch.int8, device=dev)
         be = torch.empty(pops, dtype=torch.int32, device=dev)
         hit = torch.empty(pops, dtype=torch.int64, device=dev)

@@ -56,6 +56,14 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.MemeticParams) == 88
 
 
+def test_limits_match_header():
+    import re
+    from paper_2504_00987_amd import _lib
+    text = open(os.path.join(ROOT, "include", "liblabs.h")).read()
+    val = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define (LABS_\w+) (\d+)", text)}
+    assert (val["LABS_MIN_N"], val["LABS_MAX_N"], val["LABS_MAX_K"]) == (_lib.MIN_N, _lib.MAX_N, _lib.MAX_K)
+
+
 def test_product_package_never_imports_the_oracle():
     pkg = os.path.join(ROOT, "paper_2504_00987_amd")
     for dirpath, _, files in os.walk(pkg):
