@@ -721,3 +721,73 @@ int64_t orc_memetic_advance_batched(int n, int K, int B, uint32_t p_comb, uint32
     }
     return done;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Deviation from skew-symmetry (App. A).                                     */
+/* ------------------------------------------------------------------------- */
+/* n_non-skew of an odd-length sequence t[0..m-1], m = 2c + 1: the number of
+ * i = 1..c with t[c+i] != (-1)^i t[c-i] (App. A's sum of |differences| / 2;
+ * skew-symmetry itself is Sec. II.C's condition).  Even m: -1 (undefined). */
+int orc_non_skew(const int8_t *t, int m)
+{
+    if (m < 1 || (m & 1) == 0)
+        return -1;
+    int c = (m - 1) / 2, count = 0;
+    for (int i = 1; i <= c; ++i) {
+        int sign = (i & 1) ? -1 : 1;
+        if (t[c + i] != sign * t[c - i])
+            ++count;
+    }
+    return count;
+}
+
+/* d(S) of App. A: the least n_non-skew over the sequences reachable by one
+ * rotation Rot(S; r) (the first r elements moved to the end) followed by one
+ * insertion Ins(.; i, xi) (xi after the first i elements) or one deletion
+ * Del(.; i) (the i-th element, 1-based, removed).  n_non-skew only exists
+ * for odd lengths, so an odd N is measured on its rotations alone and an
+ * even N on rotation + deletion; with_insertion = 1 also takes rotation +
+ * insertion for even N (the printed values follow deletion only).
+ * Returns -1 for n < 1 or n > ORC_MAX_N. */
+int orc_skew_deviation(const int8_t *s, int n, int with_insertion)
+{
+    int8_t rot[ORC_MAX_N], t[ORC_MAX_N + 1];
+    if (n < 1 || n > ORC_MAX_N)
+        return -1;
+    int best = n;
+    for (int r = 0; r < n; ++r) {
+        for (int k = 0; k < n; ++k)
+            rot[k] = s[(k + r) % n];
+        if (n & 1) {
+            int v = orc_non_skew(rot, n);
+            if (v < best)
+                best = v;
+            continue;
+        }
+        for (int i = 1; i <= n; ++i) {  /* Del(rot; i) */
+            int m = 0;
+            for (int k = 0; k < n; ++k)
+                if (k != i - 1)
+                    t[m++] = rot[k];
+            int v = orc_non_skew(t, n - 1);
+            if (v < best)
+                best = v;
+        }
+        if (!with_insertion)
+            continue;
+        for (int i = 0; i <= n; ++i) {  /* Ins(rot; i, xi) */
+            for (int xi = -1; xi <= 1; xi += 2) {
+                int m = 0;
+                for (int k = 0; k < i; ++k)
+                    t[m++] = rot[k];
+                t[m++] = (int8_t)xi;
+                for (int k = i; k < n; ++k)
+                    t[m++] = rot[k];
+                int v = orc_non_skew(t, n + 1);
+                if (v < best)
+                    best = v;
+            }
+        }
+    }
+    return best;
+}

@@ -53,6 +53,8 @@ def lib():
         L.orc_energy.restype = i64
         L.orc_energy_batch.argtypes = [P, P, i32, i32, i64, P]
         L.orc_bruteforce_min.argtypes = [ctypes.c_int, P, P]
+        L.orc_non_skew.argtypes = [P, ctypes.c_int]
+        L.orc_skew_deviation.argtypes = [P, ctypes.c_int, ctypes.c_int]
         L.orc_neighbour_energies_recompute.argtypes = [P, ctypes.c_int, P]
         L.orc_neighbour_energies_tables.argtypes = [P, ctypes.c_int, P]
         L.orc_walk_schedule.argtypes = [ctypes.c_int] * 10 + [u64, u32, u32, P, P, P]
@@ -143,6 +145,21 @@ def bruteforce_min(n: int):
     if lib().orc_bruteforce_min(n, _p(emin), _p(cnt)) != 0:
         raise ValueError("n out of range")
     return int(emin[0]), int(cnt[0])
+
+
+def non_skew(t) -> int:
+    """n_non-skew of an odd-length sequence (App. A); -1 for even lengths."""
+    t = _seq(t)
+    return int(lib().orc_non_skew(_p(t), len(t)))
+
+
+def skew_deviation(s, with_insertion: bool = False) -> int:
+    """d(S) of App. A (odd N: rotations; even N: rotation + one deletion,
+    and one insertion too when with_insertion)."""
+    s = _seq(s)
+    if not 1 <= len(s) <= MAX_N:
+        raise ValueError(f"sequence length must be in [1, {MAX_N}]")
+    return int(lib().orc_skew_deviation(_p(s), len(s), 1 if with_insertion else 0))
 
 
 def neighbour_energies(s, recompute: bool = True) -> np.ndarray:

@@ -210,3 +210,69 @@ def test_neighbour_energies_exhaustive_small():
         for code in range(1 << n):
             s = np.array([1 - 2 * ((code >> i) & 1) for i in range(n)], dtype=np.int8)
             assert list(O.neighbour_energies(s, recompute=False)) == list(npref.flip_energies(s))
+
+
+# ---------------------------------------------------------------------------
+# Deviation from skew-symmetry, d(S) (App. A)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("row", _table(), ids=lambda r: f"N{r[0]}-{r[5][:6]}")
+def test_skew_deviation_paper_column(row):
+    # the d(S) column of Table "labs_results": odd N over rotations, even N
+    # over rotation + one deletion
+    n, _, _, _, _, hexs, d = row
+    s = decode_hex(hexs, n)
+    assert O.skew_deviation(s) == d
+    # allowing an insertion as well can only lower it (odd N: no change)
+    di = O.skew_deviation(s, with_insertion=True)
+    assert di <= d and (n % 2 == 0 or di == d)
+
+
+def _skew_symmetric(c, rng):
+    # odd length 2c + 1: free centre half, s_{c+i} = (-1)^i s_{c-i} (Sec. II.C)
+    left = rng.choice(np.array([-1, 1], dtype=np.int8), size=c + 1)
+    s = np.zeros(2 * c + 1, dtype=np.int8)
+    s[: c + 1] = left
+    for i in range(1, c + 1):
+        s[c + i] = (-1) ** i * s[c - i]
+    return s
+
+
+def test_skew_deviation_constructions():
+    rng = np.random.default_rng(8)
+    for c in (1, 5, 30, 59, 100):
+        s = _skew_symmetric(c, rng)
+        n = len(s)
+        assert O.non_skew(s) == 0 and O.skew_deviation(s) == 0
+        # skew-symmetric sequences have C_k = 0 at every odd k
+        C = O.autocorrelation(s)
+        assert not np.any(C[1::2])
+        # breaking k pairs (flipping right-half elements) gives n_non-skew k
+        k = min(c, 7)
+        t = s.copy()
+        t[c + 1 + rng.choice(c, size=k, replace=False)] *= -1
+        assert O.non_skew(t) == k and O.skew_deviation(t) <= k
+        # rotations do not change d
+        for r in (1, n // 2, n - 1):
+            assert O.skew_deviation(np.roll(t, -r)) == O.skew_deviation(t)
+        # an even sequence one insertion away from a skew-symmetric one
+        # (some deletion undoes it): d = 0
+        for i in (0, c, n):
+            e = np.insert(s, i, np.int8(1 if i % 2 else -1))
+            assert O.skew_deviation(e) == 0
+    assert O.non_skew(np.ones(4, dtype=np.int8)) == -1
+
+
+def test_skew_deviation_bounds():
+    # d <= the unrotated value; d(S) = d(-S) = d(reversed S) (the condition
+    # is invariant under negation; reversal maps i -> -i pairs onto themselves)
+    rng = np.random.default_rng(9)
+    for n in (9, 10, 31, 64, 65, 120):
+        s = rng.choice(np.array([-1, 1], dtype=np.int8), size=n)
+        d = O.skew_deviation(s)
+        if n % 2:
+            assert d <= O.non_skew(s)
+        else:
+            assert d <= O.non_skew(s[:-1]) and d <= O.non_skew(s[1:])
+        assert O.skew_deviation(-s) == d
+        assert O.skew_deviation(s[::-1].copy()) == d
+        assert 0 <= d <= (n - 1) // 2
