@@ -1,7 +1,7 @@
 """Benchmark of the batched tabu-search hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload tabu_n64|tabu_uneven]
-                    [--no-cpu] [--no-ttt] [--no-serving]
+    python bench.py [--steps K] [--warmup W] [--workload tabu_n64|tabu_uneven|tabu_n256]
+                    [--no-cpu] [--no-ttt] [--no-serving] [--no-skew]
 
 A step is one labs_tabu_batch call over the whole batch (every walk scores
 all N single-flip neighbours at each of its steps).  The default workload is
@@ -14,8 +14,10 @@ roofline of the walk kernel (integer VALU bound) timed with HIP events on the
 stream it runs on, the CPU oracle timed on a bounded sample of the same
 workload on this host, time-to-target energy of the memetic search at N=120
 (256 replicas of K=100; one launch per generation, a replayed graph of
-one-generation launches, and the batched persistent form), and the serving
-loop's throughput and latency percentiles under Poisson arrivals.
+one-generation launches, the persistent form, and the batched-generation
+variant), the deviation from skew-symmetry d(S) of App. A over a batch of
+N=120 rows, and the serving loop's throughput and latency percentiles under
+Poisson arrivals.
 """
 from __future__ import annotations
 
@@ -46,18 +48,21 @@ KERNEL_SOURCES = ("paper_2504_00987_amd/csrc/labs_device.hpp",
 COPY_SCALE = {"FETCH_SIZE": 262144 / 131087, "WRITE_SIZE": 262144 / 262144}
 COUNTERS = {
     # per launch in the default launch configuration (four walks per
-    # workgroup); sums over the kernels of one call (the uneven batch runs
-    # one kernel per length class, concurrently)
-    "tabu_n64": {"digest": "9286a4b529551e30", "FETCH_SIZE": 47, "WRITE_SIZE": 576,
-                 "SQ_INSTS_VALU": 67005662, "SQ_INSTS_LDS": 14745600,
+    # workgroup), mean over the profiled dispatches; sums over the kernels
+    # of one call (the uneven batch runs one kernel per length class,
+    # concurrently)
+    "tabu_n64": {"digest": "ba0f197774063be3", "FETCH_SIZE": 44.9, "WRITE_SIZE": 576.0,
+                 "SQ_INSTS_VALU": 67017950, "SQ_INSTS_LDS": 14745600,
                  "SQ_LDS_BANK_CONFLICT": 1048576,
                  "source": "profiles/tabu_kernel_counters.md"},
-    "tabu_uneven": {"digest": "9286a4b529551e30", "FETCH_SIZE": 197 + 230 + 139 + 65,
-                    "WRITE_SIZE": 452 + 661 + 300 + 43,
-                    "SQ_INSTS_VALU": 143507584 + 128937064 + 18380242 + 2080190,
-                    "SQ_INSTS_LDS": 32546042 + 28460822 + 3989164 + 409056,
-                    "SQ_LDS_BANK_CONFLICT": 22137471 + 16248306 + 2932512 + 471931,
+    "tabu_uneven": {"digest": "ba0f197774063be3", "FETCH_SIZE": 628.8, "WRITE_SIZE": 1457.5,
+                    "SQ_INSTS_VALU": 292967492, "SQ_INSTS_LDS": 65405084,
+                    "SQ_LDS_BANK_CONFLICT": 41790220,
                     "source": "profiles/tabu_kernel_counters.md"},
+    "tabu_n256": {"digest": "ba0f197774063be3", "FETCH_SIZE": 167.2, "WRITE_SIZE": 1088.0,
+                  "SQ_INSTS_VALU": 2508865536, "SQ_INSTS_LDS": 524652544,
+                  "SQ_LDS_BANK_CONFLICT": 4194304,
+                  "source": "profiles/tabu_kernel_counters.md"},
 }
 
 
@@ -86,7 +91,7 @@ def tabu_section(args, lb, wl):
     ops_per_launch = 3 * int(sum(int(s) * lag_terms_per_step(int(n)) for s, n in zip(steps_per_walk, ns)))
 
     dev = torch.device("cuda", 0)
-    out = (torch.empty((W, 128), dtype=torch.int8, device=dev),
+    out = (torch.empty((W, max(128, int(ns.max()))), dtype=torch.int8, device=dev),
            torch.empty(W, dtype=torch.int32, device=dev),
            torch.empty(W, dtype=torch.int32, device=dev), None)
     uniform = wl.n is not None
@@ -202,14 +207,15 @@ def cpu_tabu(args, wl, ns):
     # spreads them over threads; nothing else is tuned.
     from oracle import oracle as O
     threads = max(1, min(16, len(os.sched_getaffinity(0))))
-    sample = args.cpu_walks or wl.walks
+    # all walks up to N = 128; a bounded prefix of the N = 256 workload
+    sample = args.cpu_walks or (wl.walks if int(ns.max()) <= 128 else 128)
     r = wl.rules
     sched = O.Schedule(r.steps_rule, r.steps_a, r.tenure_rule, r.lo_num, r.lo_den, r.lo_add,
                        r.hi_num, r.hi_den, r.hi_add, r.aspiration)
     sub_ns = ns[:sample]
     passes, c0 = 0, time.perf_counter()
     while True:
-        O.tabu_batch(sample, sched, wl.seed, ns=sub_ns, stride=128, nthreads=threads)
+        O.tabu_batch(sample, sched, wl.seed, ns=sub_ns, stride=max(128, int(sub_ns.max())), nthreads=threads)
         passes += 1
         if time.perf_counter() - c0 >= args.cpu_min_s or passes >= 100:
             break
@@ -223,6 +229,44 @@ def cpu_tabu(args, wl, ns):
         "sample": f"{passes} passes over walks 0..{sample - 1} of {wl.name} in {cpu_s:.1f} s "
                   f"(plain C, gcc -O2, {threads} threads)",
     }
+
+
+# ---------------------------------------------------------------------------
+# Deviation from skew-symmetry d(S) (App. A), an analysis of results
+# ---------------------------------------------------------------------------
+def skew_section(args, lb):
+    import torch
+    from paper_2504_00987_amd import inputs as I
+    count, n, seed = 4096, 120, 1006
+    S = torch.from_numpy(I.random_pm1(count, n, n, seed=seed)).cuda()
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        lb.skew_deviation(S, n_uniform=n, stream=stream)
+    reps = 10
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        d = lb.skew_deviation(S, n_uniform=n, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    # even N: N rotations x N deletions, (N - 2) / 2 pair tests each
+    tests = count * n * n * ((n - 2) // 2)
+    res = {"rows": count, "n": n, "data": f"uniform random +-1 rows, numpy seed {seed}",
+           "kernel_ms": ms, "rows_per_s": count / (ms * 1e-3),
+           "pair_tests_per_s": tests / (ms * 1e-3),
+           "d_histogram": np.bincount(d.cpu().numpy()).tolist()}
+    if not args.no_cpu:
+        from oracle import oracle as O
+        rows = S[:32].cpu().numpy()
+        t0 = time.perf_counter()
+        want = [O.skew_deviation(r) for r in rows]
+        dt = time.perf_counter() - t0
+        if want != d[:32].cpu().numpy().tolist():
+            raise RuntimeError("skew deviation differs from the oracle")
+        res["cpu_baseline"] = {"value": len(rows) / dt, "unit": "rows/s", "cores": 1,
+                               "kind": "oracle", "sample": f"rows 0..31 in {dt:.2f} s"}
+    return res
 
 
 # ---------------------------------------------------------------------------
@@ -370,7 +414,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="tabu_n64", choices=["tabu_n64", "tabu_uneven"])
+    ap.add_argument("--workload", default="tabu_n64", choices=["tabu_n64", "tabu_uneven", "tabu_n256"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default launch configuration instead of the tuned one")
@@ -384,6 +428,7 @@ def main() -> int:
     ap.add_argument("--ttt-children", default="8",
                     help="children per generation of the batched-generation rows (comma list)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--no-skew", action="store_true", help="skip the skew-deviation section")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=8192)
     ap.add_argument("--serve-chunk", type=int, default=25)
@@ -413,7 +458,7 @@ def main() -> int:
     from paper_2504_00987_amd import inputs as I
     from paper_2504_00987_amd.labs import Labs
 
-    wl = I.TABU_N64 if args.workload == "tabu_n64" else I.TABU_UNEVEN
+    wl = I.TABU_WORKLOADS[args.workload]
     torch.cuda.set_device(0)
     lb = Labs(0)
     line, ns = tabu_section(args, lb, wl)
@@ -426,6 +471,9 @@ def main() -> int:
         print("# time to target done", file=sys.stderr, flush=True)
         if not args.no_cpu:
             line["time_to_target"]["cpu_baseline"] = cpu_memetic(args)
+    if not args.no_skew:
+        line["skew_deviation"] = skew_section(args, lb)
+        print("# skew deviation done", file=sys.stderr, flush=True)
     if not args.no_serving:
         line["serving"] = serving_section(args, lb)
         print("# serving done", file=sys.stderr, flush=True)

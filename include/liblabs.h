@@ -133,6 +133,24 @@ int labs_energy_batch(labs_handle *h, const int8_t *seqs, const int32_t *ns,
                       int32_t *energies, void *stream);
 
 /*
+ * Deviation from skew-symmetry d(S) of App. A for a batch of sequences: the
+ * least number of broken pairs t_{c+i} != (-1)^i t_{c-i} (the condition of
+ * Sec. II.C for odd length 2c + 1) over the rotations of S (first r elements
+ * moved to the end) -- for even N, each rotation followed by the deletion
+ * of one element.  (App. A also admits one insertion; its printed values
+ * follow deletion only.)
+ *   seqs      device int8 [count][stride], +-1 in the first N entries of a row
+ *   ns        device int32 [count] per-row lengths, or NULL to use n_uniform
+ *   d         device int32 [count] output
+ * Asynchronous on `stream`; the caller guarantees LABS_MIN_N <= ns[b] <=
+ * min(stride, LABS_MAX_N).  Work per row: N^2 (odd N) or N^3 (even N) / 2
+ * pair tests.
+ */
+int labs_skew_deviation_batch(labs_handle *h, const int8_t *seqs, const int32_t *ns,
+                              int32_t n_uniform, int32_t stride, int64_t count, int32_t *d,
+                              void *stream);
+
+/*
  * Exhaustive minimum of Eq. (2) over all 2^n sequences of length n
  * (3 <= n <= LABS_MAX_BRUTE_N), the reference targets for time-to-solution
  * at small n.  E is invariant under negation (Sec. II.B), so the 2^(n-1)

@@ -17,7 +17,8 @@ MIN_N, MAX_N, MAX_K = 3, 256, 128
 
 EXPORTED = [
     "labs_create", "labs_destroy", "labs_last_error", "labs_status_name", "labs_version",
-    "labs_energy_batch", "labs_bruteforce_min", "labs_tabu_batch", "labs_set_launch", "labs_get_launch",
+    "labs_energy_batch", "labs_skew_deviation_batch", "labs_bruteforce_min", "labs_tabu_batch",
+    "labs_set_launch", "labs_get_launch",
     "labs_autotune", "labs_memetic_run", "labs_server_create", "labs_server_submit",
     "labs_server_poll", "labs_server_cancel", "labs_server_stats", "labs_server_destroy",
 ]
@@ -73,6 +74,7 @@ def load():
     L.labs_status_name.restype = ctypes.c_char_p
     L.labs_version.restype = ctypes.c_char_p
     L.labs_energy_batch.argtypes = [P, P, P, i32, i32, i64, P, P]
+    L.labs_skew_deviation_batch.argtypes = [P, P, P, i32, i32, i64, P, P]
     L.labs_bruteforce_min.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i64), P]
     L.labs_tabu_batch.argtypes = [P, ctypes.POINTER(TabuParams), P, i32, P, i32, i64, u64,
                                   P, i32, P, P, P, i32, P]

@@ -310,6 +310,27 @@ int labs_energy_batch(labs_handle *h, const int8_t *seqs, const int32_t *ns, int
     return LABS_OK;
 }
 
+int labs_skew_deviation_batch(labs_handle *h, const int8_t *seqs, const int32_t *ns,
+                              int32_t n_uniform, int32_t stride, int64_t count, int32_t *d,
+                              void *stream) {
+    if (!h) return LABS_E_INVAL;
+    h->last_error.clear();
+    if (count < 0) return fail(h, LABS_E_INVAL, "count < 0");
+    if (count == 0) return LABS_OK;
+    if (!seqs || !d) return fail(h, LABS_E_INVAL, "null seqs or output");
+    if (!ns && (n_uniform < LABS_MIN_N || n_uniform > LABS_MAX_N))
+        return fail(h, LABS_E_INVAL, "n_uniform=%d out of [%d, %d]", n_uniform, LABS_MIN_N,
+                    LABS_MAX_N);
+    if (stride < (ns ? LABS_MIN_N : n_uniform))
+        return fail(h, LABS_E_INVAL, "stride=%d shorter than a row", stride);
+    if (count > (int64_t)0x7fffffff * 4) return fail(h, LABS_E_INVAL, "count too large");
+    DeviceGuard g(h->device);
+    hipError_t e = launch_skew_deviation(seqs, ns, n_uniform, stride, count, d,
+                                         (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(h, e, "skew deviation kernel launch");
+    return LABS_OK;
+}
+
 int labs_bruteforce_min(labs_handle *h, int32_t n, int32_t *min_e, int64_t *count,
                         int8_t *argmin) {
     if (!h) return LABS_E_INVAL;

@@ -135,6 +135,8 @@ int prepare_memetic_kernels();
 hipError_t launch_memetic_advance(const MemeticLaunchArgs &a, hipStream_t s,
                                   const SideStreams *sides = nullptr);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
+hipError_t launch_skew_deviation(const int8_t *seqs, const int32_t *ns, int32_t n_uniform,
+                                 int32_t stride, int64_t count, int32_t *out, hipStream_t s);
 hipError_t launch_gather_best(const MemeticStateDev &st, const int32_t *state_idx,
                               const int32_t *ns, int32_t n_uniform, int32_t count,
                               int8_t *best_seq, int32_t out_stride, int32_t *best_e,

@@ -94,6 +94,19 @@ class Labs:
                                              _stream(stream)))
         return out
 
+    def skew_deviation(self, seqs: torch.Tensor, ns: torch.Tensor | None = None,
+                       n_uniform: int = 0, stream=None) -> torch.Tensor:
+        """d(S) of App. A for every row (odd N: rotations; even N: rotation
+        and one deletion)."""
+        assert seqs.is_cuda and seqs.dtype == torch.int8 and seqs.dim() == 2 and seqs.is_contiguous()
+        if ns is not None:
+            assert ns.is_cuda and ns.dtype == torch.int32 and ns.numel() == seqs.shape[0]
+        out = torch.empty(seqs.shape[0], dtype=torch.int32, device=seqs.device)
+        self._check(self.L.labs_skew_deviation_batch(self.h, _ptr(seqs), _ptr(ns), n_uniform,
+                                                     seqs.shape[1], seqs.shape[0], _ptr(out),
+                                                     _stream(stream)))
+        return out
+
     # -- Alg. 2 / Alg. 4 -----------------------------------------------------
     def bruteforce_min(self, n: int):
         """Exhaustive minimum energy at length n: (E_min, how many of the 2^n

@@ -68,6 +68,36 @@ def test_energy_closed_forms_and_edges(lb):
     assert empty.numel() == 0
 
 
+def test_skew_deviation(lb):
+    # App. A's d(S): the printed column of Table labs_results, then random
+    # rows of every length class against the oracle
+    from tests.test_oracle_objective import _table, decode_hex
+    say("skew deviation: paper rows and random ragged rows N = 3..256")
+    rows, ns, want = [], [], []
+    for n, _, _, _, _, hexs, d in _table():
+        r = np.zeros(256, dtype=np.int8)
+        r[:n] = decode_hex(hexs, n)
+        rows.append(r)
+        ns.append(n)
+        want.append(d)
+    rng = np.random.default_rng(17)
+    extra = [3, 4, 5, 6, 63, 64, 65, 128, 129, 255, 256] + list(rng.integers(3, 257, 120))
+    R = I.random_pm1_ragged(np.array(extra, dtype=np.int32), 256, seed=18)
+    for n, r in zip(extra, R):
+        rows.append(r)
+        ns.append(int(n))
+        want.append(O.skew_deviation(r[:n]))
+    got = lb.skew_deviation(torch.from_numpy(np.stack(rows)).cuda(),
+                            ns=torch.from_numpy(np.array(ns, dtype=np.int32)).cuda())
+    assert np.array_equal(got.cpu().numpy(), want)
+    # uniform length and the empty batch
+    U = I.random_pm1(50, 120, 120, seed=19)
+    got = lb.skew_deviation(torch.from_numpy(U).cuda(), n_uniform=120).cpu().numpy()
+    assert np.array_equal(got, [O.skew_deviation(u) for u in U])
+    assert lb.skew_deviation(torch.zeros((0, 64), dtype=torch.int8, device="cuda"),
+                             n_uniform=64).numel() == 0
+
+
 def test_bruteforce_min(lb):
     say("exhaustive minimum: oracle enumeration for n <= 22, properties beyond")
     for n in [3, 4, 5, 7, 8, 11, 13, 16, 20, 22]:
