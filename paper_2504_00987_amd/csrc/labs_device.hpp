@@ -345,10 +345,10 @@ struct WalkResult {
     int final_e;
 };
 
-// LDS layout of one walk: P records, Q records (each run preceded by 15
-// spare records, so that the byte update after a move needs no bounds
-// test), plain P, plain Q, C bytes, and six words through which the two
-// wavefronts of a split walk exchange their minima.
+// LDS layout of one walk of N > 64 (record form): P records, Q records
+// (each run preceded by 15 spare records, so that the byte update after a
+// move needs no bounds test), plain P, plain Q, C bytes, and six words
+// through which the two wavefronts of a split walk exchange their minima.
 //   P[x] = s_x for x < N, 0 otherwise; Q is the reversed sequence,
 //   Q[x] = s_{N-1-x} for x < N, 0 otherwise;
 //   record x (16 bytes, at 16 x) holds P[x .. x+15], so a window starting
@@ -362,8 +362,7 @@ struct WalkResult {
 // NBIG - 1 chunks); LEN the farthest byte the C update reads.
 template <int NW> struct WalkLds;
 template <> struct WalkLds<1> {
-    static constexpr int NBIG = 4, LEN = 128, CLEN = 64;
-    static constexpr int NREC = 64 + 16 * (NBIG - 1) + 1;
+    static constexpr int NBIG = 4;  // lag form below
 };
 template <> struct WalkLds<2> {
     static constexpr int NBIG = 8, LEN = 256, CLEN = 128;
@@ -374,10 +373,25 @@ template <> struct WalkLds<4> {
     static constexpr int NREC = 256 + 16 * (NBIG - 1) + 1;
 };
 constexpr int kSpareRecords = 15;
+
+// LDS layout of one walk of N <= 64 (lag form): 16 spare bytes, then row j
+// (kLagRow bytes apart, so that 16-byte reads of consecutive rows are
+// conflict-free) holding t_jk = s_{j+k} + s_{j-k} for k = 1..64 in bytes
+// 0..63 (terms outside the sequence are 0) and 16 spare bytes; then
+// CB[k-1] = C_k as int8.  The byte before each row is spare, so the update
+// write of the lane whose neighbour was flipped (lag 0) lands there; rows
+// j >= N are never read as neighbour data and take stray writes.
+constexpr int kLagRow = 80;
+constexpr int kLagBase = 16;
+constexpr int kLagBytes = kLagBase + 64 * kLagRow + 64;
+
 template <int NW>
 constexpr int walk_lds_bytes() {
-    return 2 * 16 * (kSpareRecords + WalkLds<NW>::NREC) + 2 * WalkLds<NW>::LEN + WalkLds<NW>::CLEN +
-           32;  // + the two-wavefront exchange words
+    if constexpr (NW == 1)
+        return kLagBytes;
+    else
+        return 2 * 16 * (kSpareRecords + WalkLds<NW>::NREC) + 2 * WalkLds<NW>::LEN +
+               WalkLds<NW>::CLEN + 32;  // + the two-wavefront exchange words
 }
 
 // Lane l receives bit l of a wave-uniform 64-bit mask.
@@ -392,6 +406,31 @@ __device__ __forceinline__ uint32_t pack4(Mask M, int x, int N) {
     if (x >= N) return 0u;
     const uint32_t nib = (uint32_t)mask_lo(m_shr(M, x)) & 0xFu;
     const int cnt = min(N - x, 4);
+    const uint32_t valid = cnt >= 4 ? 0x01010101u : (0x01010101u & ((1u << (8 * cnt)) - 1u));
+    const uint32_t ones = (nib * 0x00204081u) & 0x01010101u;  // bit b -> byte b
+    return valid | (ones * 0xFEu);
+}
+
+// |a - b| + c in one instruction, a wave-uniform.
+__device__ __forceinline__ uint32_t absdiff_add_s(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t d;
+    asm("v_sad_u32 %0, %1, %2, %3" : "=v"(d) : "s"(a), "v"(b), "v"(c));
+    return d;
+}
+
+// Bytewise a + b of four int8 lanes holding -1, 0 or +1 each (no carry
+// crosses a byte: the low seven bits of each byte add to at most 0xFE).
+__device__ __forceinline__ uint32_t add_bytes(uint32_t a, uint32_t b) {
+    return ((a & 0x7F7F7F7Fu) + (b & 0x7F7F7F7Fu)) ^ ((a ^ b) & 0x80808080u);
+}
+
+// Four int8 lanes from bits x..x+3 of a 64-bit value of which the first n
+// bits are valid (bit set <=> -1): 0x01 for +1, 0xFF for -1, 0 past n.
+// Bits past n must be clear.
+__device__ __forceinline__ uint32_t pack_bits4(uint64_t bits, int x, int n) {
+    if (x >= n) return 0u;
+    const uint32_t nib = (uint32_t)(bits >> x) & 0xFu;
+    const int cnt = min(n - x, 4);
     const uint32_t valid = cnt >= 4 ? 0x01010101u : (0x01010101u & ((1u << (8 * cnt)) - 1u));
     const uint32_t ones = (nib * 0x00204081u) & 0x01010101u;  // bit b -> byte b
     return valid | (ones * 0xFEu);
@@ -415,6 +454,147 @@ __device__ __forceinline__ void walk_sync() {
         __syncthreads();
 }
 
+// One walk of N <= 64 in the lag form (one wavefront, lane j owning
+// neighbour j and lag k = j + 1).  Neighbour j's sums are
+//   v_j = sum_k t_jk C_k   (NB chunk dot products of its row against C),
+//   u_j = sum_{k <= min(j, N-1-j)} s_{j+k} s_{j-k}   (kept per lane),
+// since sum_k t_jk^2 = N - 1 + 2 u_j.  A move at p changes, for each j != p,
+// only the lag k = |p - j| of row j: the other end of that pair is
+// q = 2j - p, so t_jk becomes s_p + s_q (s_q = 0 outside the sequence) and
+// u_j changes by -2 s_p(old) s_q when q is inside; C_k changes by
+// -2 s_p(old) t_pk, read from row p, which the move leaves unchanged.
+template <bool TRACE, int NB>
+__device__ __forceinline__ WalkResult<1> tabu_walk_lags(const int N_in, const uint64_t M0,
+                                                        const Schedule sch_in,
+                                                        const int aspiration_in,
+                                                        const uint32_t k0, const uint32_t k1,
+                                                        const uint32_t entity, const uint32_t gen,
+                                                        uint8_t *__restrict__ lds,
+                                                        int16_t *__restrict__ trace) {
+    static_assert(NB >= 1 && NB <= 4, "N <= 64 needs at most four 16-lag chunks");
+    const int lane = lane_id();
+    const int N = __builtin_amdgcn_readfirstlane(N_in);
+    const int aspiration = __builtin_amdgcn_readfirstlane(aspiration_in);
+    Schedule sch;
+    sch.T = __builtin_amdgcn_readfirstlane(sch_in.T);
+    sch.lo = __builtin_amdgcn_readfirstlane(sch_in.lo);
+    sch.hi = __builtin_amdgcn_readfirstlane(sch_in.hi);
+    uint64_t M = uniform64(M0);
+    // bit i of Mr is bit N-1-i of M
+    const uint64_t Mr = ballot(lane < N && ((M >> (N - 1 - lane)) & 1ull));
+
+    uint8_t *const rows = lds + kLagBase;
+    uint8_t *const row = rows + kLagRow * lane;
+    int8_t *const CB = (int8_t *)(rows + 64 * kLagRow);
+
+    // Row j: s_{j+k} is bit k-1 of R = M >> (j+1) (valid below N-1-j),
+    // s_{j-k} bit k-1 of L = Mr >> (N-j) (valid below j).
+    const int j = lane;
+    const int nr = max(N - 1 - j, 0), nl = j < N ? j : 0;
+    const uint64_t R = (M >> j) >> 1;
+    const uint64_t L = j < N ? (Mr >> (N - 1 - j)) >> 1 : 0ull;
+    walk_sync<1>();
+#pragma unroll
+    for (int d = 0; d < 16; ++d)
+        ((uint32_t *)row)[d] = add_bytes(pack_bits4(R, 4 * d, nr), pack_bits4(L, 4 * d, nl));
+    const int nu = min(nr, nl);
+    int u = nu - 2 * __popcll((R ^ L) & ((1ull << nu) - 1ull));
+
+    // C_k of this lane's lag (Eq. 1), its int8 mirror, the energy.
+    const int k = lane + 1;
+    int C = k < N ? lag_corr(M, N, k) : 0;
+    CB[lane] = (int8_t)C;
+    int E = wave_sum(C * C);
+
+    // lanes past the sequence are never admissible: infinite tenure and no
+    // aspiration
+    int tabu = lane < N ? 0 : INT_MAX;
+    const bool asp = aspiration && lane < N;
+    uint64_t best = M;
+    int bestE = E;
+    uint32_t dr0 = 0u, dr1 = 0u;
+    const int twoj = 2 * j;
+    // row j's byte k-1 is lds[rowm1 + k] (k = 0: the spare byte before the
+    // row)
+    const uint32_t rowm1 = (uint32_t)(kLagBase + kLagRow * lane - 1);
+
+    uint4 tc[NB];
+    walk_sync<1>();
+#pragma unroll
+    for (int r = 0; r < NB; ++r) tc[r] = ((const uint4 *)row)[r];
+
+    for (int t0 = 1; t0 <= sch.T; t0 += 64) {
+        {
+            const Draw4 d = philox10(entity, gen, (uint32_t)(t0 + lane), kTagStep, k0, k1);
+            dr0 = d.w0;
+            dr1 = d.w1;
+        }
+        const int t_end = min(sch.T, t0 + 63);
+        for (int t = t0; t <= t_end; ++t) {
+            const int slot = t - t0;
+            walk_sync<1>();  // the previous move's C bytes are visible
+            uint4 cc[NB];
+#pragma unroll
+            for (int r = 0; r < NB; ++r) cc[r] = ((const uint4 *)CB)[r];
+
+            // key d_j = 2 u_j - s_j v_j: candE_j = E + 4 (N - 1) + 4 d_j
+            const int thr = ((bestE - E) >> 2) - (N - 1);
+            int v = 0;
+#pragma unroll
+            for (int r = 0; r < NB; ++r) v = dot16(tc[r], cc[r], v);
+            const int d = 2 * u + (lane_bit(M) ? v : -v);
+            const bool admissible = tabu < t || (asp && d < thr);
+            const int key = admissible ? d : INT_MAX;
+
+            const int m = wave_min(key);
+            const uint64_t T0 = ballot(key == m);
+            const uint32_t u0 = readlane_u(dr0, slot);
+            const uint32_t u1 = readlane_u(dr1, slot);
+            uint64_t tied = T0;
+            const int count = __popc((uint32_t)T0) + __popc((uint32_t)(T0 >> 32));
+            if (count > 1) {
+                const int r = (int)below(u0, (uint32_t)count);
+                for (int i = 0; i < r; ++i) tied &= tied - 1ull;  // drop the r lowest
+            }
+            const int pick = __builtin_ctzll(tied);
+
+            const int tenure = sch.lo + (int)below(u1, (uint32_t)(sch.hi - sch.lo + 1));
+            tabu = pick == lane ? t + tenure : tabu;
+            const int sm = 1 - 2 * (int)((M >> pick) & 1ull);  // old s_pick
+            M ^= 1ull << pick;
+            E += 4 * (N - 1 + m);
+            if (E < bestE) {
+                bestE = E;
+                best = M;
+            }
+            if constexpr (TRACE) trace[t - 1] = (int16_t)pick;  // uniform store
+
+            // lag |pick - j| of row j: its other end q = 2j - pick (q = j
+            // only for j = pick; q is outside the sequence for every j >= N)
+            // s_q, or 0 outside the sequence or for j = pick
+            const int q = twoj - pick;
+            const int sq1 = __builtin_amdgcn_sbfe((int)(uint32_t)(M >> (q & 63)), 0, 1) | 1;
+            const int sq = (unsigned)q < (unsigned)N && lane != pick ? sq1 : 0;
+            u += -2 * sm * sq;  // u_j += -2 s_pick(old) s_q
+            // t_jk = s_pick(new) + s_q into row j, byte |pick - j| - 1
+            lds[absdiff_add_s((uint32_t)pick, (uint32_t)lane, rowm1)] = (uint8_t)(int8_t)(sq - sm);
+            walk_sync<1>();
+#pragma unroll
+            for (int r = 0; r < NB; ++r) tc[r] = ((const uint4 *)row)[r];
+
+            // C_k -= 2 s_pick(old) t_pick,k from row pick
+            C += -2 * sm * (int)((const int8_t *)rows)[kLagRow * pick + lane];
+            CB[lane] = (int8_t)C;
+        }
+    }
+
+    WalkResult<1> res;
+    res.best = best;
+    res.best_e = bestE;
+    res.final_e = E;
+    return res;
+}
+
 // Runs one walk of sch.T steps from mask M0 (bits >= N must be clear).
 //   NW     neighbours per lane when one wavefront runs the walk: 1 for
 //          N <= 64, 2 for N <= 128, 4 for N <= 256 (also fixes the mask
@@ -426,8 +606,8 @@ __device__ __forceinline__ void walk_sync() {
 //   trace  with TRACE: trace[t-1] = flipped index
 // Every lane of the walk's wavefronts must call this with identical uniform
 // inputs (part aside).
-template <int NW, bool TRACE = false, int SPLIT = 1, int NB = WalkLds<NW>::NBIG>
-__device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typename MaskOf<NW>::type M0,
+template <int NW, bool TRACE, int SPLIT, int NB>
+__device__ __forceinline__ WalkResult<NW> tabu_walk_records(const int N_in, const typename MaskOf<NW>::type M0,
                                                     const Schedule sch_in, const int aspiration_in,
                                                     const uint32_t k0, const uint32_t k1,
                                                     const uint32_t entity, const uint32_t gen,
@@ -435,7 +615,7 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
                                                     int16_t *__restrict__ trace,
                                                     const int part_in = 0) {
     static_assert(SPLIT == 1 || (SPLIT == 2 && NW == 2), "two wavefronts per walk need N <= 128");
-    static_assert(NW == 1 || NW == 2 || NW == 4, "mask widths of 64, 128 or 256 bits");
+    static_assert(NW == 2 || NW == 4, "record form: mask widths of 128 or 256 bits");
     static_assert(NB >= 1 && NB <= WalkLds<NW>::NBIG, "chunk count beyond the layout");
     constexpr int NS = (NB + 1) / 2;  // chunks of the shorter window (N - 1 <= 16 NB)
     using Mask = typename MaskOf<NW>::type;
@@ -533,7 +713,7 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
     for (int w = 0; w < NL; ++w) {
         const int j = lane + 64 * half(w);
         const int xr = j + 1;
-        const int xl = j < N ? N - j : 0;
+        const int xl = j < N ? N - j : N;  // j >= N: an all-zero window
         const uint8_t *right = RP + 16 * xr;
         const uint8_t *left = RQ + 16 * xl;
         const bool right_big = N - 1 - j >= j;
@@ -568,247 +748,231 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
 
     int tabu[NL];
 #pragma unroll
-    for (int w = 0; w < NL; ++w) tabu[w] = 0;
+    // lanes past the sequence are never admissible: infinite tenure, and
+    // zero windows give them d_j >= -ceil(N/2), never below the aspiration
+    // threshold (at most -(N - 1), since bestE <= E)
+    for (int w = 0; w < NL; ++w) tabu[w] = lane + 64 * half(w) < N ? 0 : INT_MAX;
     Mask best = M;
     int bestE = E;
     uint32_t dr0 = 0u, dr1 = 0u;
 
-    // Window chunks of the current pivot.  With one neighbour per lane and
-    // one wavefront they are requested one step ahead, right after the
-    // move's byte update; otherwise at the top of each step (two neighbours:
-    // the registers for early loads would cost occupancy; two wavefronts:
-    // the other one's byte update must be visible first).
-    constexpr bool kPipelineWindows = NW == 1 && SPLIT == 1;
-    // four neighbours per lane: each neighbour's chunks are read where they
-    // are used (all of them at once would not fit the register file)
+    // Window chunks of the current pivot, read at the top of each step (two
+    // neighbours: the registers for earlier loads would cost occupancy; two
+    // wavefronts: the other one's byte update must be visible first).  With
+    // four neighbours per lane each neighbour's chunks are read where they
+    // are used (all of them at once would not fit the register file).
     constexpr bool kPreload = NW != 4;
     constexpr int NLP = kPreload ? NL : 1;
     uint4 wb[NLP][NB];
     uint4 ws[NLP][NS];
-    if constexpr (kPipelineWindows) {
-        walk_sync<SPLIT>();
-#pragma unroll
-        for (int w = 0; w < NL; ++w) {
-#pragma unroll
-            for (int r = 0; r < NB; ++r) wb[w][r] = ((const uint4 *)big[w])[16 * r];
-#pragma unroll
-            for (int r = 0; r < NS; ++r) ws[w][r] = ((const uint4 *)small[w])[16 * r];
-        }
-    }
 
-    for (int t = 1; t <= sch.T; ++t) {
-        const int slot = (t - 1) & 63;
-        if (slot == 0) {
-            // draws for steps t .. t+63, one step per lane
-            const Draw4 d = philox10(entity, gen, (uint32_t)(t + lane), kTagStep, k0, k1);
+    // Steps in blocks of 64: one Philox call per lane supplies the draws of
+    // a block (read back with readlane), and the inner loop carries no
+    // refill test.
+    for (int t0 = 1; t0 <= sch.T; t0 += 64) {
+        {
+            const Draw4 d = philox10(entity, gen, (uint32_t)(t0 + lane), kTagStep, k0, k1);
             dr0 = d.w0;
             dr1 = d.w1;
         }
-        walk_sync<SPLIT>();  // the previous move's bytes are visible
-        if constexpr (!kPipelineWindows && kPreload) {
-#pragma unroll
-            for (int w = 0; w < NL; ++w) {
-#pragma unroll
-                for (int r = 0; r < NB; ++r) wb[w][r] = ((const uint4 *)big[w])[16 * r];
-#pragma unroll
-                for (int r = 0; r < NS; ++r) ws[w][r] = ((const uint4 *)small[w])[16 * r];
-            }
-        }
-
-        uint4 cc[NB];  // C_1 .. C_{16 NB} (wave-uniform)
-#pragma unroll
-        for (int r = 0; r < NB; ++r) cc[r] = ((const uint4 *)CB)[r];
-
-        // Score the neighbours this lane owns.  The key is
-        // d_j = 2 u_j - s_j v_j, so that candE_j = E + 4 (N - 1) + 4 d_j;
-        // aspiration (candE_j < bestE) is d_j < thr.  Energies are all
-        // congruent mod 4, so thr is exact.
-        const int thr = ((bestE - E) >> 2) - (N - 1);
-        // parity part (kHalfC): S_q - (N odd) s_j, q = (j + N - 1) mod 2 is
-        // the same for all of this lane's neighbours
-        const int Sq = ((lane + N - 1) & 1) ? S1 : S0;
-        int key[NL];
-#pragma unroll
-        for (int w = 0; w < NL; ++w) {
-            const int j = lane + 64 * half(w);
-            int v = 0;  // sum_k t_jk C_k (kHalfC: sum_k t_jk (C_k >> 1))
-            int u = 0;  // sum_k s_{j+k} s_{j-k}
+        const int t_end = min(sch.T, t0 + 63);
+        for (int t = t0; t <= t_end; ++t) {
+            const int slot = t - t0;
+            walk_sync<SPLIT>();  // the previous move's bytes are visible
             if constexpr (kPreload) {
 #pragma unroll
-                for (int r = 0; r < NB; ++r) {
-                    v = dot16(wb[w][r], cc[r], v);
-                    if (r < NS) {
-                        v = dot16(ws[w][r], cc[r], v);
-                        u = dot16(wb[w][r], ws[w][r], u);
-                    }
-                }
-            } else {
+                for (int w = 0; w < NL; ++w) {
 #pragma unroll
-                for (int r = 0; r < NB; ++r) {
-                    const uint4 b = ((const uint4 *)big[w])[16 * r];
-                    v = dot16(b, cc[r], v);
-                    if (r < NS) {
-                        const uint4 sm = ((const uint4 *)small[w])[16 * r];
-                        v = dot16(sm, cc[r], v);
-                        u = dot16(b, sm, u);
-                    }
+                    for (int r = 0; r < NB; ++r) wb[w][r] = ((const uint4 *)big[w])[16 * r];
+#pragma unroll
+                    for (int r = 0; r < NS; ++r) ws[w][r] = ((const uint4 *)small[w])[16 * r];
                 }
             }
-            const bool neg = lane_bit(mask_word(M, half(w)));  // s_j = -1
-            int d;
-            if constexpr (kHalfC) {
-                // v_j = 2 v + S_q - (N odd) s_j, so
-                // 2 u - s_j v_j = 2 u - s_j (2 v + S_q) + (N odd)
-                const int vq = 2 * v + Sq;
-                d = 2 * u + (neg ? vq : -vq) + (N & 1);
-            } else {
-                d = 2 * u + (neg ? v : -v);  // 2 u_j - s_j v_j
-            }
-            const bool admissible = tabu[w] < t || (aspiration && d < thr);
-            key[w] = j < N && admissible ? d : INT_MAX;
-        }
 
-        // Admissible minimum, ties broken by the step's draw: the r-th
-        // (ascending) of the tied moves, r = (u0 * count) >> 32.
-        int m;
-        uint64_t T0, T1 = 0ull, T2 = 0ull, T3 = 0ull;
-        if constexpr (SPLIT == 1) {
-            int kmin = key[0];
-            if constexpr (NW >= 2) kmin = min(kmin, key[1]);
-            if constexpr (NW == 4) kmin = min(kmin, min(key[2], key[3]));
-            m = wave_min(kmin);
-            T0 = ballot(key[0] == m);
-            if constexpr (NW >= 2) T1 = ballot(key[1] == m);
-            if constexpr (NW == 4) {
-                T2 = ballot(key[2] == m);
-                T3 = ballot(key[3] == m);
-            }
-        } else {
-            const int mine = wave_min(key[0]);
-            const uint64_t tmine = ballot(key[0] == mine);
-            XCH[3 * part] = mine;  // uniform values, every lane
-            XCH[3 * part + 1] = (int)(uint32_t)tmine;
-            XCH[3 * part + 2] = (int)(uint32_t)(tmine >> 32);
-            walk_sync<SPLIT>();
-            const int other = __builtin_amdgcn_readfirstlane(XCH[3 * (1 - part)]);
-            const uint64_t tother =
-                ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(XCH[3 * (1 - part) + 2]) << 32) |
-                (uint32_t)__builtin_amdgcn_readfirstlane(XCH[3 * (1 - part) + 1]);
-            m = min(mine, other);
-            const uint64_t a = mine == m ? tmine : 0ull;
-            const uint64_t b = other == m ? tother : 0ull;
-            T0 = part == 0 ? a : b;
-            T1 = part == 0 ? b : a;
-        }
-        const uint32_t u0 = readlane_u(dr0, slot);
-        const uint32_t u1 = readlane_u(dr1, slot);
-        int pick;
-        if constexpr (NW == 4) {
-            // the r-th tied move over the four 64-neighbour words (r = 0
-            // when only one is tied: the first word with a tied move)
-            const int c0 = __popc((uint32_t)T0) + __popc((uint32_t)(T0 >> 32));
-            const int c1 = __popc((uint32_t)T1) + __popc((uint32_t)(T1 >> 32));
-            const int c2 = __popc((uint32_t)T2) + __popc((uint32_t)(T2 >> 32));
-            const int c3 = __popc((uint32_t)T3) + __popc((uint32_t)(T3 >> 32));
-            const int count = c0 + c1 + c2 + c3;
-            int r = count > 1 ? (int)below(u0, (uint32_t)count) : 0;
-            uint64_t tied;
-            int base;
-            if (r < c0) {
-                tied = T0;
-                base = 0;
-            } else if (r < c0 + c1) {
-                tied = T1;
-                base = 64;
-                r -= c0;
-            } else if (r < c0 + c1 + c2) {
-                tied = T2;
-                base = 128;
-                r -= c0 + c1;
-            } else {
-                tied = T3;
-                base = 192;
-                r -= c0 + c1 + c2;
-            }
-            for (int i = 0; i < r; ++i) tied &= tied - 1ull;  // drop the r lowest
-            pick = base + __builtin_ctzll(tied);
-        } else {
-            uint64_t tied = T0;
-            int pick_base = 0;
-            if constexpr (NW == 2) {
-                if (T0 == 0ull) {
-                    tied = T1;
-                    pick_base = 64;
-                }
-            }
-            // several tied moves: take the r-th (counts in 32-bit halves keep
-            // the test on the scalar unit)
-            const int c0 = __popc((uint32_t)T0) + __popc((uint32_t)(T0 >> 32));
-            const int count = c0 + __popc((uint32_t)T1) + __popc((uint32_t)(T1 >> 32));
-            if (count > 1) {
-                int r = (int)below(u0, (uint32_t)count);
-                tied = T0;
-                pick_base = 0;
-                if constexpr (NW == 2) {
-                    if (r >= c0) {
-                        tied = T1;
-                        pick_base = 64;
-                        r -= c0;
+            uint4 cc[NB];  // C_1 .. C_{16 NB} (wave-uniform)
+#pragma unroll
+            for (int r = 0; r < NB; ++r) cc[r] = ((const uint4 *)CB)[r];
+
+            // Score the neighbours this lane owns.  The key is
+            // d_j = 2 u_j - s_j v_j, so that candE_j = E + 4 (N - 1) + 4 d_j;
+            // aspiration (candE_j < bestE) is d_j < thr.  Energies are all
+            // congruent mod 4, so thr is exact.
+            const int thr = ((bestE - E) >> 2) - (N - 1);
+            // parity part (kHalfC): S_q - (N odd) s_j, q = (j + N - 1) mod 2 is
+            // the same for all of this lane's neighbours
+            const int Sq = ((lane + N - 1) & 1) ? S1 : S0;
+            int key[NL];
+#pragma unroll
+            for (int w = 0; w < NL; ++w) {
+                const int j = lane + 64 * half(w);
+                int v = 0;  // sum_k t_jk C_k (kHalfC: sum_k t_jk (C_k >> 1))
+                int u = 0;  // sum_k s_{j+k} s_{j-k}
+                if constexpr (kPreload) {
+#pragma unroll
+                    for (int r = 0; r < NB; ++r) {
+                        v = dot16(wb[w][r], cc[r], v);
+                        if (r < NS) {
+                            v = dot16(ws[w][r], cc[r], v);
+                            u = dot16(wb[w][r], ws[w][r], u);
+                        }
                     }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < NB; ++r) {
+                        const uint4 b = ((const uint4 *)big[w])[16 * r];
+                        v = dot16(b, cc[r], v);
+                        if (r < NS) {
+                            const uint4 sm = ((const uint4 *)small[w])[16 * r];
+                            v = dot16(sm, cc[r], v);
+                            u = dot16(b, sm, u);
+                        }
+                    }
+                }
+                const bool neg = lane_bit(mask_word(M, half(w)));  // s_j = -1
+                int d;
+                if constexpr (kHalfC) {
+                    // v_j = 2 v + S_q - (N odd) s_j, so
+                    // 2 u - s_j v_j = 2 u - s_j (2 v + S_q) + (N odd)
+                    const int vq = 2 * v + Sq;
+                    d = 2 * u + (neg ? vq : -vq) + (N & 1);
+                } else {
+                    d = 2 * u + (neg ? v : -v);  // 2 u_j - s_j v_j
+                }
+                const bool admissible = tabu[w] < t || (aspiration && d < thr);
+                key[w] = admissible ? d : INT_MAX;
+            }
+
+            // Admissible minimum, ties broken by the step's draw: the r-th
+            // (ascending) of the tied moves, r = (u0 * count) >> 32.
+            int m;
+            uint64_t T0, T1 = 0ull, T2 = 0ull, T3 = 0ull;
+            if constexpr (SPLIT == 1) {
+                int kmin = key[0];
+                if constexpr (NW >= 2) kmin = min(kmin, key[1]);
+                if constexpr (NW == 4) kmin = min(kmin, min(key[2], key[3]));
+                m = wave_min(kmin);
+                T0 = ballot(key[0] == m);
+                if constexpr (NW >= 2) T1 = ballot(key[1] == m);
+                if constexpr (NW == 4) {
+                    T2 = ballot(key[2] == m);
+                    T3 = ballot(key[3] == m);
+                }
+            } else {
+                const int mine = wave_min(key[0]);
+                const uint64_t tmine = ballot(key[0] == mine);
+                XCH[3 * part] = mine;  // uniform values, every lane
+                XCH[3 * part + 1] = (int)(uint32_t)tmine;
+                XCH[3 * part + 2] = (int)(uint32_t)(tmine >> 32);
+                walk_sync<SPLIT>();
+                const int other = __builtin_amdgcn_readfirstlane(XCH[3 * (1 - part)]);
+                const uint64_t tother =
+                    ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(XCH[3 * (1 - part) + 2]) << 32) |
+                    (uint32_t)__builtin_amdgcn_readfirstlane(XCH[3 * (1 - part) + 1]);
+                m = min(mine, other);
+                const uint64_t a = mine == m ? tmine : 0ull;
+                const uint64_t b = other == m ? tother : 0ull;
+                T0 = part == 0 ? a : b;
+                T1 = part == 0 ? b : a;
+            }
+            const uint32_t u0 = readlane_u(dr0, slot);
+            const uint32_t u1 = readlane_u(dr1, slot);
+            int pick;
+            if constexpr (NW == 4) {
+                // the r-th tied move over the four 64-neighbour words (r = 0
+                // when only one is tied: the first word with a tied move)
+                const int c0 = __popc((uint32_t)T0) + __popc((uint32_t)(T0 >> 32));
+                const int c1 = __popc((uint32_t)T1) + __popc((uint32_t)(T1 >> 32));
+                const int c2 = __popc((uint32_t)T2) + __popc((uint32_t)(T2 >> 32));
+                const int c3 = __popc((uint32_t)T3) + __popc((uint32_t)(T3 >> 32));
+                const int count = c0 + c1 + c2 + c3;
+                int r = count > 1 ? (int)below(u0, (uint32_t)count) : 0;
+                uint64_t tied;
+                int base;
+                if (r < c0) {
+                    tied = T0;
+                    base = 0;
+                } else if (r < c0 + c1) {
+                    tied = T1;
+                    base = 64;
+                    r -= c0;
+                } else if (r < c0 + c1 + c2) {
+                    tied = T2;
+                    base = 128;
+                    r -= c0 + c1;
+                } else {
+                    tied = T3;
+                    base = 192;
+                    r -= c0 + c1 + c2;
                 }
                 for (int i = 0; i < r; ++i) tied &= tied - 1ull;  // drop the r lowest
+                pick = base + __builtin_ctzll(tied);
+            } else {
+                uint64_t tied = T0;
+                int pick_base = 0;
+                if constexpr (NW == 2) {
+                    if (T0 == 0ull) {
+                        tied = T1;
+                        pick_base = 64;
+                    }
+                }
+                // several tied moves: take the r-th (counts in 32-bit halves keep
+                // the test on the scalar unit)
+                const int c0 = __popc((uint32_t)T0) + __popc((uint32_t)(T0 >> 32));
+                const int count = c0 + __popc((uint32_t)T1) + __popc((uint32_t)(T1 >> 32));
+                if (count > 1) {
+                    int r = (int)below(u0, (uint32_t)count);
+                    tied = T0;
+                    pick_base = 0;
+                    if constexpr (NW == 2) {
+                        if (r >= c0) {
+                            tied = T1;
+                            pick_base = 64;
+                            r -= c0;
+                        }
+                    }
+                    for (int i = 0; i < r; ++i) tied &= tied - 1ull;  // drop the r lowest
+                }
+                pick = pick_base + __builtin_ctzll(tied);
             }
-            pick = pick_base + __builtin_ctzll(tied);
-        }
 
-        // Apply the move: tenure, sequence, energy, best.
-        const int tenure = sch.lo + (int)below(u1, (uint32_t)(sch.hi - sch.lo + 1));
+            // Apply the move: tenure, sequence, energy, best.
+            const int tenure = sch.lo + (int)below(u1, (uint32_t)(sch.hi - sch.lo + 1));
 #pragma unroll
-        for (int w = 0; w < NL; ++w) tabu[w] = pick == lane + 64 * half(w) ? t + tenure : tabu[w];
-        const int sm = 1 - 2 * m_bit(M, pick);  // old s_pick
-        M = m_xor(M, m_onebit(M, pick));
-        E += 4 * (N - 1 + m);
-        if constexpr (kHalfC) {
-            if (pick & 1)
-                S1 -= 2 * sm;
-            else
-                S0 -= 2 * sm;
-        }
-        if (E < bestE) {
-            bestE = E;
-            best = M;
-        }
-        if constexpr (TRACE) {
-            if (part == 0) trace[t - 1] = (int16_t)pick;  // uniform store
-        }
-
-        // New s_pick into every record and plain copy that holds it; then
-        // the next step's window chunks are requested at once.
-        if (updater) RP[upd_a + upd_b * pick] = (uint8_t)(int8_t)(-sm);
-        if constexpr (kPipelineWindows) {
-            wave_sync();
-#pragma unroll
-            for (int w = 0; w < NL; ++w) {
-#pragma unroll
-                for (int r = 0; r < NB; ++r) wb[w][r] = ((const uint4 *)big[w])[16 * r];
-#pragma unroll
-                for (int r = 0; r < NS; ++r) ws[w][r] = ((const uint4 *)small[w])[16 * r];
+            for (int w = 0; w < NL; ++w) tabu[w] = pick == lane + 64 * half(w) ? t + tenure : tabu[w];
+            const int sm = 1 - 2 * m_bit(M, pick);  // old s_pick
+            M = m_xor(M, m_onebit(M, pick));
+            E += 4 * (N - 1 + m);
+            if constexpr (kHalfC) {
+                if (pick & 1)
+                    S1 -= 2 * sm;
+                else
+                    S0 -= 2 * sm;
             }
-        }
+            if (E < bestE) {
+                bestE = E;
+                best = M;
+            }
+            if constexpr (TRACE) {
+                if (part == 0) trace[t - 1] = (int16_t)pick;  // uniform store
+            }
 
-        // C_k -= 2 s_pick t_pick,k for every lag (lane-parallel):
-        // s_{pick+k} = P[pick+k] and s_{pick-k} = Q[N-1-pick+k] are bytes of
-        // the plain copies, zero past the ends (position pick itself is not
-        // read, so the other wavefront's byte update cannot race with it).
-        {
-            const int k2 = -2 * sm;
+            // New s_pick into every record and plain copy that holds it.
+            if (updater) RP[upd_a + upd_b * pick] = (uint8_t)(int8_t)(-sm);
+
+            // C_k -= 2 s_pick t_pick,k for every lag (lane-parallel):
+            // s_{pick+k} = P[pick+k] and s_{pick-k} = Q[N-1-pick+k] are bytes of
+            // the plain copies, zero past the ends (position pick itself is not
+            // read, so the other wavefront's byte update cannot race with it).
+            {
+                const int k2 = -2 * sm;
 #pragma unroll
-            for (int w = 0; w < NL; ++w) {
-                const int k = lane + 1 + 64 * half(w);
-                const int t_k = (int)((const int8_t *)PP)[pick + k] +
-                                (int)((const int8_t *)PQ)[N - 1 - pick + k];
-                C[w] += k2 * t_k;
-                CB[k - 1] = (int8_t)(kHalfC ? C[w] >> 1 : C[w]);
+                for (int w = 0; w < NL; ++w) {
+                    const int k = lane + 1 + 64 * half(w);
+                    const int t_k = (int)((const int8_t *)PP)[pick + k] +
+                                    (int)((const int8_t *)PQ)[N - 1 - pick + k];
+                    C[w] += k2 * t_k;
+                    CB[k - 1] = (int8_t)(kHalfC ? C[w] >> 1 : C[w]);
+                }
             }
         }
     }
@@ -818,6 +982,27 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in, const typena
     res.best_e = bestE;
     res.final_e = E;
     return res;
+}
+
+// Runs one walk of sch.T steps from mask M0 (bits >= N must be clear): the
+// lag form for N <= 64, the record form beyond (arguments as above).
+template <int NW, bool TRACE = false, int SPLIT = 1, int NB = WalkLds<NW>::NBIG>
+__device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in,
+                                                    const typename MaskOf<NW>::type M0,
+                                                    const Schedule sch_in, const int aspiration_in,
+                                                    const uint32_t k0, const uint32_t k1,
+                                                    const uint32_t entity, const uint32_t gen,
+                                                    uint8_t *__restrict__ lds,
+                                                    int16_t *__restrict__ trace,
+                                                    const int part_in = 0) {
+    if constexpr (NW == 1) {
+        static_assert(SPLIT == 1, "N <= 64 runs on one wavefront");
+        return tabu_walk_lags<TRACE, NB>(N_in, M0, sch_in, aspiration_in, k0, k1, entity, gen, lds,
+                                         trace);
+    } else {
+        return tabu_walk_records<NW, TRACE, SPLIT, NB>(N_in, M0, sch_in, aspiration_in, k0, k1,
+                                                       entity, gen, lds, trace, part_in);
+    }
 }
 
 }  // namespace liblabs
