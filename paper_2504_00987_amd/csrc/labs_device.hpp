@@ -746,12 +746,26 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_records(const int N_in, cons
     }
     const bool updater = part == 0 && lane < 34;
 
-    int tabu[NL];
-#pragma unroll
     // lanes past the sequence are never admissible: infinite tenure, and
     // zero windows give them d_j >= -ceil(N/2), never below the aspiration
     // threshold (at most -(N - 1), since bestE <= E)
+    int tabu[NL];
+#pragma unroll
     for (int w = 0; w < NL; ++w) tabu[w] = lane + 64 * half(w) < N ? 0 : INT_MAX;
+
+    // u_j = sum_{k <= min(j, N-1-j)} s_{j+k} s_{j-k}: from the windows once,
+    // then per move (a move at p changes only the term with k = |p - j|,
+    // whose other end is q = 2j - p, by -2 s_p(old) s_q)
+    int uj[NL];
+    walk_sync<SPLIT>();
+#pragma unroll
+    for (int w = 0; w < NL; ++w) {
+        int a = 0;
+#pragma unroll
+        for (int r = 0; r < NS; ++r)
+            a = dot16(((const uint4 *)big[w])[16 * r], ((const uint4 *)small[w])[16 * r], a);
+        uj[w] = a;
+    }
     Mask best = M;
     int bestE = E;
     uint32_t dr0 = 0u, dr1 = 0u;
@@ -806,26 +820,18 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_records(const int N_in, cons
             for (int w = 0; w < NL; ++w) {
                 const int j = lane + 64 * half(w);
                 int v = 0;  // sum_k t_jk C_k (kHalfC: sum_k t_jk (C_k >> 1))
-                int u = 0;  // sum_k s_{j+k} s_{j-k}
+                const int u = uj[w];
                 if constexpr (kPreload) {
 #pragma unroll
                     for (int r = 0; r < NB; ++r) {
                         v = dot16(wb[w][r], cc[r], v);
-                        if (r < NS) {
-                            v = dot16(ws[w][r], cc[r], v);
-                            u = dot16(wb[w][r], ws[w][r], u);
-                        }
+                        if (r < NS) v = dot16(ws[w][r], cc[r], v);
                     }
                 } else {
 #pragma unroll
                     for (int r = 0; r < NB; ++r) {
-                        const uint4 b = ((const uint4 *)big[w])[16 * r];
-                        v = dot16(b, cc[r], v);
-                        if (r < NS) {
-                            const uint4 sm = ((const uint4 *)small[w])[16 * r];
-                            v = dot16(sm, cc[r], v);
-                            u = dot16(b, sm, u);
-                        }
+                        v = dot16(((const uint4 *)big[w])[16 * r], cc[r], v);
+                        if (r < NS) v = dot16(((const uint4 *)small[w])[16 * r], cc[r], v);
                     }
                 }
                 const bool neg = lane_bit(mask_word(M, half(w)));  // s_j = -1
@@ -973,6 +979,17 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_records(const int N_in, cons
                     C[w] += k2 * t_k;
                     CB[k - 1] = (int8_t)(kHalfC ? C[w] >> 1 : C[w]);
                 }
+            }
+
+            // u_j += -2 s_pick(old) s_q with s_q = P[q], q = 2j - pick (zero
+            // past the end; q < 0 and j = pick contribute nothing; P[pick]
+            // itself is never used, so the byte update cannot race with it)
+#pragma unroll
+            for (int w = 0; w < NL; ++w) {
+                const int jw = lane + 64 * half(w);
+                const int q = 2 * jw - pick;
+                const int sq = (int)((const int8_t *)PP)[q & (Cfg::LEN - 1)];
+                uj[w] += q >= 0 && jw != pick ? -2 * sm * sq : 0;
             }
         }
     }
