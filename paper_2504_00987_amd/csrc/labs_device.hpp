@@ -381,19 +381,31 @@ constexpr int kSpareRecords = 15;
 // CB[k-1] = C_k as int8.  The byte before each row is spare, so the update
 // write of the lane whose neighbour was flipped (lag 0) lands there; rows
 // j >= N are never read as neighbour data and take stray writes.
-constexpr int kLagRow = 80;
-constexpr int kLagBase = 16;
-constexpr int kLagBytes = kLagBase + 64 * kLagRow + 64;
+// (N <= 128: 64 NW rows of 64 NW + 16 bytes, C as 64 NW bytes.)
+template <int NW>
+struct LagLds {
+    static constexpr int ROW = 64 * NW + 16, BASE = 16;
+    static constexpr int BYTES = BASE + 64 * NW * ROW + 64 * NW;
+};
 
 template <int NW>
-constexpr int walk_lds_bytes() {
-    if constexpr (NW == 1)
-        return kLagBytes;
-    else
-        return 2 * 16 * (kSpareRecords + WalkLds<NW>::NREC) + 2 * WalkLds<NW>::LEN +
-               WalkLds<NW>::CLEN + 32;  // + the two-wavefront exchange words
+constexpr int record_lds_bytes() {
+    return 2 * 16 * (kSpareRecords + WalkLds<NW>::NREC) + 2 * WalkLds<NW>::LEN +
+           WalkLds<NW>::CLEN + 32;  // + the two-wavefront exchange words
 }
 
+// LDS bytes of one walk: the lag form (LAG, N <= 128) or the record form.
+// The lag form always serves N <= 64; for 64 < N <= 128 its 18 KB per walk
+// halve the walks a CU holds, so only kernels whose occupancy is fixed by
+// other means (batched memetic generations) choose it.
+template <int NW, bool LAG = (NW == 1)>
+constexpr int walk_lds_bytes() {
+    static_assert(!LAG || NW <= 2, "the lag form covers N <= 128");
+    if constexpr (LAG)
+        return LagLds<NW>::BYTES;
+    else
+        return record_lds_bytes<NW>();
+}
 // Lane l receives bit l of a wave-uniform 64-bit mask.
 __device__ __forceinline__ bool lane_bit(uint64_t mask) {
     return __builtin_amdgcn_inverse_ballot_w64(mask);
@@ -454,24 +466,29 @@ __device__ __forceinline__ void walk_sync() {
         __syncthreads();
 }
 
-// One walk of N <= 64 in the lag form (one wavefront, lane j owning
-// neighbour j and lag k = j + 1).  Neighbour j's sums are
+// One walk of N <= 64 NW (NW = 1 or 2) in the lag form on one wavefront,
+// lane l owning neighbours j = l + 64h and lags k = j + 1 (h < NW).
+// Neighbour j's sums are
 //   v_j = sum_k t_jk C_k   (NB chunk dot products of its row against C),
-//   u_j = sum_{k <= min(j, N-1-j)} s_{j+k} s_{j-k}   (kept per lane),
+//   u_j = sum_{k <= min(j, N-1-j)} s_{j+k} s_{j-k}   (kept per neighbour),
 // since sum_k t_jk^2 = N - 1 + 2 u_j.  A move at p changes, for each j != p,
 // only the lag k = |p - j| of row j: the other end of that pair is
 // q = 2j - p, so t_jk becomes s_p + s_q (s_q = 0 outside the sequence) and
 // u_j changes by -2 s_p(old) s_q when q is inside; C_k changes by
 // -2 s_p(old) t_pk, read from row p, which the move leaves unchanged.
-template <bool TRACE, int NB>
-__device__ __forceinline__ WalkResult<1> tabu_walk_lags(const int N_in, const uint64_t M0,
-                                                        const Schedule sch_in,
-                                                        const int aspiration_in,
-                                                        const uint32_t k0, const uint32_t k1,
-                                                        const uint32_t entity, const uint32_t gen,
-                                                        uint8_t *__restrict__ lds,
-                                                        int16_t *__restrict__ trace) {
-    static_assert(NB >= 1 && NB <= 4, "N <= 64 needs at most four 16-lag chunks");
+template <int NW, bool TRACE, int NB>
+__device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
+                                                         const typename MaskOf<NW>::type M0,
+                                                         const Schedule sch_in,
+                                                         const int aspiration_in,
+                                                         const uint32_t k0, const uint32_t k1,
+                                                         const uint32_t entity, const uint32_t gen,
+                                                         uint8_t *__restrict__ lds,
+                                                         int16_t *__restrict__ trace) {
+    static_assert(NW == 1 || NW == 2, "lag form: N <= 128");
+    static_assert(NB >= 1 && NB <= 4 * NW, "N <= 64 NW needs at most 4 NW 16-lag chunks");
+    using Mask = typename MaskOf<NW>::type;
+    constexpr int ROW = LagLds<NW>::ROW;
     const int lane = lane_id();
     const int N = __builtin_amdgcn_readfirstlane(N_in);
     const int aspiration = __builtin_amdgcn_readfirstlane(aspiration_in);
@@ -479,49 +496,66 @@ __device__ __forceinline__ WalkResult<1> tabu_walk_lags(const int N_in, const ui
     sch.T = __builtin_amdgcn_readfirstlane(sch_in.T);
     sch.lo = __builtin_amdgcn_readfirstlane(sch_in.lo);
     sch.hi = __builtin_amdgcn_readfirstlane(sch_in.hi);
-    uint64_t M = uniform64(M0);
+    Mask M = make_mask<NW>(uniform64(mask_word(M0, 0)), uniform64(mask_word(M0, 1)));
     // bit i of Mr is bit N-1-i of M
-    const uint64_t Mr = ballot(lane < N && ((M >> (N - 1 - lane)) & 1ull));
+    Mask Mr;
+    {
+        uint64_t r[2] = {0ull, 0ull};
+#pragma unroll
+        for (int h = 0; h < NW; ++h) {
+            const int i = lane + 64 * h;
+            r[h] = ballot(i < N && m_bit(M, N - 1 - i));
+        }
+        Mr = make_mask<NW>(r[0], r[1]);
+    }
 
-    uint8_t *const rows = lds + kLagBase;
-    uint8_t *const row = rows + kLagRow * lane;
-    int8_t *const CB = (int8_t *)(rows + 64 * kLagRow);
+    uint8_t *const rows = lds + LagLds<NW>::BASE;
+    int8_t *const CB = (int8_t *)(rows + 64 * NW * ROW);
 
     // Row j: s_{j+k} is bit k-1 of R = M >> (j+1) (valid below N-1-j),
     // s_{j-k} bit k-1 of L = Mr >> (N-j) (valid below j).
-    const int j = lane;
-    const int nr = max(N - 1 - j, 0), nl = j < N ? j : 0;
-    const uint64_t R = (M >> j) >> 1;
-    const uint64_t L = j < N ? (Mr >> (N - 1 - j)) >> 1 : 0ull;
+    int u[NW], C[NW], tabu[NW];
+    bool asp[NW];
+    uint32_t rowm1[NW];  // row j's byte k-1 is lds[rowm1 + k] (k = 0: the spare byte before it)
+    int sq_e = 0;        // sum of C_k^2 over this lane's lags
     walk_sync<1>();
 #pragma unroll
-    for (int d = 0; d < 16; ++d)
-        ((uint32_t *)row)[d] = add_bytes(pack_bits4(R, 4 * d, nr), pack_bits4(L, 4 * d, nl));
-    const int nu = min(nr, nl);
-    int u = nu - 2 * __popcll((R ^ L) & ((1ull << nu) - 1ull));
-
-    // C_k of this lane's lag (Eq. 1), its int8 mirror, the energy.
-    const int k = lane + 1;
-    int C = k < N ? lag_corr(M, N, k) : 0;
-    CB[lane] = (int8_t)C;
-    int E = wave_sum(C * C);
-
-    // lanes past the sequence are never admissible: infinite tenure and no
-    // aspiration
-    int tabu = lane < N ? 0 : INT_MAX;
-    const bool asp = aspiration && lane < N;
-    uint64_t best = M;
+    for (int h = 0; h < NW; ++h) {
+        const int j = lane + 64 * h;
+        const int nr = max(N - 1 - j, 0), nl = j < N ? j : 0;
+        const Mask R = m_shr(m_shr(M, j), 1);
+        const Mask L = j < N ? m_shr(m_shr(Mr, N - 1 - j), 1) : make_mask<NW>(0ull, 0ull);
+        uint32_t *const row = (uint32_t *)(rows + ROW * j);
+#pragma unroll
+        for (int d = 0; d < 16 * NW; ++d) {
+            const int x = 4 * d;  // a nibble never straddles two words
+            row[d] = add_bytes(pack_bits4(mask_word(R, x >> 6), x & 63, nr - (x & ~63)),
+                               pack_bits4(mask_word(L, x >> 6), x & 63, nl - (x & ~63)));
+        }
+        const int nu = min(nr, nl);
+        u[h] = nu - 2 * m_popc(m_and(m_xor(R, L), m_low(R, nu)));
+        // C_k of this lane's lag (Eq. 1) and its int8 mirror
+        const int k = j + 1;
+        C[h] = k < N ? lag_corr(M, N, k) : 0;
+        CB[k - 1] = (int8_t)C[h];
+        sq_e += C[h] * C[h];
+        // lanes past the sequence are never admissible: infinite tenure
+        // and no aspiration
+        tabu[h] = j < N ? 0 : INT_MAX;
+        asp[h] = aspiration && j < N;
+        rowm1[h] = (uint32_t)(LagLds<NW>::BASE + ROW * j - 1);
+    }
+    int E = wave_sum(sq_e);
+    Mask best = M;
     int bestE = E;
     uint32_t dr0 = 0u, dr1 = 0u;
-    const int twoj = 2 * j;
-    // row j's byte k-1 is lds[rowm1 + k] (k = 0: the spare byte before the
-    // row)
-    const uint32_t rowm1 = (uint32_t)(kLagBase + kLagRow * lane - 1);
 
-    uint4 tc[NB];
+    uint4 tc[NW][NB];
     walk_sync<1>();
 #pragma unroll
-    for (int r = 0; r < NB; ++r) tc[r] = ((const uint4 *)row)[r];
+    for (int h = 0; h < NW; ++h)
+#pragma unroll
+        for (int r = 0; r < NB; ++r) tc[h][r] = ((const uint4 *)(rows + ROW * (lane + 64 * h)))[r];
 
     for (int t0 = 1; t0 <= sch.T; t0 += 64) {
         {
@@ -539,29 +573,56 @@ __device__ __forceinline__ WalkResult<1> tabu_walk_lags(const int N_in, const ui
 
             // key d_j = 2 u_j - s_j v_j: candE_j = E + 4 (N - 1) + 4 d_j
             const int thr = ((bestE - E) >> 2) - (N - 1);
-            int v = 0;
+            int key[NW];
 #pragma unroll
-            for (int r = 0; r < NB; ++r) v = dot16(tc[r], cc[r], v);
-            const int d = 2 * u + (lane_bit(M) ? v : -v);
-            const bool admissible = tabu < t || (asp && d < thr);
-            const int key = admissible ? d : INT_MAX;
-
-            const int m = wave_min(key);
-            const uint64_t T0 = ballot(key == m);
+            for (int h = 0; h < NW; ++h) {
+                int v = 0;
+#pragma unroll
+                for (int r = 0; r < NB; ++r) v = dot16(tc[h][r], cc[r], v);
+                const int d = 2 * u[h] + (lane_bit(mask_word(M, h)) ? v : -v);
+                const bool admissible = tabu[h] < t || (asp[h] && d < thr);
+                key[h] = admissible ? d : INT_MAX;
+            }
+            int kmin = key[0];
+            if constexpr (NW == 2) kmin = min(kmin, key[1]);
+            const int m = wave_min(kmin);
+            const uint64_t T0 = ballot(key[0] == m);
+            uint64_t T1 = 0ull;
+            if constexpr (NW == 2) T1 = ballot(key[1] == m);
             const uint32_t u0 = readlane_u(dr0, slot);
             const uint32_t u1 = readlane_u(dr1, slot);
             uint64_t tied = T0;
-            const int count = __popc((uint32_t)T0) + __popc((uint32_t)(T0 >> 32));
+            int pick_base = 0;
+            if constexpr (NW == 2) {
+                if (T0 == 0ull) {
+                    tied = T1;
+                    pick_base = 64;
+                }
+            }
+            // several tied moves: take the r-th (counts in 32-bit halves keep
+            // the test on the scalar unit)
+            const int c0 = __popc((uint32_t)T0) + __popc((uint32_t)(T0 >> 32));
+            const int count = c0 + __popc((uint32_t)T1) + __popc((uint32_t)(T1 >> 32));
             if (count > 1) {
-                const int r = (int)below(u0, (uint32_t)count);
+                int r = (int)below(u0, (uint32_t)count);
+                tied = T0;
+                pick_base = 0;
+                if constexpr (NW == 2) {
+                    if (r >= c0) {
+                        tied = T1;
+                        pick_base = 64;
+                        r -= c0;
+                    }
+                }
                 for (int i = 0; i < r; ++i) tied &= tied - 1ull;  // drop the r lowest
             }
-            const int pick = __builtin_ctzll(tied);
+            const int pick = pick_base + __builtin_ctzll(tied);
 
             const int tenure = sch.lo + (int)below(u1, (uint32_t)(sch.hi - sch.lo + 1));
-            tabu = pick == lane ? t + tenure : tabu;
-            const int sm = 1 - 2 * (int)((M >> pick) & 1ull);  // old s_pick
-            M ^= 1ull << pick;
+#pragma unroll
+            for (int h = 0; h < NW; ++h) tabu[h] = pick == lane + 64 * h ? t + tenure : tabu[h];
+            const int sm = 1 - 2 * m_bit(M, pick);  // old s_pick
+            M = m_xor(M, m_onebit(M, pick));
             E += 4 * (N - 1 + m);
             if (E < bestE) {
                 bestE = E;
@@ -569,26 +630,41 @@ __device__ __forceinline__ WalkResult<1> tabu_walk_lags(const int N_in, const ui
             }
             if constexpr (TRACE) trace[t - 1] = (int16_t)pick;  // uniform store
 
-            // lag |pick - j| of row j: its other end q = 2j - pick (q = j
-            // only for j = pick; q is outside the sequence for every j >= N)
-            // s_q, or 0 outside the sequence or for j = pick
-            const int q = twoj - pick;
-            const int sq1 = __builtin_amdgcn_sbfe((int)(uint32_t)(M >> (q & 63)), 0, 1) | 1;
-            const int sq = (unsigned)q < (unsigned)N && lane != pick ? sq1 : 0;
-            u += -2 * sm * sq;  // u_j += -2 s_pick(old) s_q
-            // t_jk = s_pick(new) + s_q into row j, byte |pick - j| - 1
-            lds[absdiff_add_s((uint32_t)pick, (uint32_t)lane, rowm1)] = (uint8_t)(int8_t)(sq - sm);
+#pragma unroll
+            for (int h = 0; h < NW; ++h) {
+                // lag |pick - j| of row j: its other end q = 2j - pick (q = j
+                // only for j = pick; q is outside the sequence for j >= N);
+                // s_q, or 0 outside the sequence or for j = pick
+                const int j = lane + 64 * h;
+                const int q = 2 * j - pick;
+                int sq1;
+                if constexpr (NW == 1)
+                    sq1 = __builtin_amdgcn_sbfe((int)(uint32_t)(mask_word(M, 0) >> (q & 63)), 0, 1) | 1;
+                else
+                    sq1 = 1 - 2 * m_bit(M, q & 127);
+                const int sq = (unsigned)q < (unsigned)N && j != pick ? sq1 : 0;
+                u[h] += -2 * sm * sq;  // u_j += -2 s_pick(old) s_q
+                // t_jk = s_pick(new) + s_q into row j, byte |pick - j| - 1
+                lds[absdiff_add_s((uint32_t)pick, (uint32_t)j, rowm1[h])] = (uint8_t)(int8_t)(sq - sm);
+            }
             walk_sync<1>();
 #pragma unroll
-            for (int r = 0; r < NB; ++r) tc[r] = ((const uint4 *)row)[r];
+            for (int h = 0; h < NW; ++h)
+#pragma unroll
+                for (int r = 0; r < NB; ++r)
+                    tc[h][r] = ((const uint4 *)(rows + ROW * (lane + 64 * h)))[r];
 
             // C_k -= 2 s_pick(old) t_pick,k from row pick
-            C += -2 * sm * (int)((const int8_t *)rows)[kLagRow * pick + lane];
-            CB[lane] = (int8_t)C;
+#pragma unroll
+            for (int h = 0; h < NW; ++h) {
+                const int k = lane + 1 + 64 * h;
+                C[h] += -2 * sm * (int)((const int8_t *)rows)[ROW * pick + k - 1];
+                CB[k - 1] = (int8_t)C[h];
+            }
         }
     }
 
-    WalkResult<1> res;
+    WalkResult<NW> res;
     res.best = best;
     res.best_e = bestE;
     res.final_e = E;
@@ -1002,8 +1078,10 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_records(const int N_in, cons
 }
 
 // Runs one walk of sch.T steps from mask M0 (bits >= N must be clear): the
-// lag form for N <= 64, the record form beyond (arguments as above).
-template <int NW, bool TRACE = false, int SPLIT = 1, int NB = WalkLds<NW>::NBIG>
+// lag form when LAG (N <= 128, one wavefront), the record form otherwise
+// (arguments as above; lds holds walk_lds_bytes<NW, LAG>() bytes).
+template <int NW, bool TRACE = false, int SPLIT = 1, int NB = WalkLds<NW>::NBIG,
+          bool LAG = (NW == 1)>
 __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in,
                                                     const typename MaskOf<NW>::type M0,
                                                     const Schedule sch_in, const int aspiration_in,
@@ -1012,10 +1090,10 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in,
                                                     uint8_t *__restrict__ lds,
                                                     int16_t *__restrict__ trace,
                                                     const int part_in = 0) {
-    if constexpr (NW == 1) {
-        static_assert(SPLIT == 1, "N <= 64 runs on one wavefront");
-        return tabu_walk_lags<TRACE, NB>(N_in, M0, sch_in, aspiration_in, k0, k1, entity, gen, lds,
-                                         trace);
+    if constexpr (LAG) {
+        static_assert(NW <= 2 && SPLIT == 1, "the lag form: N <= 128 on one wavefront");
+        return tabu_walk_lags<NW, TRACE, NB>(N_in, M0, sch_in, aspiration_in, k0, k1, entity, gen,
+                                             lds, trace);
     } else {
         return tabu_walk_records<NW, TRACE, SPLIT, NB>(N_in, M0, sch_in, aspiration_in, k0, k1,
                                                        entity, gen, lds, trace, part_in);

@@ -218,7 +218,11 @@ __attribute__((amdgpu_waves_per_eu(1, SPLIT == 2 ? 2 : 8))) void memetic_advance
 // holds identically, so every wavefront reaches every barrier.
 // Dynamic LDS: population [kMaxK][NW] words, energies [kMaxK], per child
 // kResWords words (mask, energy, replaced slot), then the B walk scratches.
+// Children walk in the lag form up to N = 128: a replica's workgroup of B
+// wavefronts occupies its CU whatever the LDS per walk.
 constexpr int kResWords = 8;
+template <int NW>
+constexpr bool kBatchedLag = NW <= 2;
 template <int NW>
 constexpr int batched_header() {
     return kMaxK * 8 * NW + kMaxK * 4 + kMaxChildren * kResWords * 8;
@@ -238,7 +242,7 @@ __global__ __launch_bounds__(64 * kMaxChildren) void memetic_batched_kernel(
     if (sl.state < 0 || (1 << memetic_class(sl.n)) != NW) return;
     const int B = a.children;
     const int b = (int)(threadIdx.x >> 6);
-    uint8_t *lds = dyn_lds + batched_header<NW>() + b * walk_lds_bytes<NW>();
+    uint8_t *lds = dyn_lds + batched_header<NW>() + b * walk_lds_bytes<NW, kBatchedLag<NW>>();
     const int N = sl.n, K = a.K, st = sl.state;
     const int64_t base = (int64_t)st * K;
     for (int i = (int)threadIdx.x; i < K; i += 64 * B) {
@@ -283,8 +287,8 @@ __global__ __launch_bounds__(64 * kMaxChildren) void memetic_batched_kernel(
         child = m_xor(child, mutation_mask<NW>(sl, gg, (uint32_t)(64 * b), thr));
         const uint32_t wgen = (uint32_t)(g * B + b);
         const Schedule sch = make_schedule(a.rule, N, sl.k0, sl.k1, sl.pop_id, wgen);
-        const WalkResult<NW> r = tabu_walk<NW>(N, child, sch, a.rule.aspiration, sl.k0, sl.k1,
-                                               sl.pop_id, wgen, lds, nullptr);
+        const WalkResult<NW> r = tabu_walk<NW, false, 1, WalkLds<NW>::NBIG, kBatchedLag<NW>>(
+            N, child, sch, a.rule.aspiration, sl.k0, sl.k1, sl.pop_id, wgen, lds, nullptr);
         uint64_t *mine = res + kResWords * b;
         store_mask<NW>(mine, r.best);  // uniform values, every lane of wavefront b
         mine[4] = (uint64_t)(uint32_t)r.best_e;
@@ -362,7 +366,7 @@ namespace {
 // population plus B walk scratches.
 template <int NW>
 constexpr size_t batched_lds_bytes(int children) {
-    return batched_header<NW>() + (size_t)children * walk_lds_bytes<NW>();
+    return batched_header<NW>() + (size_t)children * walk_lds_bytes<NW, kBatchedLag<NW>>();
 }
 
 template <int NW>
