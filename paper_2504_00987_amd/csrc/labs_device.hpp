@@ -1,27 +1,31 @@
 // Device building blocks of liblabs (gfx950): counter-based RNG, wavefront
-// primitives, 128-bit sequence masks and the tabu walk.
+// primitives, sequence masks of up to 256 bits and the tabu walk.
 //
 // One tabu walk (Alg. 2 / Alg. 4 of arXiv:2504.00987) runs on one 64-lane
-// wavefront.  The sequence is a wave-uniform bit mask (bit i set <=> s_i = -1)
-// held in scalar registers; lane l owns neighbour j = l (and j = l + 64 when
-// N > 64) and lag k = l + 1 (and k = l + 65).  The score of neighbour j is
+// wavefront (or two, for N <= 128 when few walks share the device).  The
+// sequence is a wave-uniform bit mask (bit i set <=> s_i = -1) held in
+// scalar registers; lane l owns neighbours j = l + 64h and lags k = j + 1.
+// The score of neighbour j is
 //
 //     dE_j = 4 * ( sum_k t_jk^2  -  s_j * sum_k t_jk C_k ),
 //     t_jk = s_{j+k} + s_{j-k}   (terms outside the sequence are 0),
 //
-// (flipping s_j changes C_k of Eq. 1 by -2 s_j t_jk).  The sequence lives in
-// LDS twice as int8 +-1 with zeros past its ends -- forwards (P) and reversed
-// (Q) -- as 16-byte records, record x holding bytes x .. x+15, so that every
-// lane's right window s_{j+1..} and left window s_{j-1..} (reversed) is a
-// run of aligned 16-byte reads.  C_k is kept per lane in registers and mirrored in
-// LDS as int8 (|C_k| <= N-k <= 127).  A neighbour's sums are then packed
-// 4-way int8 dot products of 16-byte window chunks against C chunks:
-// sum_k t_jk C_k = <right, C> + <left, C>, sum_k s_{j+k} s_{j-k} =
-// <right, left> over the shorter window.  Each neighbour reads its longer
-// window over the full lag range and its shorter one over half of it.  After
-// a move, C_k is updated lane-parallel (the paper's O(N) update of one "row
-// and column", Sec. III.C) and one byte per record is rewritten.  All
-// arithmetic is exact int32.
+// (flipping s_j changes C_k of Eq. 1 by -2 s_j t_jk), and sum_k t_jk^2 is
+// N - 1 + 2 u_j with u_j = sum_k s_{j+k} s_{j-k}, which each lane keeps per
+// neighbour: a move changes one of its terms.  sum_k t_jk C_k is a run of
+// packed 4-way int8 dot products against C_k mirrored in LDS as int8 (as
+// C_k >> 1 for N > 128, the parity part added from two wave-uniform sums).
+// Two LDS layouts hold the t_jk:
+//   lag form     row j holds t_j1 .. t_j64 (t_j128) as int8; a move rewrites
+//                one byte per row (N <= 64, and N <= 128 where occupancy
+//                does not depend on LDS);
+//   record form  the sequence forwards (P) and reversed (Q) as 16-byte
+//                records, record x holding bytes x .. x+15, so that every
+//                lane's right window s_{j+1..} and left window s_{j-1..} is a
+//                run of aligned 16-byte reads; a move rewrites one byte in
+//                each of the 16 records that hold s_pick.
+// After a move, C_k is updated lane-parallel (the paper's O(N) update of one
+// "row and column", Sec. III.C).  All arithmetic is exact int32.
 #pragma once
 
 #include <hip/hip_runtime.h>
