@@ -385,11 +385,14 @@ constexpr int kSpareRecords = 15;
 // CB[k-1] = C_k as int8.  The byte before each row is spare, so the update
 // write of the lane whose neighbour was flipped (lag 0) lands there; rows
 // j >= N are never read as neighbour data and take stray writes.
-// (N <= 128: 64 NW rows of 64 NW + 16 bytes, C as 64 NW bytes.)
+// (N <= 128: 64 NW rows of 64 NW + 16 bytes, C as 64 NW bytes, and six
+// words through which the two wavefronts of a split walk exchange their
+// minima.)
 template <int NW>
 struct LagLds {
     static constexpr int ROW = 64 * NW + 16, BASE = 16;
-    static constexpr int BYTES = BASE + 64 * NW * ROW + 64 * NW;
+    static constexpr int XCH = BASE + 64 * NW * ROW + 64 * NW;
+    static constexpr int BYTES = XCH + 32;
 };
 
 template <int NW>
@@ -480,7 +483,7 @@ __device__ __forceinline__ void walk_sync() {
 // q = 2j - p, so t_jk becomes s_p + s_q (s_q = 0 outside the sequence) and
 // u_j changes by -2 s_p(old) s_q when q is inside; C_k changes by
 // -2 s_p(old) t_pk, read from row p, which the move leaves unchanged.
-template <int NW, bool TRACE, int NB>
+template <int NW, bool TRACE, int NB, int SPLIT = 1>
 __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
                                                          const typename MaskOf<NW>::type M0,
                                                          const Schedule sch_in,
@@ -488,12 +491,18 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
                                                          const uint32_t k0, const uint32_t k1,
                                                          const uint32_t entity, const uint32_t gen,
                                                          uint8_t *__restrict__ lds,
-                                                         int16_t *__restrict__ trace) {
+                                                         int16_t *__restrict__ trace,
+                                                         const int part_in = 0) {
     static_assert(NW == 1 || NW == 2, "lag form: N <= 128");
+    static_assert(SPLIT == 1 || (SPLIT == 2 && NW == 2), "two wavefronts per walk need N <= 128");
     static_assert(NB >= 1 && NB <= 4 * NW, "N <= 64 NW needs at most 4 NW 16-lag chunks");
     using Mask = typename MaskOf<NW>::type;
     constexpr int ROW = LagLds<NW>::ROW;
+    constexpr int NL = NW / SPLIT;  // neighbours per lane
     const int lane = lane_id();
+    const int part = SPLIT == 1 ? 0 : __builtin_amdgcn_readfirstlane(part_in);
+    // register h of a lane holds neighbour j = lane + 64 half(h)
+    auto half = [&](int h) { return SPLIT == 1 ? h : part; };
     const int N = __builtin_amdgcn_readfirstlane(N_in);
     const int aspiration = __builtin_amdgcn_readfirstlane(aspiration_in);
     Schedule sch;
@@ -515,17 +524,18 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
 
     uint8_t *const rows = lds + LagLds<NW>::BASE;
     int8_t *const CB = (int8_t *)(rows + 64 * NW * ROW);
+    int *const XCH = (int *)(lds + LagLds<NW>::XCH);  // SPLIT: [part][min, tie lo, tie hi]
 
     // Row j: s_{j+k} is bit k-1 of R = M >> (j+1) (valid below N-1-j),
     // s_{j-k} bit k-1 of L = Mr >> (N-j) (valid below j).
-    int u[NW], C[NW], tabu[NW];
-    bool asp[NW];
-    uint32_t rowm1[NW];  // row j's byte k-1 is lds[rowm1 + k] (k = 0: the spare byte before it)
+    int u[NL], C[NL], tabu[NL];
+    bool asp[NL];
+    uint32_t rowm1[NL];  // row j's byte k-1 is lds[rowm1 + k] (k = 0: the spare byte before it)
     int sq_e = 0;        // sum of C_k^2 over this lane's lags
-    walk_sync<1>();
+    walk_sync<SPLIT>();
 #pragma unroll
-    for (int h = 0; h < NW; ++h) {
-        const int j = lane + 64 * h;
+    for (int h = 0; h < NL; ++h) {
+        const int j = lane + 64 * half(h);
         const int nr = max(N - 1 - j, 0), nl = j < N ? j : 0;
         const Mask R = m_shr(m_shr(M, j), 1);
         const Mask L = j < N ? m_shr(m_shr(Mr, N - 1 - j), 1) : make_mask<NW>(0ull, 0ull);
@@ -550,16 +560,22 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
         rowm1[h] = (uint32_t)(LagLds<NW>::BASE + ROW * j - 1);
     }
     int E = wave_sum(sq_e);
+    if constexpr (SPLIT == 2) {
+        XCH[3 * part] = E;  // uniform value, every lane
+        walk_sync<SPLIT>();
+        E += __builtin_amdgcn_readfirstlane(XCH[3 * (1 - part)]);
+    }
     Mask best = M;
     int bestE = E;
     uint32_t dr0 = 0u, dr1 = 0u;
 
-    uint4 tc[NW][NB];
-    walk_sync<1>();
+    uint4 tc[NL][NB];
+    walk_sync<SPLIT>();
 #pragma unroll
-    for (int h = 0; h < NW; ++h)
+    for (int h = 0; h < NL; ++h)
 #pragma unroll
-        for (int r = 0; r < NB; ++r) tc[h][r] = ((const uint4 *)(rows + ROW * (lane + 64 * h)))[r];
+        for (int r = 0; r < NB; ++r)
+            tc[h][r] = ((const uint4 *)(rows + ROW * (lane + 64 * half(h))))[r];
 
     for (int t0 = 1; t0 <= sch.T; t0 += 64) {
         {
@@ -570,29 +586,49 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
         const int t_end = min(sch.T, t0 + 63);
         for (int t = t0; t <= t_end; ++t) {
             const int slot = t - t0;
-            walk_sync<1>();  // the previous move's C bytes are visible
+            walk_sync<SPLIT>();  // the previous move's C and row bytes are visible
             uint4 cc[NB];
 #pragma unroll
             for (int r = 0; r < NB; ++r) cc[r] = ((const uint4 *)CB)[r];
 
             // key d_j = 2 u_j - s_j v_j: candE_j = E + 4 (N - 1) + 4 d_j
             const int thr = ((bestE - E) >> 2) - (N - 1);
-            int key[NW];
+            int key[NL];
 #pragma unroll
-            for (int h = 0; h < NW; ++h) {
+            for (int h = 0; h < NL; ++h) {
                 int v = 0;
 #pragma unroll
                 for (int r = 0; r < NB; ++r) v = dot16(tc[h][r], cc[r], v);
-                const int d = 2 * u[h] + (lane_bit(mask_word(M, h)) ? v : -v);
+                const int d = 2 * u[h] + (lane_bit(mask_word(M, half(h))) ? v : -v);
                 const bool admissible = tabu[h] < t || (asp[h] && d < thr);
                 key[h] = admissible ? d : INT_MAX;
             }
-            int kmin = key[0];
-            if constexpr (NW == 2) kmin = min(kmin, key[1]);
-            const int m = wave_min(kmin);
-            const uint64_t T0 = ballot(key[0] == m);
-            uint64_t T1 = 0ull;
-            if constexpr (NW == 2) T1 = ballot(key[1] == m);
+            int m;
+            uint64_t T0, T1 = 0ull;
+            if constexpr (SPLIT == 1) {
+                int kmin = key[0];
+                if constexpr (NW == 2) kmin = min(kmin, key[1]);
+                m = wave_min(kmin);
+                T0 = ballot(key[0] == m);
+                if constexpr (NW == 2) T1 = ballot(key[1] == m);
+            } else {
+                // each wavefront's minimum and tie ballot, exchanged in LDS
+                const int mine = wave_min(key[0]);
+                const uint64_t tmine = ballot(key[0] == mine);
+                XCH[3 * part] = mine;  // uniform values, every lane
+                XCH[3 * part + 1] = (int)(uint32_t)tmine;
+                XCH[3 * part + 2] = (int)(uint32_t)(tmine >> 32);
+                walk_sync<SPLIT>();
+                const int other = __builtin_amdgcn_readfirstlane(XCH[3 * (1 - part)]);
+                const uint64_t tother =
+                    ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(XCH[3 * (1 - part) + 2]) << 32) |
+                    (uint32_t)__builtin_amdgcn_readfirstlane(XCH[3 * (1 - part) + 1]);
+                m = min(mine, other);
+                const uint64_t a = mine == m ? tmine : 0ull;
+                const uint64_t b = other == m ? tother : 0ull;
+                T0 = part == 0 ? a : b;
+                T1 = part == 0 ? b : a;
+            }
             const uint32_t u0 = readlane_u(dr0, slot);
             const uint32_t u1 = readlane_u(dr1, slot);
             uint64_t tied = T0;
@@ -624,7 +660,8 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
 
             const int tenure = sch.lo + (int)below(u1, (uint32_t)(sch.hi - sch.lo + 1));
 #pragma unroll
-            for (int h = 0; h < NW; ++h) tabu[h] = pick == lane + 64 * h ? t + tenure : tabu[h];
+            for (int h = 0; h < NL; ++h)
+                tabu[h] = pick == lane + 64 * half(h) ? t + tenure : tabu[h];
             const int sm = 1 - 2 * m_bit(M, pick);  // old s_pick
             M = m_xor(M, m_onebit(M, pick));
             E += 4 * (N - 1 + m);
@@ -632,14 +669,18 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
                 bestE = E;
                 best = M;
             }
-            if constexpr (TRACE) trace[t - 1] = (int16_t)pick;  // uniform store
+            if constexpr (TRACE) {
+                if (part == 0) trace[t - 1] = (int16_t)pick;  // uniform store
+            }
 
+            // each wavefront rewrites the rows of its own neighbours (row
+            // pick, which another wavefront may read below, does not change)
 #pragma unroll
-            for (int h = 0; h < NW; ++h) {
+            for (int h = 0; h < NL; ++h) {
                 // lag |pick - j| of row j: its other end q = 2j - pick (q = j
                 // only for j = pick; q is outside the sequence for j >= N);
                 // s_q, or 0 outside the sequence or for j = pick
-                const int j = lane + 64 * h;
+                const int j = lane + 64 * half(h);
                 const int q = 2 * j - pick;
                 int sq1;
                 if constexpr (NW == 1)
@@ -651,17 +692,17 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
                 // t_jk = s_pick(new) + s_q into row j, byte |pick - j| - 1
                 lds[absdiff_add_s((uint32_t)pick, (uint32_t)j, rowm1[h])] = (uint8_t)(int8_t)(sq - sm);
             }
-            walk_sync<1>();
+            wave_sync();  // own rows only
 #pragma unroll
-            for (int h = 0; h < NW; ++h)
+            for (int h = 0; h < NL; ++h)
 #pragma unroll
                 for (int r = 0; r < NB; ++r)
-                    tc[h][r] = ((const uint4 *)(rows + ROW * (lane + 64 * h)))[r];
+                    tc[h][r] = ((const uint4 *)(rows + ROW * (lane + 64 * half(h))))[r];
 
             // C_k -= 2 s_pick(old) t_pick,k from row pick
 #pragma unroll
-            for (int h = 0; h < NW; ++h) {
-                const int k = lane + 1 + 64 * h;
+            for (int h = 0; h < NL; ++h) {
+                const int k = lane + 1 + 64 * half(h);
                 C[h] += -2 * sm * (int)((const int8_t *)rows)[ROW * pick + k - 1];
                 CB[k - 1] = (int8_t)C[h];
             }
@@ -1082,7 +1123,7 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_records(const int N_in, cons
 }
 
 // Runs one walk of sch.T steps from mask M0 (bits >= N must be clear): the
-// lag form when LAG (N <= 128, one wavefront), the record form otherwise
+// lag form when LAG (N <= 128), the record form otherwise
 // (arguments as above; lds holds walk_lds_bytes<NW, LAG>() bytes).
 template <int NW, bool TRACE = false, int SPLIT = 1, int NB = WalkLds<NW>::NBIG,
           bool LAG = (NW == 1)>
@@ -1095,9 +1136,9 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk(const int N_in,
                                                     int16_t *__restrict__ trace,
                                                     const int part_in = 0) {
     if constexpr (LAG) {
-        static_assert(NW <= 2 && SPLIT == 1, "the lag form: N <= 128 on one wavefront");
-        return tabu_walk_lags<NW, TRACE, NB>(N_in, M0, sch_in, aspiration_in, k0, k1, entity, gen,
-                                             lds, trace);
+        static_assert(NW <= 2, "the lag form: N <= 128");
+        return tabu_walk_lags<NW, TRACE, NB, SPLIT>(N_in, M0, sch_in, aspiration_in, k0, k1, entity,
+                                                    gen, lds, trace, part_in);
     } else {
         return tabu_walk_records<NW, TRACE, SPLIT, NB>(N_in, M0, sch_in, aspiration_in, k0, k1,
                                                        entity, gen, lds, trace, part_in);

@@ -18,6 +18,11 @@ namespace {
 
 constexpr int kMaxK = 128;
 
+// Walk form of the one-child kernels: the lag form for N <= 64, and for
+// 64 < N <= 128 when two wavefronts run a replica (few replicas per CU).
+template <int NW, int SPLIT>
+constexpr bool kAdvanceLag = NW == 1 || (NW == 2 && SPLIT == 2);
+
 
 // ---------------------------------------------------------------------------
 // Memetic replicas.
@@ -156,9 +161,8 @@ __device__ void memetic_replica(const MemeticLaunchArgs &a, const MemeticSlot &s
         // Mutate: bit i flips when word i%4 of draw (pop, g, i/4, MUT) < thr.
         child = m_xor(child, mutation_mask<NW>(sl, gg, 0u, thr));
         const Schedule sch = make_schedule(a.rule, N, sl.k0, sl.k1, sl.pop_id, gg);
-        const WalkResult<NW> r = tabu_walk<NW, false, SPLIT>(N, child, sch, a.rule.aspiration,
-                                                             sl.k0, sl.k1, sl.pop_id, gg, lds,
-                                                             nullptr, part);
+        const WalkResult<NW> r = tabu_walk<NW, false, SPLIT, WalkLds<NW>::NBIG, kAdvanceLag<NW, SPLIT>>(
+            N, child, sch, a.rule.aspiration, sl.k0, sl.k1, sl.pop_id, gg, lds, nullptr, part);
         if (r.best_e < bestE) {
             bestE = r.best_e;
             best = r.best;
@@ -190,17 +194,18 @@ __device__ void memetic_replica(const MemeticLaunchArgs &a, const MemeticSlot &s
 
 // Replicas of one length class: N <= 64 (NW = 1), 64 < N <= 128 (NW = 2) or
 // 128 < N <= 256 (NW = 4), one workgroup of SPLIT wavefronts per replica;
-// slots of the other classes and idle slots return at once.  The two-wavefront form only runs when
-// there are at most two replicas per compute unit, so it is compiled for
-// latency (all of a step's LDS reads in flight at once) rather than for
-// occupancy.
+// slots of the other classes and idle slots return at once.  The
+// two-wavefront form only runs when there are at most two replicas per
+// compute unit, so it is compiled for latency (all of a step's LDS reads in
+// flight at once) rather than for occupancy, and its walks take the lag form
+// (18 KB of LDS, which costs nothing at that occupancy).
 template <int NW, int SPLIT>
 __global__ __launch_bounds__(64 * SPLIT)
 __attribute__((amdgpu_waves_per_eu(1, SPLIT == 2 ? 2 : 8))) void memetic_advance_kernel(
     MemeticLaunchArgs a) {
     __shared__ uint64_t pop[kMaxK][NW];
     __shared__ int popE[kMaxK];
-    __shared__ __attribute__((aligned(16))) uint8_t lds[walk_lds_bytes<NW>()];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[walk_lds_bytes<NW, kAdvanceLag<NW, SPLIT>>()];
     const int s = blockIdx.x;
     if (s >= a.n_slots) return;
     const MemeticSlot sl = a.slots[s];
