@@ -116,10 +116,11 @@ __device__ __forceinline__ void wave_sync() {
 // Minimum over the 64 lanes, returned wave-uniform: row minima by DPP, then
 // rows combined with the row broadcasts (lane 63 ends with the total).
 __device__ __forceinline__ int wave_min(int v) {
-    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, LABS_DPP_QUAD_1032, 0xf, 0xf, false));
-    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, LABS_DPP_QUAD_2301, 0xf, 0xf, false));
-    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, LABS_DPP_ROW_HALF_MIRROR, 0xf, 0xf, false));
-    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, LABS_DPP_ROW_MIRROR, 0xf, 0xf, false));
+    // the first four patterns give every lane a source: no fill value
+    v = min(v, __builtin_amdgcn_mov_dpp(v, LABS_DPP_QUAD_1032, 0xf, 0xf, true));
+    v = min(v, __builtin_amdgcn_mov_dpp(v, LABS_DPP_QUAD_2301, 0xf, 0xf, true));
+    v = min(v, __builtin_amdgcn_mov_dpp(v, LABS_DPP_ROW_HALF_MIRROR, 0xf, 0xf, true));
+    v = min(v, __builtin_amdgcn_mov_dpp(v, LABS_DPP_ROW_MIRROR, 0xf, 0xf, true));
     v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, LABS_DPP_ROW_BCAST15, 0xa, 0xf, false));
     v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, LABS_DPP_ROW_BCAST31, 0xc, 0xf, false));
     return readlane(v, 63);
@@ -351,13 +352,21 @@ struct WalkResult {
 
 // LDS layout of one walk of N > 64 (record form): P records, Q records
 // (each run preceded by 15 spare records, so that the byte update after a
-// move needs no bounds test), plain P, plain Q, C bytes, and six words
+// move needs no bounds test; the Q run sits 0..15 records further on,
+// depending on N, see below), plain P, plain Q, C bytes, and six words
 // through which the two wavefronts of a split walk exchange their minima.
 //   P[x] = s_x for x < N, 0 otherwise; Q is the reversed sequence,
 //   Q[x] = s_{N-1-x} for x < N, 0 otherwise;
 //   record x (16 bytes, at 16 x) holds P[x .. x+15], so a window starting
 //   at any x is the records x, x+16, x+32, ...; lanes that read
 //   consecutive starts touch consecutive 16-byte slots (no bank conflicts);
+//   where the lanes switch from P windows (ascending starts) to Q windows
+//   (descending), a 16-lane group would touch some 16-byte bank slot twice:
+//   lanes j < m (P record j + 1) and j' >= m (Q record N - j') of the
+//   group starting at g meet iff j + j' = dq + N - 1 (mod 16) for a Q run
+//   shifted by dq records; the sums j + j' fill g + m .. g + m + 14, so
+//   dq = m - N (mod 16) clears that group (m = (N + 1) / 2, the first lane
+//   whose longer window is Q);
 //   the plain copies hold P[0 .. LEN) and Q[0 .. LEN) for the C update;
 //   CB[k-1] = C_k as int8 (N <= 128), or C_k >> 1 (N <= 256, where |C_k|
 //   may reach 255; C_k = 2 (C_k >> 1) + ((N - k) & 1) since C_k is a sum of
@@ -387,18 +396,22 @@ constexpr int kSpareRecords = 15;
 // j >= N are never read as neighbour data and take stray writes.
 // (N <= 128: 64 NW rows of 64 NW + 16 bytes, C as 64 NW bytes, and six
 // words through which the two wavefronts of a split walk exchange their
-// minima.)
+// minima.)  Last, the sequence as int8 with zeros around it: SP[q] = s_q
+// for 0 <= q < N and 0 for the other q in -64 NW .. 128 NW - 1, which
+// covers every q = 2j - p of two positions j, p < 64 NW.
 template <int NW>
 struct LagLds {
     static constexpr int ROW = 64 * NW + 16, BASE = 16;
     static constexpr int XCH = BASE + 64 * NW * ROW + 64 * NW;
-    static constexpr int BYTES = XCH + 32;
+    static constexpr int SPLO = XCH + 32, SP = SPLO + 64 * NW;
+    static constexpr int BYTES = SP + 128 * NW;
 };
 
 template <int NW>
 constexpr int record_lds_bytes() {
-    return 2 * 16 * (kSpareRecords + WalkLds<NW>::NREC) + 2 * WalkLds<NW>::LEN +
-           WalkLds<NW>::CLEN + 32;  // + the two-wavefront exchange words
+    // + 16 records of room for the Q run's shift, + the exchange words
+    return 2 * 16 * (kSpareRecords + WalkLds<NW>::NREC) + 16 * 16 + 2 * WalkLds<NW>::LEN +
+           WalkLds<NW>::CLEN + 32;
 }
 
 // LDS bytes of one walk: the lag form (LAG, N <= 128) or the record form.
@@ -437,6 +450,34 @@ __device__ __forceinline__ uint32_t absdiff_add_s(uint32_t a, uint32_t b, uint32
     return d;
 }
 
+// a * b + c for a, b of at most 24 significant bits (signed), where b
+// comes straight from a dot-product instruction: a VALU read of a dot
+// result needs three wait states, which the compiler cannot see to
+// through inline assembly, so five are taken here first.
+__device__ __forceinline__ int mad_i24_after_dot(int a, int b, int c) {
+    int d;
+    asm("s_nop 4\n\tv_mad_i32_i24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
+// The same with b wave-uniform (a scalar operand).
+__device__ __forceinline__ int mad_i24_s(int a, int b, int c) {
+    int d;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "s"(b), "v"(c));
+    return d;
+}
+
+// Byte accesses by LDS offset (the 32-bit address of the local address
+// space, so that an offset computed in one instruction is the address).
+typedef __attribute__((address_space(3))) int8_t lds_i8;
+__device__ __forceinline__ uint32_t lds_offset(const void *p) {
+    return (uint32_t)(uintptr_t)(const lds_i8 *)p;
+}
+__device__ __forceinline__ int lds_load_i8(uint32_t a) { return *(const lds_i8 *)(uintptr_t)a; }
+__device__ __forceinline__ void lds_store_i8(uint32_t a, int v) {
+    *(lds_i8 *)(uintptr_t)a = (int8_t)v;
+}
+
 // Bytewise a + b of four int8 lanes holding -1, 0 or +1 each (no carry
 // crosses a byte: the low seven bits of each byte add to at most 0xFE).
 __device__ __forceinline__ uint32_t add_bytes(uint32_t a, uint32_t b) {
@@ -454,6 +495,7 @@ __device__ __forceinline__ uint32_t pack_bits4(uint64_t bits, int x, int n) {
     const uint32_t ones = (nib * 0x00204081u) & 0x01010101u;  // bit b -> byte b
     return valid | (ones * 0xFEu);
 }
+
 
 __device__ __forceinline__ int dot16(const uint4 a, const uint4 b, int acc) {
     acc = __builtin_amdgcn_sdot4((int)a.x, (int)b.x, acc, false);
@@ -528,11 +570,16 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
 
     // Row j: s_{j+k} is bit k-1 of R = M >> (j+1) (valid below N-1-j),
     // s_{j-k} bit k-1 of L = Mr >> (N-j) (valid below j).
-    int u[NL], C[NL], tabu[NL];
+    int u2[NL], ns[NL], C[NL], tabu[NL];  // 2 u_j, -s_j (set per step)
     bool asp[NL];
-    uint32_t rowm1[NL];  // row j's byte k-1 is lds[rowm1 + k] (k = 0: the spare byte before it)
+    uint32_t rowm1[NL];  // LDS offset of row j's byte k-1, minus k (k = 0: the spare byte)
+    uint32_t spj[NL];    // LDS offset of SP[2j]
     int sq_e = 0;        // sum of C_k^2 over this lane's lags
     walk_sync<SPLIT>();
+    for (int idx = lane + 64 * part; idx < 48 * NW; idx += 64 * SPLIT) {
+        const int x = 4 * idx - 64 * NW;  // SP[x .. x+3]
+        ((uint32_t *)(lds + LagLds<NW>::SPLO))[idx] = x < 0 ? 0u : pack4(M, x, N);
+    }
 #pragma unroll
     for (int h = 0; h < NL; ++h) {
         const int j = lane + 64 * half(h);
@@ -547,7 +594,7 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
                                pack_bits4(mask_word(L, x >> 6), x & 63, nl - (x & ~63)));
         }
         const int nu = min(nr, nl);
-        u[h] = nu - 2 * m_popc(m_and(m_xor(R, L), m_low(R, nu)));
+        u2[h] = 2 * (nu - 2 * m_popc(m_and(m_xor(R, L), m_low(R, nu))));
         // C_k of this lane's lag (Eq. 1) and its int8 mirror
         const int k = j + 1;
         C[h] = k < N ? lag_corr(M, N, k) : 0;
@@ -557,7 +604,8 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
         // and no aspiration
         tabu[h] = j < N ? 0 : INT_MAX;
         asp[h] = aspiration && j < N;
-        rowm1[h] = (uint32_t)(LagLds<NW>::BASE + ROW * j - 1);
+        rowm1[h] = lds_offset(lds) + (uint32_t)(LagLds<NW>::BASE + ROW * j - 1);
+        spj[h] = lds_offset(lds) + (uint32_t)(LagLds<NW>::SP + 2 * j);
     }
     int E = wave_sum(sq_e);
     if constexpr (SPLIT == 2) {
@@ -599,7 +647,8 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
                 int v = 0;
 #pragma unroll
                 for (int r = 0; r < NB; ++r) v = dot16(tc[h][r], cc[r], v);
-                const int d = 2 * u[h] + (lane_bit(mask_word(M, half(h))) ? v : -v);
+                ns[h] = lane_bit(mask_word(M, half(h))) ? 1 : -1;  // -s_j
+                const int d = mad_i24_after_dot(ns[h], v, u2[h]);  // |v| <= N^2
                 const bool admissible = tabu[h] < t || (asp[h] && d < thr);
                 key[h] = admissible ? d : INT_MAX;
             }
@@ -659,9 +708,6 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
             const int pick = pick_base + __builtin_ctzll(tied);
 
             const int tenure = sch.lo + (int)below(u1, (uint32_t)(sch.hi - sch.lo + 1));
-#pragma unroll
-            for (int h = 0; h < NL; ++h)
-                tabu[h] = pick == lane + 64 * half(h) ? t + tenure : tabu[h];
             const int sm = 1 - 2 * m_bit(M, pick);  // old s_pick
             M = m_xor(M, m_onebit(M, pick));
             E += 4 * (N - 1 + m);
@@ -673,24 +719,30 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
                 if (part == 0) trace[t - 1] = (int16_t)pick;  // uniform store
             }
 
-            // each wavefront rewrites the rows of its own neighbours (row
-            // pick, which another wavefront may read below, does not change)
+            // Lag |pick - j| of row j has its other end at q = 2j - pick
+            // (q >= N for j >= N), s_q = SP[q], and changes u_j by
+            // -2 s_pick(old) s_q.  q = j only for j = pick, whose u is
+            // unchanged: that lane reads s_pick(old) itself, and adds back
+            // the -2 it takes; it also stores the new s_pick (its -s_j before
+            // the move) into SP[pick] after the reads (with two wavefronts
+            // the lane is on pick's owner; the other one reads other entries
+            // only).  Each wavefront rewrites the rows of its own neighbours
+            // (row pick, which another wavefront may read below, does not
+            // change; for j = pick the write goes to the spare byte).
 #pragma unroll
             for (int h = 0; h < NL; ++h) {
-                // lag |pick - j| of row j: its other end q = 2j - pick (q = j
-                // only for j = pick; q is outside the sequence for j >= N);
-                // s_q, or 0 outside the sequence or for j = pick
                 const int j = lane + 64 * half(h);
-                const int q = 2 * j - pick;
-                int sq1;
-                if constexpr (NW == 1)
-                    sq1 = __builtin_amdgcn_sbfe((int)(uint32_t)(mask_word(M, 0) >> (q & 63)), 0, 1) | 1;
-                else
-                    sq1 = 1 - 2 * m_bit(M, q & 127);
-                const int sq = (unsigned)q < (unsigned)N && j != pick ? sq1 : 0;
-                u[h] += -2 * sm * sq;  // u_j += -2 s_pick(old) s_q
+                const uint32_t qa = spj[h] - (uint32_t)pick;
+                int sq = lds_load_i8(qa);
+                asm("" : "+v"(sq));  // one sign-extending load
+                u2[h] = mad_i24_s(sq, -4 * sm, u2[h]);
                 // t_jk = s_pick(new) + s_q into row j, byte |pick - j| - 1
-                lds[absdiff_add_s((uint32_t)pick, (uint32_t)j, rowm1[h])] = (uint8_t)(int8_t)(sq - sm);
+                lds_store_i8(absdiff_add_s((uint32_t)pick, (uint32_t)j, rowm1[h]), sq - sm);
+                if (j == pick) {
+                    lds_store_i8(qa, ns[h]);
+                    u2[h] += 4;
+                    tabu[h] = t + tenure;
+                }
             }
             wave_sync();  // own rows only
 #pragma unroll
@@ -784,9 +836,10 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_records(const int N_in, cons
     }
 
     constexpr int kRunBytes = 16 * (kSpareRecords + Cfg::NREC);
+    const int dq = ((N + 1) / 2 - N) & 15;  // the Q run's shift in records
     uint8_t *const RP = lds + 16 * kSpareRecords;
-    uint8_t *const RQ = RP + kRunBytes;
-    uint8_t *const PP = RP - 16 * kSpareRecords + 2 * kRunBytes;
+    uint8_t *const RQ = RP + kRunBytes + 16 * dq;
+    uint8_t *const PP = lds + 2 * kRunBytes + 16 * 16;
     uint8_t *const PQ = PP + Cfg::LEN;
     int8_t *const CB = (int8_t *)(PQ + Cfg::LEN);
     int *const XCH = (int *)(CB + Cfg::CLEN);  // SPLIT exchange: [part][min, tie lo, tie hi]
@@ -834,7 +887,10 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_records(const int N_in, cons
     for (int w = 0; w < NL; ++w) {
         const int j = lane + 64 * half(w);
         const int xr = j + 1;
-        const int xl = j < N ? N - j : N;  // j >= N: an all-zero window
+        // j >= N: an all-zero window, at a start that is a multiple of 16 so
+        // that it shares no bank slot with lanes j < N of its group (all
+        // lanes j >= N read the same address)
+        const int xl = j < N ? N - j : (N + 15) & ~15;
         const uint8_t *right = RP + 16 * xr;
         const uint8_t *left = RQ + 16 * xl;
         const bool right_big = N - 1 - j >= j;
@@ -850,12 +906,12 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_records(const int N_in, cons
     int upd_a, upd_b;
     {
         const int c = lane & 15;
-        const int pln = 2 * kRunBytes - 16 * kSpareRecords;  // PP - RP
+        const int pln = 2 * kRunBytes + 16 * 16 - 16 * kSpareRecords;  // PP - RP
         if (lane < 16) {
             upd_a = -15 * c;
             upd_b = 16;
         } else if (lane < 32) {
-            upd_a = kRunBytes + 16 * (N - 1) - 15 * c;
+            upd_a = kRunBytes + 16 * dq + 16 * (N - 1) - 15 * c;
             upd_b = -16;
         } else if (lane == 32) {
             upd_a = pln;
