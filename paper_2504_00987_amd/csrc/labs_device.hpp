@@ -615,7 +615,8 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
     }
     Mask best = M;
     int bestE = E;
-    uint32_t dr0 = 0u, dr1 = 0u;
+    uint32_t dr0 = 0u;
+    int expire = 0;  // lane l: step t0 + l plus that step's tenure
 
     uint4 tc[NL][NB];
     walk_sync<SPLIT>();
@@ -629,7 +630,7 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
         {
             const Draw4 d = philox10(entity, gen, (uint32_t)(t0 + lane), kTagStep, k0, k1);
             dr0 = d.w0;
-            dr1 = d.w1;
+            expire = t0 + lane + sch.lo + (int)below(d.w1, (uint32_t)(sch.hi - sch.lo + 1));
         }
         const int t_end = min(sch.T, t0 + 63);
         for (int t = t0; t <= t_end; ++t) {
@@ -678,8 +679,6 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
                 T0 = part == 0 ? a : b;
                 T1 = part == 0 ? b : a;
             }
-            const uint32_t u0 = readlane_u(dr0, slot);
-            const uint32_t u1 = readlane_u(dr1, slot);
             uint64_t tied = T0;
             int pick_base = 0;
             if constexpr (NW == 2) {
@@ -688,12 +687,11 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
                     pick_base = 64;
                 }
             }
-            // several tied moves: take the r-th (counts in 32-bit halves keep
-            // the test on the scalar unit)
-            const int c0 = __popc((uint32_t)T0) + __popc((uint32_t)(T0 >> 32));
-            const int count = c0 + __popc((uint32_t)T1) + __popc((uint32_t)(T1 >> 32));
+            // several tied moves: take the r-th, r from the step's first draw
+            int c0 = __popcll(T0), count = NW == 2 ? c0 + __popcll(T1) : c0;
+            asm("" : "+s"(count));  // a 32-bit scalar compare below
             if (count > 1) {
-                int r = (int)below(u0, (uint32_t)count);
+                int r = (int)below(readlane_u(dr0, slot), (uint32_t)count);
                 tied = T0;
                 pick_base = 0;
                 if constexpr (NW == 2) {
@@ -707,8 +705,11 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
             }
             const int pick = pick_base + __builtin_ctzll(tied);
 
-            const int tenure = sch.lo + (int)below(u1, (uint32_t)(sch.hi - sch.lo + 1));
-            const int sm = 1 - 2 * m_bit(M, pick);  // old s_pick
+            const int tabu_new = readlane(expire, slot);  // t + tenure
+            const bool neg = m_bit(M, pick);
+            const int sm = neg ? -1 : 1;    // old s_pick
+            const int k2 = neg ? 2 : -2;    // -2 s_pick(old)
+            const int k4 = neg ? 4 : -4;
             M = m_xor(M, m_onebit(M, pick));
             E += 4 * (N - 1 + m);
             if (E < bestE) {
@@ -729,19 +730,33 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
             // only).  Each wavefront rewrites the rows of its own neighbours
             // (row pick, which another wavefront may read below, does not
             // change; for j = pick the write goes to the spare byte).
+            // Both loads of the move depend on pick alone and go out together:
+            // s_q, and t_pick,k of this lane's lags from row pick (which the
+            // move leaves unchanged) for C_k -= 2 s_pick(old) t_pick,k.
+            uint32_t qa[NL];
+            int sq[NL], tpk[NL];
+#pragma unroll
+            for (int h = 0; h < NL; ++h) {
+                qa[h] = spj[h] - (uint32_t)pick;
+                sq[h] = lds_load_i8(qa[h]);
+                asm("" : "+v"(sq[h]));  // one sign-extending load
+                tpk[h] = ((const int8_t *)rows)[ROW * pick + lane + 64 * half(h)];
+            }
+#pragma unroll
+            for (int h = 0; h < NL; ++h) {
+                C[h] = mad_i24_s(tpk[h], k2, C[h]);
+                CB[lane + 64 * half(h)] = (int8_t)C[h];
+            }
 #pragma unroll
             for (int h = 0; h < NL; ++h) {
                 const int j = lane + 64 * half(h);
-                const uint32_t qa = spj[h] - (uint32_t)pick;
-                int sq = lds_load_i8(qa);
-                asm("" : "+v"(sq));  // one sign-extending load
-                u2[h] = mad_i24_s(sq, -4 * sm, u2[h]);
+                u2[h] = mad_i24_s(sq[h], k4, u2[h]);
                 // t_jk = s_pick(new) + s_q into row j, byte |pick - j| - 1
-                lds_store_i8(absdiff_add_s((uint32_t)pick, (uint32_t)j, rowm1[h]), sq - sm);
+                lds_store_i8(absdiff_add_s((uint32_t)pick, (uint32_t)j, rowm1[h]), sq[h] - sm);
                 if (j == pick) {
-                    lds_store_i8(qa, ns[h]);
+                    lds_store_i8(qa[h], ns[h]);
                     u2[h] += 4;
-                    tabu[h] = t + tenure;
+                    tabu[h] = tabu_new;
                 }
             }
             wave_sync();  // own rows only
@@ -750,14 +765,6 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
 #pragma unroll
                 for (int r = 0; r < NB; ++r)
                     tc[h][r] = ((const uint4 *)(rows + ROW * (lane + 64 * half(h))))[r];
-
-            // C_k -= 2 s_pick(old) t_pick,k from row pick
-#pragma unroll
-            for (int h = 0; h < NL; ++h) {
-                const int k = lane + 1 + 64 * half(h);
-                C[h] += -2 * sm * (int)((const int8_t *)rows)[ROW * pick + k - 1];
-                CB[k - 1] = (int8_t)C[h];
-            }
         }
     }
 
