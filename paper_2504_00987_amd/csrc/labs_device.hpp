@@ -753,7 +753,10 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
                 u2[h] = mad_i24_s(sq[h], k4, u2[h]);
                 // t_jk = s_pick(new) + s_q into row j, byte |pick - j| - 1
                 lds_store_i8(absdiff_add_s((uint32_t)pick, (uint32_t)j, rowm1[h]), sq[h] - sm);
-                if (j == pick) {
+                // lane pick (one neighbour per lane: the one-lane mask
+                // straight from pick's bit; two: a compare is cheaper than
+                // building the masks)
+                if (NW == 1 ? lane_bit(1ull << pick) : j == pick) {
                     lds_store_i8(qa[h], ns[h]);
                     u2[h] += 4;
                     tabu[h] = tabu_new;
@@ -952,7 +955,8 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_records(const int N_in, cons
     }
     Mask best = M;
     int bestE = E;
-    uint32_t dr0 = 0u, dr1 = 0u;
+    uint32_t dr0 = 0u;
+    int expire = 0;  // lane l: step t0 + l plus that step's tenure
 
     // Window chunks of the current pivot, read at the top of each step (two
     // neighbours: the registers for earlier loads would cost occupancy; two
@@ -971,7 +975,7 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_records(const int N_in, cons
         {
             const Draw4 d = philox10(entity, gen, (uint32_t)(t0 + lane), kTagStep, k0, k1);
             dr0 = d.w0;
-            dr1 = d.w1;
+            expire = t0 + lane + sch.lo + (int)below(d.w1, (uint32_t)(sch.hi - sch.lo + 1));
         }
         const int t_end = min(sch.T, t0 + 63);
         for (int t = t0; t <= t_end; ++t) {
@@ -1064,18 +1068,15 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_records(const int N_in, cons
                 T0 = part == 0 ? a : b;
                 T1 = part == 0 ? b : a;
             }
-            const uint32_t u0 = readlane_u(dr0, slot);
-            const uint32_t u1 = readlane_u(dr1, slot);
             int pick;
             if constexpr (NW == 4) {
                 // the r-th tied move over the four 64-neighbour words (r = 0
                 // when only one is tied: the first word with a tied move)
-                const int c0 = __popc((uint32_t)T0) + __popc((uint32_t)(T0 >> 32));
-                const int c1 = __popc((uint32_t)T1) + __popc((uint32_t)(T1 >> 32));
-                const int c2 = __popc((uint32_t)T2) + __popc((uint32_t)(T2 >> 32));
-                const int c3 = __popc((uint32_t)T3) + __popc((uint32_t)(T3 >> 32));
+                int c0 = __popcll(T0), c1 = __popcll(T1), c2 = __popcll(T2), c3 = __popcll(T3);
+                asm("" : "+s"(c0), "+s"(c1), "+s"(c2), "+s"(c3));  // 32-bit scalar arithmetic
                 const int count = c0 + c1 + c2 + c3;
-                int r = count > 1 ? (int)below(u0, (uint32_t)count) : 0;
+                int r = 0;
+                if (count > 1) r = (int)below(readlane_u(dr0, slot), (uint32_t)count);
                 uint64_t tied;
                 int base;
                 if (r < c0) {
@@ -1105,12 +1106,11 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_records(const int N_in, cons
                         pick_base = 64;
                     }
                 }
-                // several tied moves: take the r-th (counts in 32-bit halves keep
-                // the test on the scalar unit)
-                const int c0 = __popc((uint32_t)T0) + __popc((uint32_t)(T0 >> 32));
-                const int count = c0 + __popc((uint32_t)T1) + __popc((uint32_t)(T1 >> 32));
+                // several tied moves: take the r-th, r from the step's first draw
+                int c0 = __popcll(T0), count = c0 + __popcll(T1);
+                asm("" : "+s"(c0), "+s"(count));  // 32-bit scalar arithmetic
                 if (count > 1) {
-                    int r = (int)below(u0, (uint32_t)count);
+                    int r = (int)below(readlane_u(dr0, slot), (uint32_t)count);
                     tied = T0;
                     pick_base = 0;
                     if constexpr (NW == 2) {
@@ -1126,10 +1126,17 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_records(const int N_in, cons
             }
 
             // Apply the move: tenure, sequence, energy, best.
-            const int tenure = sch.lo + (int)below(u1, (uint32_t)(sch.hi - sch.lo + 1));
+            const int tabu_new = readlane(expire, slot);  // t + tenure
+            const bool neg = m_bit(M, pick);
+            const int sm = neg ? -1 : 1;  // old s_pick
+            const int k2 = neg ? 2 : -2;  // -2 s_pick(old)
+            // lane pick (a one-lane mask straight from pick's bit) in
+            // register w = pick >> 6 (one wavefront) or on wavefront part
+            auto is_pick = [&](int w) {
+                return lane_bit((pick >> 6) == half(w) ? 1ull << (pick & 63) : 0ull);
+            };
 #pragma unroll
-            for (int w = 0; w < NL; ++w) tabu[w] = pick == lane + 64 * half(w) ? t + tenure : tabu[w];
-            const int sm = 1 - 2 * m_bit(M, pick);  // old s_pick
+            for (int w = 0; w < NL; ++w) tabu[w] = is_pick(w) ? tabu_new : tabu[w];
             M = m_xor(M, m_onebit(M, pick));
             E += 4 * (N - 1 + m);
             if constexpr (kHalfC) {
@@ -1148,13 +1155,13 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_records(const int N_in, cons
 
             // New s_pick into every record and plain copy that holds it.
             if (updater) RP[upd_a + upd_b * pick] = (uint8_t)(int8_t)(-sm);
+            if constexpr (SPLIT == 1) wave_sync();  // lane pick reads P[pick] below
 
             // C_k -= 2 s_pick t_pick,k for every lag (lane-parallel):
             // s_{pick+k} = P[pick+k] and s_{pick-k} = Q[N-1-pick+k] are bytes of
             // the plain copies, zero past the ends (position pick itself is not
             // read, so the other wavefront's byte update cannot race with it).
             {
-                const int k2 = -2 * sm;
 #pragma unroll
                 for (int w = 0; w < NL; ++w) {
                     const int k = lane + 1 + 64 * half(w);
@@ -1165,15 +1172,23 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_records(const int N_in, cons
                 }
             }
 
-            // u_j += -2 s_pick(old) s_q with s_q = P[q], q = 2j - pick (zero
-            // past the end; q < 0 and j = pick contribute nothing; P[pick]
-            // itself is never used, so the byte update cannot race with it)
+            // u_j += -2 s_pick(old) s_q with s_q = P[q], q = 2j - pick: q >= N
+            // reads a zero, and so does q < 0 (index LEN + q >= N); j = pick,
+            // whose u does not change, reads the new s_pick = -s_pick(old)
+            // (one wavefront: the byte update above is in program order),
+            // so that lane takes back the 2 it adds.  Two wavefronts: the
+            // other one may be writing P[pick], which lane pick then skips.
 #pragma unroll
             for (int w = 0; w < NL; ++w) {
                 const int jw = lane + 64 * half(w);
                 const int q = 2 * jw - pick;
                 const int sq = (int)((const int8_t *)PP)[q & (Cfg::LEN - 1)];
-                uj[w] += q >= 0 && jw != pick ? -2 * sm * sq : 0;
+                if constexpr (SPLIT == 1) {
+                    uj[w] += k2 * sq;
+                    if (is_pick(w)) uj[w] -= 2;
+                } else {
+                    uj[w] += jw != pick ? k2 * sq : 0;
+                }
             }
         }
     }
