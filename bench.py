@@ -51,16 +51,16 @@ COUNTERS = {
     # workgroup), mean over the profiled dispatches; sums over the kernels
     # of one call (the uneven batch runs one kernel per length class,
     # concurrently)
-    "tabu_n64": {"digest": "8d9be66ca26811e1", "FETCH_SIZE": 82.7, "WRITE_SIZE": 576.0,
-                 "SQ_INSTS_VALU": 56782046, "SQ_INSTS_LDS": 11620352,
+    "tabu_n64": {"digest": "fdd150d01ce798fe", "FETCH_SIZE": 82.5, "WRITE_SIZE": 576.0,
+                 "SQ_INSTS_VALU": 45537724, "SQ_INSTS_LDS": 13721600,
                  "SQ_LDS_BANK_CONFLICT": 2847176,
                  "source": "profiles/tabu_kernel_counters.md"},
-    "tabu_uneven": {"digest": "8d9be66ca26811e1", "FETCH_SIZE": 695.1, "WRITE_SIZE": 1456.8,
-                    "SQ_INSTS_VALU": 259116576, "SQ_INSTS_LDS": 68038890,
-                    "SQ_LDS_BANK_CONFLICT": 50911450,
+    "tabu_uneven": {"digest": "fdd150d01ce798fe", "FETCH_SIZE": 706.5, "WRITE_SIZE": 1457.1,
+                    "SQ_INSTS_VALU": 247309768, "SQ_INSTS_LDS": 68674472,
+                    "SQ_LDS_BANK_CONFLICT": 37410650,
                     "source": "profiles/tabu_kernel_counters.md"},
-    "tabu_n256": {"digest": "8d9be66ca26811e1", "FETCH_SIZE": 177.7, "WRITE_SIZE": 1088.0,
-                  "SQ_INSTS_VALU": 2073210880, "SQ_INSTS_LDS": 541691904,
+    "tabu_n256": {"digest": "fdd150d01ce798fe", "FETCH_SIZE": 177.1, "WRITE_SIZE": 1088.0,
+                  "SQ_INSTS_VALU": 2027584427, "SQ_INSTS_LDS": 541691904,
                   "SQ_LDS_BANK_CONFLICT": 4194304,
                   "source": "profiles/tabu_kernel_counters.md"},
 }

@@ -206,10 +206,13 @@ int labs_get_launch(labs_handle *h, int32_t n, labs_launch *out);
  * workgroup, i.e. 1, 2, 4 walks per workgroup} x {one wave per walk,
  * persistent queue at 1/2/4/8 x 4/(walks per workgroup) groups per CU} on
  * `walks` random-start walks with lengths spread evenly over [n_min, n_max]
- * and parameters `p`, and keeps the fastest for the batches whose longest
- * walk falls in the length bucket (of 16) of n_max.  *tried (may be NULL)
- * receives the number of configurations timed.  Synchronous; results never
- * depend on the choice (only speed does).
+ * and parameters `p` (each: one warm-up call, then four calls back to
+ * back), and keeps the fastest for the batches whose longest walk falls in
+ * the length bucket (of 16) of n_max; the default launch (four walks per
+ * workgroup, one wave per walk) stays unless a configuration is more than
+ * 2 % faster.  *tried (may be NULL) receives the number of configurations
+ * timed.  Synchronous; results never depend on the choice (only speed
+ * does).
  */
 int labs_autotune(labs_handle *h, const labs_tabu_params *p, int32_t n_min,
                   int32_t n_max, int64_t walks, uint64_t seed, int32_t *tried);

@@ -509,6 +509,29 @@ def test_tabu_all_classes_ragged(lb):
     assert np.array_equal(res.best_seq.cpu().numpy(), best)
 
 
+@pytest.mark.parametrize("launch", [(4, 0, 0), (2, 1, 1)])
+def test_tabu_every_length(lb, launch):
+    """One walk at every N in 3..256, move traces compared: each N has its own
+    placement of the reversed records (a shift of 0..15 records that keeps the
+    window reads conflict-free) and its own start of the zero window for lanes
+    past N, and the lengths span every class boundary."""
+    say(f"tabu: every N in 3..256, traces, launch {launch}")
+    ns = np.arange(3, 257, dtype=np.int32)
+    rules = I.Rules(I.STEPS_MULT_N, 1, I.TENURE_LINEAR, 1, 10, 0, 1, 5, 0, 1)
+    lb.set_launch(*launch)
+    try:
+        res = lb.tabu_batch(rules, len(ns), 7007, ns=ns, out_stride=256, trace_stride=256)
+    finally:
+        lb.set_launch(None)
+    best, be, fe, trs = _oracle_walks(len(ns), ns, rules, 7007)
+    assert np.array_equal(res.best_e.cpu().numpy(), be)
+    assert np.array_equal(res.final_e.cpu().numpy(), fe)
+    assert np.array_equal(res.best_seq.cpu().numpy(), best)
+    tr = res.trace.cpu().numpy()
+    for w in range(len(ns)):
+        assert np.array_equal(tr[w, : len(trs[w])], trs[w]), f"N={ns[w]}"
+
+
 def test_tabu_n256_full_size_sampled(lb):
     # 4096 walks of N = 256 (four per workgroup, the default launch);
     # sampled walks against the oracle, properties at every walk
