@@ -192,13 +192,11 @@ __device__ __forceinline__ M128 m_low(M128, int n) {
     return r;
 }
 __device__ __forceinline__ int m_bit(M128 a, int i) {
-    return i < 64 ? (int)((a.lo >> i) & 1ull) : (int)((a.hi >> (i - 64)) & 1ull);
+    return (int)(((i < 64 ? a.lo : a.hi) >> (i & 63)) & 1ull);
 }
 __device__ __forceinline__ M128 m_onebit(M128, int i) {
-    M128 r;
-    r.lo = i < 64 ? (1ull << i) : 0ull;
-    r.hi = i < 64 ? 0ull : (1ull << (i - 64));
-    return r;
+    const uint64_t b = 1ull << (i & 63);
+    return {i < 64 ? b : 0ull, i < 64 ? 0ull : b};
 }
 
 // 256-bit masks for N <= 256 (four words, selected by value so that a
@@ -460,6 +458,14 @@ __device__ __forceinline__ int mad_i24_after_dot(int a, int b, int c) {
     return d;
 }
 
+// Two of them (a0 * b0 + c0, a1 * b1 + c1) after one such wait.
+__device__ __forceinline__ void mad2_i24_after_dot(int a0, int b0, int c0, int a1, int b1, int c1,
+                                                   int &d0, int &d1) {
+    asm("s_nop 4\n\tv_mad_i32_i24 %0, %2, %3, %4\n\tv_mad_i32_i24 %1, %5, %6, %7"
+        : "=&v"(d0), "=&v"(d1)
+        : "v"(a0), "v"(b0), "v"(c0), "v"(a1), "v"(b1), "v"(c1));
+}
+
 // The same with b wave-uniform (a scalar operand).
 __device__ __forceinline__ int mad_i24_s(int a, int b, int c) {
     int d;
@@ -642,16 +648,22 @@ __device__ __forceinline__ WalkResult<NW> tabu_walk_lags(const int N_in,
 
             // key d_j = 2 u_j - s_j v_j: candE_j = E + 4 (N - 1) + 4 d_j
             const int thr = ((bestE - E) >> 2) - (N - 1);
-            int key[NL];
+            int key[NL], v[NL], d[NL];
 #pragma unroll
             for (int h = 0; h < NL; ++h) {
-                int v = 0;
+                v[h] = 0;
 #pragma unroll
-                for (int r = 0; r < NB; ++r) v = dot16(tc[h][r], cc[r], v);
+                for (int r = 0; r < NB; ++r) v[h] = dot16(tc[h][r], cc[r], v[h]);
                 ns[h] = lane_bit(mask_word(M, half(h))) ? 1 : -1;  // -s_j
-                const int d = mad_i24_after_dot(ns[h], v, u2[h]);  // |v| <= N^2
-                const bool admissible = tabu[h] < t || (asp[h] && d < thr);
-                key[h] = admissible ? d : INT_MAX;
+            }
+            if constexpr (NL == 2)  // |v| <= N^2
+                mad2_i24_after_dot(ns[0], v[0], u2[0], ns[1], v[1], u2[1], d[0], d[1]);
+            else
+                d[0] = mad_i24_after_dot(ns[0], v[0], u2[0]);
+#pragma unroll
+            for (int h = 0; h < NL; ++h) {
+                const bool admissible = tabu[h] < t || (asp[h] && d[h] < thr);
+                key[h] = admissible ? d[h] : INT_MAX;
             }
             int m;
             uint64_t T0, T1 = 0ull;
