@@ -208,9 +208,9 @@ int labs_get_launch(labs_handle *h, int32_t n, labs_launch *out);
  * `walks` random-start walks with lengths spread evenly over [n_min, n_max]
  * and parameters `p` (each: one warm-up call, then four calls back to
  * back), and keeps the fastest for the batches whose longest walk falls in
- * the length bucket (of 16) of n_max; the default launch (four walks per
- * workgroup, one wave per walk) stays unless a configuration is more than
- * 2 % faster.  *tried (may be NULL) receives the number of configurations
+ * the length bucket (of 16) of n_max; the default launch (one wave per
+ * walk; one walk per workgroup up to N = 128, four above) stays unless a
+ * configuration is more than 2 % faster.  *tried (may be NULL) receives the number of configurations
  * timed.  Synchronous; results never depend on the choice (only speed
  * does).
  */

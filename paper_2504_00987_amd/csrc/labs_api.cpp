@@ -187,17 +187,17 @@ RuleParams to_rule(const labs_tabu_params &p) {
 
 int bucket_of(int n) { return std::min(LABS_MAX_N / 16 - 1, std::max(0, (n - 1) / 16)); }
 
-// Four walks per workgroup, one workgroup per four walks: the four
-// wavefronts land on the four SIMDs of a CU, and the results of neighbouring
-// walks are written by one workgroup (the autotuner's choice on the N=64 and
-// uneven batches).
-labs_launch default_launch(labs_handle *h, bool uneven) {
+// One wave per walk.  Up to N = 128, one walk per 64-lane workgroup: the
+// kernels compiled for that size keep their registers low enough for four
+// wavefronts per SIMD (the two-neighbour ones need 104 VGPRs there, 136 with
+// four walks per workgroup), 3 to 8 % faster on the N = 64 and uneven
+// batches.  Longer walks are bound by LDS (18 KB per walk), and four walks
+// per 256-lane workgroup, one per SIMD of a CU, time best there.
+labs_launch default_launch(int n_max) {
     labs_launch l;
-    l.waves_per_group = 4;
+    l.waves_per_group = n_max <= 128 ? 1 : 4;
     l.persistent = 0;
     l.groups_per_cu = 0;
-    (void)h;
-    (void)uneven;
     return l;
 }
 
@@ -396,7 +396,7 @@ int labs_get_launch(labs_handle *h, int32_t n, labs_launch *out) {
     if (!h || !out) return LABS_E_INVAL;
     h->last_error.clear();
     if (n < LABS_MIN_N || n > LABS_MAX_N) return fail(h, LABS_E_INVAL, "n out of range");
-    *out = liblabs::choose_launch(h, n, false);
+    *out = liblabs::choose_launch(h, n);
     return LABS_OK;
 }
 
@@ -404,11 +404,11 @@ int labs_get_launch(labs_handle *h, int32_t n, labs_launch *out) {
 
 namespace liblabs {
 
-labs_launch choose_launch(labs_handle *h, int n_max, bool uneven) {
+labs_launch choose_launch(labs_handle *h, int n_max) {
     if (h->has_override) return h->override_launch;
     const labs_launch &t = h->tuned[bucket_of(n_max)];
     if (t.waves_per_group != 0) return t;
-    return default_launch(h, uneven);
+    return default_launch(n_max);
 }
 
 // Shared body of labs_tabu_batch (also used by the autotuner).
@@ -458,8 +458,7 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
     if (trace && trace_stride < tmax)
         return fail(h, LABS_E_INVAL, "trace_stride=%d < longest walk %lld", trace_stride, tmax);
 
-    const bool uneven = ns_host && n_min != n_max;
-    const labs_launch L = force ? *force : choose_launch(h, n_max, uneven);
+    const labs_launch L = force ? *force : choose_launch(h, n_max);
 
     DeviceGuard g(h->device);
     // Workspace: [queue heads (32 words per class)] [ns (W int32)] [order (W int32)].
@@ -589,7 +588,7 @@ extern "C" int labs_autotune(labs_handle *h, const labs_tabu_params *p, int32_t 
     constexpr int kReps = 4;
     constexpr float kMargin = 0.98f;
     const bool uneven = n_min != n_max;
-    std::vector<labs_launch> cands{default_launch(h, uneven)};
+    std::vector<labs_launch> cands{default_launch(n_max)};
     for (int w : {1, 2, 4}) {
         cands.push_back(labs_launch{w, 0, 0});
         for (int gpc : {1, 2, 4, 8}) cands.push_back(labs_launch{w, 1, gpc * 4 / w});

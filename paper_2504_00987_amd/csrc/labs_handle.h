@@ -72,7 +72,7 @@ int stage_release(labs_handle *h, hipStream_t s);
 int check_rule(labs_handle *h, const RuleParams &r, int n);
 long long max_steps(const RuleParams &r, int n);
 RuleParams to_rule(const labs_tabu_params &p);
-labs_launch choose_launch(labs_handle *h, int n_max, bool uneven);
+labs_launch choose_launch(labs_handle *h, int n_max);
 int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *starts,
                     int32_t start_stride, const int32_t *ns_host, int32_t n_uniform, int64_t W,
                     uint64_t seed, int8_t *best_seq, int32_t out_stride, int32_t *best_e,

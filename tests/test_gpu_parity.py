@@ -207,7 +207,7 @@ def test_autotune_then_parity():
         wpg, pers, gpc = h.get_launch(120)
         assert wpg in (1, 2, 4) and pers in (0, 1)
         assert (not pers and gpc == 0) or (pers and gpc * wpg in (4, 8, 16, 32))
-        assert before == (4, 0, 0)
+        assert before == (1, 0, 0)  # the default up to N = 128
         ns = I.uneven_lengths(200, 48, 120, seed=23)
         res = h.tabu_batch(rules, len(ns), 1002, ns=ns)
         best, be, fe = O.tabu_batch(len(ns), osched(rules), 1002, ns=ns, stride=128, nthreads=8)
