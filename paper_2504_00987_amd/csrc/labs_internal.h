@@ -46,6 +46,14 @@ inline int walk_class(int n) {
 }
 // Streams besides the caller's one that a batch may fork onto.
 constexpr int kSideStreams = kWalkClasses - 1;
+// Whether the walks of N <= 128 (classes 2..5, consecutive positions of the
+// processing order) span more than one class: then they run in one launch,
+// on the stream of class 2 (which every class of the range uses).
+inline bool mixed_short_classes(const int64_t *class_end) {
+    int present = 0;
+    for (int c = 2; c < 6; ++c) present += class_end[c] > class_end[c - 1];
+    return present > 1;
+}
 
 // Words of a sequence mask in the memetic state (N <= 256).
 constexpr int kStateWords = 4;

@@ -130,6 +130,45 @@ __global__ __launch_bounds__(64 * WPG) void tabu_kernel(TabuLaunchArgs a, int64_
     }
 }
 
+// Walks of the classes with N <= 128 (processing-order positions
+// [class_end[1], class_end[5])) in one launch: each wavefront runs the
+// instantiation of its own walk's class, in LDS scratch sized for the
+// largest of them.  One launch on the caller's stream spares a batch of
+// several such classes the fork to side streams and the join back, whose
+// event waits cost tens of microseconds per call, and drains the whole
+// longest-first order at once.
+constexpr int kMixedLds = walk_lds_bytes<2>() > walk_lds_bytes<1>() ? walk_lds_bytes<2>()
+                                                                    : walk_lds_bytes<1>();
+
+template <bool TRACE>
+__device__ __forceinline__ void run_mixed_item(const TabuLaunchArgs &a, int64_t w, uint8_t *lds) {
+    const int N = __builtin_amdgcn_readfirstlane(a.ns ? a.ns[w] : a.n_uniform);
+    if (N > kClassMaxN[3])
+        run_tabu_item<2, 8, TRACE>(a, w, N, lds);
+    else if (N > kClassMaxN[4])
+        run_tabu_item<2, 6, TRACE>(a, w, N, lds);
+    else if (N > kClassMaxN[5])
+        run_tabu_item<1, 4, TRACE>(a, w, N, lds);
+    else
+        run_tabu_item<1, 3, TRACE>(a, w, N, lds);
+}
+
+template <int WPG, bool PERSIST, bool TRACE>
+__global__ __launch_bounds__(64 * WPG) void tabu_kernel_mixed(TabuLaunchArgs a, int64_t begin,
+                                                              int64_t end, uint32_t *counter) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds_all[WPG][kMixedLds];
+    const int wave = threadIdx.x >> 6;
+    uint8_t *lds = lds_all[wave];
+    if constexpr (PERSIST) {
+        for (int64_t pos = begin + next_work(counter); pos < end;
+             pos = begin + next_work(counter))
+            run_mixed_item<TRACE>(a, a.order ? (int64_t)a.order[pos] : pos, lds);
+    } else {
+        const int64_t pos = begin + (int64_t)blockIdx.x * WPG + wave;
+        if (pos < end) run_mixed_item<TRACE>(a, a.order ? (int64_t)a.order[pos] : pos, lds);
+    }
+}
+
 __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t count) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = v;
@@ -176,6 +215,24 @@ hipError_t launch_tabu_part(const TabuLaunchArgs &a, int64_t begin, int64_t end,
                : launch_tabu_part_t<NW, NB, WPG, false>(a, begin, end, groups, counter, s);
 }
 
+template <int WPG, bool TRACE>
+hipError_t launch_mixed_t(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
+                          uint32_t *counter, hipStream_t s) {
+    if (groups > 0) {
+        hipError_t e = launch_fill_u32(counter, 0u, 1, s);
+        if (e != hipSuccess) return e;
+        const int64_t need = (end - begin + WPG - 1) / WPG;
+        hipLaunchKernelGGL((tabu_kernel_mixed<WPG, true, TRACE>),
+                           dim3((unsigned)std::min<int64_t>(groups, need)), dim3(64 * WPG), 0, s, a,
+                           begin, end, counter);
+    } else {
+        const int64_t grid = (end - begin + WPG - 1) / WPG;
+        hipLaunchKernelGGL((tabu_kernel_mixed<WPG, false, TRACE>), dim3((unsigned)grid),
+                           dim3(64 * WPG), 0, s, a, begin, end, counter);
+    }
+    return hipGetLastError();
+}
+
 // One launch per non-empty length class, each on its own stream with its
 // own queue head (32 words apart).
 template <int WPG>
@@ -185,7 +242,14 @@ hipError_t launch_tabu_wpg(const TabuLaunchArgs &a, int groups, const hipStream_
     uint32_t *q = a.counter;
     hipError_t e = launch_tabu_part<4, 16, WPG>(a, 0, ce[0], groups, q, st[0]);
     if (e == hipSuccess) e = launch_tabu_part<4, 12, WPG>(a, ce[0], ce[1], groups, q + 32, st[1]);
-    if (e == hipSuccess) e = launch_tabu_part<2, 8, WPG>(a, ce[1], ce[2], groups, q + 64, st[2]);
+    if (e != hipSuccess) return e;
+    if (mixed_short_classes(ce)) {
+        // classes 2..5 share one launch, on class 2's stream
+        return a.trace != nullptr
+                   ? launch_mixed_t<WPG, true>(a, ce[1], ce[5], groups, q + 64, st[2])
+                   : launch_mixed_t<WPG, false>(a, ce[1], ce[5], groups, q + 64, st[2]);
+    }
+    e = launch_tabu_part<2, 8, WPG>(a, ce[1], ce[2], groups, q + 64, st[2]);
     if (e == hipSuccess) e = launch_tabu_part<2, 6, WPG>(a, ce[2], ce[3], groups, q + 96, st[3]);
     if (e == hipSuccess) e = launch_tabu_part<1, 4, WPG>(a, ce[3], ce[4], groups, q + 128, st[4]);
     if (e == hipSuccess) e = launch_tabu_part<1, 3, WPG>(a, ce[4], ce[5], groups, q + 160, st[5]);
