@@ -142,11 +142,17 @@ constexpr int kMixedLds = walk_lds_bytes<2>() > walk_lds_bytes<1>() ? walk_lds_b
 
 template <bool TRACE>
 __device__ __forceinline__ void run_mixed_item(const TabuLaunchArgs &a, int64_t w, uint8_t *lds) {
+    // windows of the fewest 16-lag chunks that hold N - 1 lags (within the
+    // launch, finer steps than the classes cost only code)
     const int N = __builtin_amdgcn_readfirstlane(a.ns ? a.ns[w] : a.n_uniform);
-    if (N > kClassMaxN[3])
+    if (N > 113)
         run_tabu_item<2, 8, TRACE>(a, w, N, lds);
-    else if (N > kClassMaxN[4])
+    else if (N > kClassMaxN[3])
+        run_tabu_item<2, 7, TRACE>(a, w, N, lds);
+    else if (N > 81)
         run_tabu_item<2, 6, TRACE>(a, w, N, lds);
+    else if (N > kClassMaxN[4])
+        run_tabu_item<2, 5, TRACE>(a, w, N, lds);
     else if (N > kClassMaxN[5])
         run_tabu_item<1, 4, TRACE>(a, w, N, lds);
     else
@@ -154,7 +160,7 @@ __device__ __forceinline__ void run_mixed_item(const TabuLaunchArgs &a, int64_t 
 }
 
 template <int WPG, bool PERSIST, bool TRACE>
-__global__ __launch_bounds__(64 * WPG) void tabu_kernel_mixed(TabuLaunchArgs a, int64_t begin,
+__global__ __launch_bounds__(64 * WPG) __attribute__((amdgpu_waves_per_eu(WPG == 1 && !PERSIST ? 4 : 1))) void tabu_kernel_mixed(TabuLaunchArgs a, int64_t begin,
                                                               int64_t end, uint32_t *counter) {
     __shared__ __attribute__((aligned(16))) uint8_t lds_all[WPG][kMixedLds];
     const int wave = threadIdx.x >> 6;
