@@ -51,18 +51,18 @@ COUNTERS = {
     # workgroup), mean over the profiled dispatches; sums over the kernels
     # of one call (the uneven batch runs one kernel per length class,
     # concurrently)
-    "tabu_n64": {"digest": "2c326f1103a4815b", "FETCH_SIZE": 77.0, "WRITE_SIZE": 576.0,
-                 "SQ_INSTS_VALU": 45537724, "SQ_INSTS_LDS": 13721600,
-                 "SQ_LDS_BANK_CONFLICT": 2847176,
-                 "source": "profiles/tabu_kernel_counters.md"},
-    "tabu_uneven": {"digest": "2c326f1103a4815b", "FETCH_SIZE": 695.6, "WRITE_SIZE": 1456.2,
-                    "SQ_INSTS_VALU": 247353910, "SQ_INSTS_LDS": 68674472,
-                    "SQ_LDS_BANK_CONFLICT": 37410650,
-                    "source": "profiles/tabu_kernel_counters.md"},
-    "tabu_n256": {"digest": "2c326f1103a4815b", "FETCH_SIZE": 177.1, "WRITE_SIZE": 1088.0,
-                  "SQ_INSTS_VALU": 2027584427, "SQ_INSTS_LDS": 541691904,
-                  "SQ_LDS_BANK_CONFLICT": 4194304,
-                  "source": "profiles/tabu_kernel_counters.md"},
+    "tabu_n64": {"digest": "9c2c4d8e9fc02dea", "FETCH_SIZE": 84.2, "WRITE_SIZE": 768.0,
+        "SQ_INSTS_VALU": 45513148, "SQ_INSTS_LDS": 13721600,
+        "SQ_LDS_BANK_CONFLICT": 2847176,
+        "source": "profiles/tabu_kernel_counters.md"},
+    "tabu_uneven": {"digest": "9c2c4d8e9fc02dea", "FETCH_SIZE": 634.6, "WRITE_SIZE": 1361.1,
+        "SQ_INSTS_VALU": 238153444, "SQ_INSTS_LDS": 65717792,
+        "SQ_LDS_BANK_CONFLICT": 35697887,
+        "source": "profiles/tabu_kernel_counters.md"},
+    "tabu_n256": {"digest": "9c2c4d8e9fc02dea", "FETCH_SIZE": 176.2, "WRITE_SIZE": 1088.0,
+        "SQ_INSTS_VALU": 2027584427, "SQ_INSTS_LDS": 541691904,
+        "SQ_LDS_BANK_CONFLICT": 4194304,
+        "source": "profiles/tabu_kernel_counters.md"},
 }
 
 
