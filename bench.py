@@ -1,6 +1,6 @@
 """Benchmark of the batched tabu-search hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload tabu_n64|tabu_uneven|tabu_n256]
+    python bench.py [--steps K] [--warmup W] [--workload tabu_n64|tabu_uneven|tabu_n256|tabu_long_uneven]
                     [--no-cpu] [--no-ttt] [--no-serving] [--no-skew]
 
 A step is one labs_tabu_batch call over the whole batch (every walk scores
@@ -51,15 +51,15 @@ COUNTERS = {
     # workgroup), mean over the profiled dispatches; sums over the kernels
     # of one call (the uneven batch runs one kernel per length class,
     # concurrently)
-    "tabu_n64": {"digest": "9c2c4d8e9fc02dea", "FETCH_SIZE": 84.2, "WRITE_SIZE": 768.0,
+    "tabu_n64": {"digest": "f71d5cbffbfaf0fc", "FETCH_SIZE": 80.5, "WRITE_SIZE": 768.0,
         "SQ_INSTS_VALU": 45513148, "SQ_INSTS_LDS": 13721600,
         "SQ_LDS_BANK_CONFLICT": 2847176,
         "source": "profiles/tabu_kernel_counters.md"},
-    "tabu_uneven": {"digest": "9c2c4d8e9fc02dea", "FETCH_SIZE": 634.6, "WRITE_SIZE": 1361.1,
+    "tabu_uneven": {"digest": "f71d5cbffbfaf0fc", "FETCH_SIZE": 631.8, "WRITE_SIZE": 1361.1,
         "SQ_INSTS_VALU": 238153444, "SQ_INSTS_LDS": 65717792,
         "SQ_LDS_BANK_CONFLICT": 35697887,
         "source": "profiles/tabu_kernel_counters.md"},
-    "tabu_n256": {"digest": "9c2c4d8e9fc02dea", "FETCH_SIZE": 176.2, "WRITE_SIZE": 1088.0,
+    "tabu_n256": {"digest": "f71d5cbffbfaf0fc", "FETCH_SIZE": 176.1, "WRITE_SIZE": 1088.0,
         "SQ_INSTS_VALU": 2027584427, "SQ_INSTS_LDS": 541691904,
         "SQ_LDS_BANK_CONFLICT": 4194304,
         "source": "profiles/tabu_kernel_counters.md"},
@@ -420,7 +420,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="tabu_n64", choices=["tabu_n64", "tabu_uneven", "tabu_n256"])
+    ap.add_argument("--workload", default="tabu_n64", choices=["tabu_n64", "tabu_uneven", "tabu_n256", "tabu_long_uneven"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default launch configuration instead of the tuned one")

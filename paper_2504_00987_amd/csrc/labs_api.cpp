@@ -513,22 +513,25 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
     a.trace = trace;
     a.trace_stride = trace_stride;
     const int groups = L.persistent ? persistent_groups(h, L) : 0;
-    // The length classes present run concurrently: the first on `s`, the
-    // others on the handle's side streams, forked from and joined into `s`.
-    // Classes 2..5 (N <= 128), when more than one is present, are one launch
-    // and take one stream.
+    // The launches present run concurrently: the first on `s`, the others on
+    // the handle's side streams, forked from and joined into `s`.  A launch
+    // is one length class, or classes 0..1 (N > 128) and classes 2..5
+    // (N <= 128) when more than one class of that range is present.
     const SideStreams &sides = h->sides;
     hipStream_t streams[kWalkClasses];
-    const bool mixed = mixed_short_classes(a.class_end);
+    const bool mixed_long = mixed_long_classes(a.class_end);
+    const bool mixed_short = mixed_short_classes(a.class_end);
     int n_sides = 0;
     for (int c = 0, used = 0; c < kWalkClasses; ++c) {
         const int64_t begin = c ? a.class_end[c - 1] : 0;
         streams[c] = s;
-        const bool present = mixed && c >= 2 ? c == 2 && a.class_end[5] > a.class_end[1]
-                                             : a.class_end[c] > begin;
+        bool present = a.class_end[c] > begin;
+        if (mixed_long && c < 2) present = c == 0;  // both non-empty
+        if (mixed_short && c >= 2) present = c == 2 && a.class_end[5] > a.class_end[1];
         if (present && used++ > 0) streams[c] = sides.s[n_sides++];
     }
-    if (mixed)
+    if (mixed_long) streams[1] = streams[0];
+    if (mixed_short)
         for (int c = 3; c < 6; ++c) streams[c] = streams[2];
     hipError_t e = hipSuccess;
     if (n_sides > 0) {

@@ -54,6 +54,11 @@ inline bool mixed_short_classes(const int64_t *class_end) {
     for (int c = 2; c < 6; ++c) present += class_end[c] > class_end[c - 1];
     return present > 1;
 }
+// Whether both classes of N > 128 (0 and 1, positions [0, class_end[1]))
+// are present: then they likewise run in one launch, on the stream of class 0.
+inline bool mixed_long_classes(const int64_t *class_end) {
+    return class_end[0] > 0 && class_end[1] > class_end[0];
+}
 
 // Words of a sequence mask in the memetic state (N <= 256).
 constexpr int kStateWords = 4;

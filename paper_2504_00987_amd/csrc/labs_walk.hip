@@ -159,19 +159,46 @@ __device__ __forceinline__ void run_mixed_item(const TabuLaunchArgs &a, int64_t 
         run_tabu_item<1, 3, TRACE>(a, w, N, lds);
 }
 
-template <int WPG, bool PERSIST, bool TRACE>
-__global__ __launch_bounds__(64 * WPG) __attribute__((amdgpu_waves_per_eu(WPG == 1 && !PERSIST ? 4 : 1))) void tabu_kernel_mixed(TabuLaunchArgs a, int64_t begin,
+// Walks of N > 128 (classes 0 and 1, positions [0, class_end[1])) in one
+// launch, for the same reason; all take four neighbours per lane, so they
+// share one LDS layout, and each walk again spans the fewest chunks that
+// hold its N - 1 lags.
+template <bool TRACE>
+__device__ __forceinline__ void run_mixed_long_item(const TabuLaunchArgs &a, int64_t w,
+                                                    uint8_t *lds) {
+    const int N = __builtin_amdgcn_readfirstlane(a.ns ? a.ns[w] : a.n_uniform);
+    if (N > kClassMaxN[1])
+        run_tabu_item<4, 16, TRACE>(a, w, N, lds);
+    else
+        run_tabu_item<4, 12, TRACE>(a, w, N, lds);
+}
+
+template <bool TRACE, bool LONG>
+__device__ __forceinline__ void run_mixed_range_item(const TabuLaunchArgs &a, int64_t pos,
+                                                     uint8_t *lds) {
+    const int64_t w = a.order ? (int64_t)a.order[pos] : pos;
+    if constexpr (LONG)
+        run_mixed_long_item<TRACE>(a, w, lds);
+    else
+        run_mixed_item<TRACE>(a, w, lds);
+}
+
+// LONG selects the N > 128 range (four wavefronts per SIMD is a hint for the
+// short range only, whose default launch is one walk per workgroup).
+template <int WPG, bool PERSIST, bool TRACE, bool LONG>
+__global__ __launch_bounds__(64 * WPG) __attribute__((amdgpu_waves_per_eu(WPG == 1 && !PERSIST && !LONG ? 4 : 1))) void tabu_kernel_mixed(TabuLaunchArgs a, int64_t begin,
                                                               int64_t end, uint32_t *counter) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds_all[WPG][kMixedLds];
+    constexpr int kLds = LONG ? walk_lds_bytes<4>() : kMixedLds;
+    __shared__ __attribute__((aligned(16))) uint8_t lds_all[WPG][kLds];
     const int wave = threadIdx.x >> 6;
     uint8_t *lds = lds_all[wave];
     if constexpr (PERSIST) {
         for (int64_t pos = begin + next_work(counter); pos < end;
              pos = begin + next_work(counter))
-            run_mixed_item<TRACE>(a, a.order ? (int64_t)a.order[pos] : pos, lds);
+            run_mixed_range_item<TRACE, LONG>(a, pos, lds);
     } else {
         const int64_t pos = begin + (int64_t)blockIdx.x * WPG + wave;
-        if (pos < end) run_mixed_item<TRACE>(a, a.order ? (int64_t)a.order[pos] : pos, lds);
+        if (pos < end) run_mixed_range_item<TRACE, LONG>(a, pos, lds);
     }
 }
 
@@ -221,39 +248,48 @@ hipError_t launch_tabu_part(const TabuLaunchArgs &a, int64_t begin, int64_t end,
                : launch_tabu_part_t<NW, NB, WPG, false>(a, begin, end, groups, counter, s);
 }
 
-template <int WPG, bool TRACE>
+template <int WPG, bool TRACE, bool LONG>
 hipError_t launch_mixed_t(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
                           uint32_t *counter, hipStream_t s) {
     if (groups > 0) {
         hipError_t e = launch_fill_u32(counter, 0u, 1, s);
         if (e != hipSuccess) return e;
         const int64_t need = (end - begin + WPG - 1) / WPG;
-        hipLaunchKernelGGL((tabu_kernel_mixed<WPG, true, TRACE>),
+        hipLaunchKernelGGL((tabu_kernel_mixed<WPG, true, TRACE, LONG>),
                            dim3((unsigned)std::min<int64_t>(groups, need)), dim3(64 * WPG), 0, s, a,
                            begin, end, counter);
     } else {
         const int64_t grid = (end - begin + WPG - 1) / WPG;
-        hipLaunchKernelGGL((tabu_kernel_mixed<WPG, false, TRACE>), dim3((unsigned)grid),
+        hipLaunchKernelGGL((tabu_kernel_mixed<WPG, false, TRACE, LONG>), dim3((unsigned)grid),
                            dim3(64 * WPG), 0, s, a, begin, end, counter);
     }
     return hipGetLastError();
 }
 
 // One launch per non-empty length class, each on its own stream with its
-// own queue head (32 words apart).
+// own queue head (32 words apart); mixed ranges of classes 0..1 and 2..5
+// take one launch each.
 template <int WPG>
 hipError_t launch_tabu_wpg(const TabuLaunchArgs &a, int groups, const hipStream_t *st) {
     static_assert(kWalkClasses == 6, "one launcher per class below");
     const int64_t *ce = a.class_end;
     uint32_t *q = a.counter;
-    hipError_t e = launch_tabu_part<4, 16, WPG>(a, 0, ce[0], groups, q, st[0]);
-    if (e == hipSuccess) e = launch_tabu_part<4, 12, WPG>(a, ce[0], ce[1], groups, q + 32, st[1]);
+    hipError_t e = hipSuccess;
+    if (mixed_long_classes(ce)) {
+        // classes 0 and 1 share one launch, on class 0's stream
+        e = a.trace != nullptr ? launch_mixed_t<WPG, true, true>(a, 0, ce[1], groups, q, st[0])
+                               : launch_mixed_t<WPG, false, true>(a, 0, ce[1], groups, q, st[0]);
+    } else {
+        e = launch_tabu_part<4, 16, WPG>(a, 0, ce[0], groups, q, st[0]);
+        if (e == hipSuccess)
+            e = launch_tabu_part<4, 12, WPG>(a, ce[0], ce[1], groups, q + 32, st[1]);
+    }
     if (e != hipSuccess) return e;
     if (mixed_short_classes(ce)) {
         // classes 2..5 share one launch, on class 2's stream
         return a.trace != nullptr
-                   ? launch_mixed_t<WPG, true>(a, ce[1], ce[5], groups, q + 64, st[2])
-                   : launch_mixed_t<WPG, false>(a, ce[1], ce[5], groups, q + 64, st[2]);
+                   ? launch_mixed_t<WPG, true, false>(a, ce[1], ce[5], groups, q + 64, st[2])
+                   : launch_mixed_t<WPG, false, false>(a, ce[1], ce[5], groups, q + 64, st[2]);
     }
     e = launch_tabu_part<2, 8, WPG>(a, ce[1], ce[2], groups, q + 64, st[2]);
     if (e == hipSuccess) e = launch_tabu_part<2, 6, WPG>(a, ce[2], ce[3], groups, q + 96, st[3]);

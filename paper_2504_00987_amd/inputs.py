@@ -97,7 +97,10 @@ TABU_N64 = TabuWorkload("tabu_n64", 4096, 64, rules=rules_tabu(4), seed=1001)
 TABU_UNEVEN = TabuWorkload("tabu_uneven", 8192, None, 48, 120, rules=rules_tabu(3), seed=1002)
 # The longest class (four neighbours per lane), same rules as tabu_n64.
 TABU_N256 = TabuWorkload("tabu_n256", 4096, 256, rules=rules_tabu(4), seed=1005)
-TABU_WORKLOADS = {w.name: w for w in (TABU_N64, TABU_UNEVEN, TABU_N256)}
+# Both classes of N > 128 (four neighbours per lane), mixed.
+TABU_LONG_UNEVEN = TabuWorkload("tabu_long_uneven", 4096, None, 129, 256, rules=rules_tabu(4),
+                                seed=1007)
+TABU_WORKLOADS = {w.name: w for w in (TABU_N64, TABU_UNEVEN, TABU_N256, TABU_LONG_UNEVEN)}
 MEMETIC_N20 = MemeticWorkload("memetic_n20", 20, 100, 1, 50, seed=1000)
 MEMETIC_N120 = MemeticWorkload("memetic_n120", 120, 100, 256, 100000, seed=1003)
 SERVING_SEED = 1004

@@ -229,13 +229,15 @@ def test_tabu_n64_full_size(lb):
     assert np.array_equal(res.best_seq.cpu().numpy(), best)
 
 
-def test_tabu_uneven_full_size_sampled(lb):
-    wl = I.TABU_UNEVEN
+@pytest.mark.parametrize("name,n_sample", [("tabu_uneven", 256), ("tabu_long_uneven", 48)])
+def test_tabu_uneven_full_size_sampled(lb, name, n_sample):
+    # tabu_long_uneven: both N > 128 classes, mixed in one launch
+    wl = I.TABU_WORKLOADS[name]
     ns = wl.lengths()
     say(f"tabu: {wl.name} full size W={wl.walks}, sampled walks against the oracle")
     res = lb.tabu_batch(wl.rules, wl.walks, wl.seed, ns=ns)
     rng = np.random.default_rng(5)
-    sample = np.sort(rng.choice(wl.walks, size=256, replace=False))
+    sample = np.sort(rng.choice(wl.walks, size=n_sample, replace=False))
     sample = np.unique(np.concatenate([sample, [0, wl.walks - 1], np.argsort(-ns)[:4]]))
     sch = osched(wl.rules)
     be_g = res.best_e.cpu().numpy()
