@@ -500,6 +500,24 @@ def test_tabu_long_extreme_starts(lb, launch):
         assert np.array_equal(tr[w, : len(trs[w])], trs[w])
 
 
+@pytest.mark.parametrize("launch", [(1, 0, 0), (2, 0, 0), (4, 0, 0), (1, 1, 0), (2, 1, 1), (4, 1, 2)])
+def test_tabu_long_launch_invariance(lb, launch):
+    # both N > 128 classes in one batch: their single launch, every form
+    say(f"tabu: N in 129..256, launch configuration {launch} gives identical walks")
+    ns = I.uneven_lengths(120, 129, 256, seed=43)
+    assert ns.min() <= 193 < ns.max()
+    rules = I.rules_tabu(2)
+    lb.set_launch(*launch)
+    try:
+        res = lb.tabu_batch(rules, len(ns), 77, ns=ns, out_stride=256)
+    finally:
+        lb.set_launch(None)
+    best, be, fe = O.tabu_batch(len(ns), osched(rules), 77, ns=ns, stride=256, nthreads=16)
+    assert np.array_equal(res.best_e.cpu().numpy(), be)
+    assert np.array_equal(res.final_e.cpu().numpy(), fe)
+    assert np.array_equal(res.best_seq.cpu().numpy(), best)
+
+
 def test_tabu_all_classes_ragged(lb):
     ns = I.uneven_lengths(240, 3, 256, seed=41)
     say("tabu: ragged N in 3..256 (all six length classes), Philox starts")
