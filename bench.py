@@ -47,10 +47,9 @@ KERNEL_SOURCES = ("paper_2504_00987_amd/csrc/labs_device.hpp",
 # 1.0x of the bytes moved).  The summaries live in profiles/.
 COPY_SCALE = {"FETCH_SIZE": 262144 / 131087, "WRITE_SIZE": 262144 / 262144}
 COUNTERS = {
-    # per launch in the default launch configuration (four walks per
-    # workgroup), mean over the profiled dispatches; sums over the kernels
-    # of one call (the uneven batch runs one kernel per length class,
-    # concurrently)
+    # per call in the default launch configuration, mean over the profiled
+    # dispatches; summed over the kernels of one call (a batch with walks
+    # on both sides of N = 128 runs two, concurrently)
     "tabu_n64": {"digest": "f71d5cbffbfaf0fc", "FETCH_SIZE": 80.5, "WRITE_SIZE": 768.0,
         "SQ_INSTS_VALU": 45513148, "SQ_INSTS_LDS": 13721600,
         "SQ_LDS_BANK_CONFLICT": 2847176,
@@ -63,6 +62,10 @@ COUNTERS = {
         "SQ_INSTS_VALU": 2027584427, "SQ_INSTS_LDS": 541691904,
         "SQ_LDS_BANK_CONFLICT": 4194304,
         "source": "profiles/tabu_kernel_counters.md"},
+    "tabu_long_uneven": {"digest": "f71d5cbffbfaf0fc", "FETCH_SIZE": 439.5, "WRITE_SIZE": 1184.9,
+        "SQ_INSTS_VALU": 1391622528, "SQ_INSTS_LDS": 368409501,
+        "SQ_LDS_BANK_CONFLICT": 114441374,
+        "source": "profiles/tabu_kernel_long_uneven_kernel_trace.md"},
 }
 
 
