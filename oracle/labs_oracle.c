@@ -252,8 +252,17 @@ void orc_neighbour_energies_tables(const int8_t *s, int n, int64_t *out)
 /* ------------------------------------------------------------------------- */
 /* Walk schedule: walk length maxIter and tenure range [minTabu, maxTabu].    */
 /* ------------------------------------------------------------------------- */
-enum { ORC_STEPS_FIXED = 0, ORC_STEPS_MULT_N = 1, ORC_STEPS_PAPER = 2 };
+enum { ORC_STEPS_FIXED = 0, ORC_STEPS_MULT_N = 1, ORC_STEPS_PAPER = 2, ORC_STEPS_RANGE = 3 };
 enum { ORC_TENURE_LINEAR = 0, ORC_TENURE_PAPER = 1 };
+
+/* The parameters of a walk (Alg. 2): how maxIter and the tenure range are
+ * obtained for a length n, and whether aspiration is on. */
+typedef struct {
+    int steps_rule, steps_a, tenure_rule;
+    int lo_num, lo_den, lo_add, hi_num, hi_den, hi_add;
+    int aspiration;
+    int slo_num, slo_den, shi_num, shi_den; /* ORC_STEPS_RANGE bounds */
+} orc_rule_t;
 
 /*
  * steps_rule
@@ -261,6 +270,11 @@ enum { ORC_TENURE_LINEAR = 0, ORC_TENURE_PAPER = 1 };
  *   MULT_N: maxIter = a * n
  *   PAPER : maxIter = randomInt(0, n) + floor(n/2) (Alg. 4, both ends
  *           inclusive), one draw (entity, gen, 0, TAG_LEN), word 0.
+ *   RANGE : maxIter uniform in [floor(slo_num*n/slo_den),
+ *           floor(shi_num*n/shi_den)] (both ends inclusive) from the same
+ *           draw: lo + ((w0 * (hi - lo + 1)) >> 32).  Sec. III.B states the
+ *           walk length as randInt[N/2, 3N/2]; RANGE(1/2, 3/2) is that
+ *           statement.
  * tenure_rule
  *   LINEAR: minTabu = floor(lo_num*n/lo_den) + lo_add,
  *           maxTabu = floor(hi_num*n/hi_den) + hi_add
@@ -268,31 +282,37 @@ enum { ORC_TENURE_LINEAR = 0, ORC_TENURE_PAPER = 1 };
  *           (Sec. III.B), in integers floor(T/10) and floor(3T/25).
  * Returns 0, or -1 when the schedule is invalid (0 <= lo <= hi < n fails).
  */
-int orc_walk_schedule(int n, int steps_rule, int steps_a, int tenure_rule,
-                      int lo_num, int lo_den, int lo_add,
-                      int hi_num, int hi_den, int hi_add,
-                      uint64_t seed, uint32_t entity, uint32_t gen,
-                      int *steps, int *lo, int *hi)
+int orc_walk_schedule(int n, const orc_rule_t *r, uint64_t seed, uint32_t entity,
+                      uint32_t gen, int *steps, int *lo, int *hi)
 {
     int T;
-    if (steps_rule == ORC_STEPS_FIXED) {
-        T = steps_a;
-    } else if (steps_rule == ORC_STEPS_MULT_N) {
-        T = steps_a * n;
-    } else if (steps_rule == ORC_STEPS_PAPER) {
+    if (r->steps_rule == ORC_STEPS_FIXED) {
+        T = r->steps_a;
+    } else if (r->steps_rule == ORC_STEPS_MULT_N) {
+        T = r->steps_a * n;
+    } else if (r->steps_rule == ORC_STEPS_PAPER) {
         uint32_t w[4];
         draw(seed, entity, gen, 0, ORC_TAG_LEN, w);
         T = n / 2 + (int)uniform_below(w[0], (uint32_t)(n + 1));
+    } else if (r->steps_rule == ORC_STEPS_RANGE) {
+        if (r->slo_den <= 0 || r->shi_den <= 0 || r->slo_num < 0 || r->shi_num < 0)
+            return -1;
+        int tlo = r->slo_num * n / r->slo_den, thi = r->shi_num * n / r->shi_den;
+        if (thi < tlo)
+            return -1;
+        uint32_t w[4];
+        draw(seed, entity, gen, 0, ORC_TAG_LEN, w);
+        T = tlo + (int)uniform_below(w[0], (uint32_t)(thi - tlo + 1));
     } else {
         return -1;
     }
     int l, h;
-    if (tenure_rule == ORC_TENURE_LINEAR) {
-        if (lo_den <= 0 || hi_den <= 0)
+    if (r->tenure_rule == ORC_TENURE_LINEAR) {
+        if (r->lo_den <= 0 || r->hi_den <= 0)
             return -1;
-        l = lo_num * n / lo_den + lo_add;
-        h = hi_num * n / hi_den + hi_add;
-    } else if (tenure_rule == ORC_TENURE_PAPER) {
+        l = r->lo_num * n / r->lo_den + r->lo_add;
+        h = r->hi_num * n / r->hi_den + r->hi_add;
+    } else if (r->tenure_rule == ORC_TENURE_PAPER) {
         l = T / 10;
         h = 3 * T / 25;
     } else {
@@ -338,14 +358,16 @@ void orc_random_start(int n, uint64_t seed, uint32_t walk, int8_t *s)
  * recompute = 1 scores every neighbour from Eq. (2) directly; recompute = 0
  * uses tableC/vectorC (Sec. III.C).  Both must give identical walks.
  * trace[t-1] (optional) receives the flipped index, trace_e[t-1] (optional)
- * the energy after step t.
+ * the energy after step t, trace_x[t-1] (optional) the tabuList entry the
+ * flipped index receives at step t (the last step at which it is tabu).
  * Returns 0, or -1 if a step has no admissible move (cannot happen when
  * hi < n: at most hi bits are tabu at any step).
  */
 int orc_tabu_walk(int n, const int8_t *start, uint64_t seed, uint32_t entity,
                   uint32_t gen, int steps, int lo, int hi, int aspiration,
                   int recompute, int8_t *best, int64_t *best_e,
-                  int64_t *final_e, int16_t *trace, int64_t *trace_e)
+                  int64_t *final_e, int16_t *trace, int64_t *trace_e,
+                  int64_t *trace_x)
 {
     int8_t pivot[ORC_MAX_N];
     int64_t tabu[ORC_MAX_N];
@@ -410,6 +432,8 @@ int orc_tabu_walk(int n, const int8_t *start, uint64_t seed, uint32_t entity,
             trace[t - 1] = (int16_t)pick;
         if (trace_e)
             trace_e[t - 1] = E;
+        if (trace_x)
+            trace_x[t - 1] = tabu[pick];
     }
     free(T);
     *best_e = bestE;
@@ -427,9 +451,7 @@ typedef struct {
     const int8_t *starts; /* [W][stride] or NULL for random starts */
     int32_t stride;
     uint64_t seed;
-    int steps_rule, steps_a, tenure_rule;
-    int lo_num, lo_den, lo_add, hi_num, hi_den, hi_add;
-    int aspiration;
+    orc_rule_t rule;
     int8_t *best_seq;     /* [W][stride], positions >= n are set to 0 */
     int64_t *best_e;
     int64_t *final_e;
@@ -445,10 +467,7 @@ static int run_one_walk(batch_job_t *J, int64_t w)
     int steps, lo, hi;
     if (n < 3 || n > ORC_MAX_N || n > J->stride)
         return -1;
-    if (orc_walk_schedule(n, J->steps_rule, J->steps_a, J->tenure_rule,
-                          J->lo_num, J->lo_den, J->lo_add,
-                          J->hi_num, J->hi_den, J->hi_add,
-                          J->seed, (uint32_t)w, 0, &steps, &lo, &hi))
+    if (orc_walk_schedule(n, &J->rule, J->seed, (uint32_t)w, 0, &steps, &lo, &hi))
         return -1;
     if (J->starts)
         memcpy(start, J->starts + w * J->stride, (size_t)n);
@@ -457,8 +476,8 @@ static int run_one_walk(batch_job_t *J, int64_t w)
     int8_t *out = J->best_seq + w * J->stride;
     memset(out, 0, (size_t)J->stride);
     return orc_tabu_walk(n, start, J->seed, (uint32_t)w, 0, steps, lo, hi,
-                         J->aspiration, 0, out, &J->best_e[w], &J->final_e[w],
-                         NULL, NULL);
+                         J->rule.aspiration, 0, out, &J->best_e[w], &J->final_e[w],
+                         NULL, NULL, NULL);
 }
 
 static void *batch_worker(void *arg)
@@ -481,9 +500,7 @@ static void *batch_worker(void *arg)
 
 int orc_tabu_batch(int64_t W, const int32_t *ns, int32_t n_uniform,
                    const int8_t *starts, int32_t stride, uint64_t seed,
-                   int steps_rule, int steps_a, int tenure_rule,
-                   int lo_num, int lo_den, int lo_add,
-                   int hi_num, int hi_den, int hi_add, int aspiration,
+                   const orc_rule_t *rule,
                    int8_t *best_seq, int64_t *best_e, int64_t *final_e,
                    int nthreads)
 {
@@ -491,10 +508,7 @@ int orc_tabu_batch(int64_t W, const int32_t *ns, int32_t n_uniform,
     memset(&J, 0, sizeof(J));
     J.W = W; J.ns = ns; J.n_uniform = n_uniform; J.starts = starts;
     J.stride = stride; J.seed = seed;
-    J.steps_rule = steps_rule; J.steps_a = steps_a; J.tenure_rule = tenure_rule;
-    J.lo_num = lo_num; J.lo_den = lo_den; J.lo_add = lo_add;
-    J.hi_num = hi_num; J.hi_den = hi_den; J.hi_add = hi_add;
-    J.aspiration = aspiration;
+    J.rule = *rule;
     J.best_seq = best_seq; J.best_e = best_e; J.final_e = final_e;
     pthread_mutex_init(&J.lock, NULL);
     if (nthreads < 1)
@@ -574,10 +588,7 @@ static int tournament(const int64_t *popE, int K, uint32_t u, uint32_t v)
  * Returns the number of generations executed, or -1 on an invalid schedule.
  */
 int64_t orc_memetic_advance(int n, int K, uint32_t p_comb, uint32_t p_mut,
-                            int steps_rule, int steps_a, int tenure_rule,
-                            int lo_num, int lo_den, int lo_add,
-                            int hi_num, int hi_den, int hi_add, int aspiration,
-                            uint64_t seed, uint32_t pop_id, int64_t g0,
+                            const orc_rule_t *rule, uint64_t seed, uint32_t pop_id, int64_t g0,
                             int64_t n_gens, int64_t target,
                             int8_t *pop, int64_t *popE, int8_t *best,
                             int64_t *best_e, int64_t *hit_gen)
@@ -612,13 +623,11 @@ int64_t orc_memetic_advance(int n, int K, uint32_t p_comb, uint32_t p_mut,
                 child[i] = (int8_t)-child[i];
         }
         int steps, lo, hi;
-        if (orc_walk_schedule(n, steps_rule, steps_a, tenure_rule, lo_num, lo_den,
-                              lo_add, hi_num, hi_den, hi_add, seed, pop_id,
-                              (uint32_t)g, &steps, &lo, &hi))
+        if (orc_walk_schedule(n, rule, seed, pop_id, (uint32_t)g, &steps, &lo, &hi))
             return -1;
         int64_t ce, fe;
         if (orc_tabu_walk(n, child, seed, pop_id, (uint32_t)g, steps, lo, hi,
-                          aspiration, 0, child_best, &ce, &fe, NULL, NULL))
+                          rule->aspiration, 0, child_best, &ce, &fe, NULL, NULL, NULL))
             return -1;
         if (ce < *best_e) {
             *best_e = ce;
@@ -651,10 +660,7 @@ int64_t orc_memetic_advance(int n, int K, uint32_t p_comb, uint32_t p_mut,
  * generations.  Returns the generations executed or -1.
  */
 int64_t orc_memetic_advance_batched(int n, int K, int B, uint32_t p_comb, uint32_t p_mut,
-                                    int steps_rule, int steps_a, int tenure_rule,
-                                    int lo_num, int lo_den, int lo_add,
-                                    int hi_num, int hi_den, int hi_add, int aspiration,
-                                    uint64_t seed, uint32_t pop_id, int64_t g0,
+                                    const orc_rule_t *rule, uint64_t seed, uint32_t pop_id, int64_t g0,
                                     int64_t n_gens, int64_t target,
                                     int8_t *pop, int64_t *popE, int8_t *best,
                                     int64_t *best_e, int64_t *hit_gen)
@@ -694,13 +700,11 @@ int64_t orc_memetic_advance_batched(int n, int K, int B, uint32_t p_comb, uint32
             }
             const uint32_t walk_gen = (uint32_t)(g * B + b);
             int steps, lo, hi;
-            if (orc_walk_schedule(n, steps_rule, steps_a, tenure_rule, lo_num, lo_den,
-                                  lo_add, hi_num, hi_den, hi_add, seed, pop_id, walk_gen,
-                                  &steps, &lo, &hi))
+            if (orc_walk_schedule(n, rule, seed, pop_id, walk_gen, &steps, &lo, &hi))
                 return -1;
             int64_t fe;
-            if (orc_tabu_walk(n, child, seed, pop_id, walk_gen, steps, lo, hi, aspiration, 0,
-                              kids[b], &kid_e[b], &fe, NULL, NULL))
+            if (orc_tabu_walk(n, child, seed, pop_id, walk_gen, steps, lo, hi,
+                              rule->aspiration, 0, kids[b], &kid_e[b], &fe, NULL, NULL, NULL))
                 return -1;
             kid_slot[b] = (int)uniform_below(wb[2], (uint32_t)K);
         }

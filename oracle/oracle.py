@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "labs_oracle.c")
 _SO = os.path.join(_HERE, "liboracle.so")
 MAX_N = 256  # longest sequence of the walk and memetic routines
 
-STEPS_FIXED, STEPS_MULT_N, STEPS_PAPER = 0, 1, 2
+STEPS_FIXED, STEPS_MULT_N, STEPS_PAPER, STEPS_RANGE = 0, 1, 2, 3
 TENURE_LINEAR, TENURE_PAPER = 0, 1
 TAG_START, TAG_STEP, TAG_LEN, TAG_INIT, TAG_GEN, TAG_MUT = 1, 2, 3, 4, 5, 6
 
@@ -57,20 +57,19 @@ def lib():
         L.orc_skew_deviation.argtypes = [P, ctypes.c_int, ctypes.c_int]
         L.orc_neighbour_energies_recompute.argtypes = [P, ctypes.c_int, P]
         L.orc_neighbour_energies_tables.argtypes = [P, ctypes.c_int, P]
-        L.orc_walk_schedule.argtypes = [ctypes.c_int] * 10 + [u64, u32, u32, P, P, P]
+        R = ctypes.POINTER(_Rule)
+        L.orc_walk_schedule.argtypes = [ctypes.c_int, R, u64, u32, u32, P, P, P]
         L.orc_random_start.argtypes = [ctypes.c_int, u64, u32, P]
         L.orc_tabu_walk.argtypes = [ctypes.c_int, P, u64, u32, u32, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                    ctypes.c_int, P, P, P, P, P]
-        L.orc_tabu_batch.argtypes = [i64, P, i32, P, i32, u64] + [ctypes.c_int] * 10 + \
-            [P, P, P, ctypes.c_int]
+                                    ctypes.c_int, P, P, P, P, P, P]
+        L.orc_tabu_batch.argtypes = [i64, P, i32, P, i32, u64, R, P, P, P, ctypes.c_int]
         L.orc_memetic_init.argtypes = [ctypes.c_int, ctypes.c_int, u64, u32, P, P, P, P]
-        L.orc_memetic_advance.argtypes = [ctypes.c_int, ctypes.c_int, u32, u32] + \
-            [ctypes.c_int] * 10 + [u64, u32, i64, i64, i64, P, P, P, P, P]
+        L.orc_memetic_advance.argtypes = [ctypes.c_int, ctypes.c_int, u32, u32, R,
+                                          u64, u32, i64, i64, i64, P, P, P, P, P]
         L.orc_memetic_advance.restype = i64
         L.orc_memetic_advance_batched.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, u32,
-                                                  u32] + [ctypes.c_int] * 10 + \
-            [u64, u32, i64, i64, i64, P, P, P, P, P]
+                                                  u32, R, u64, u32, i64, i64, i64, P, P, P, P, P]
         L.orc_memetic_advance_batched.restype = i64
         _lib = L
     return _lib
@@ -80,9 +79,19 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+_RULE_FIELDS = ("steps_rule", "steps_a", "tenure_rule", "lo_num", "lo_den", "lo_add",
+                "hi_num", "hi_den", "hi_add", "aspiration", "slo_num", "slo_den", "shi_num",
+                "shi_den")
+
+
+class _Rule(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int) for f in _RULE_FIELDS]
+
+
 @dataclass(frozen=True)
 class Schedule:
-    """Walk length and tenure rule (see ``orc_walk_schedule``)."""
+    """Walk length and tenure rule (see ``orc_walk_schedule``); the last four
+    fields bound the walk length of STEPS_RANGE."""
     steps_rule: int = STEPS_MULT_N
     steps_a: int = 4
     tenure_rule: int = TENURE_LINEAR
@@ -93,10 +102,13 @@ class Schedule:
     hi_den: int = 5
     hi_add: int = 0
     aspiration: int = 1
+    slo_num: int = 0
+    slo_den: int = 1
+    shi_num: int = 0
+    shi_den: int = 1
 
-    def rule_args(self):
-        return (self.steps_rule, self.steps_a, self.tenure_rule, self.lo_num,
-                self.lo_den, self.lo_add, self.hi_num, self.hi_den, self.hi_add)
+    def rule(self) -> "_Rule":
+        return _Rule(*(getattr(self, f) for f in _RULE_FIELDS))
 
 
 def philox4x32_10(ctr, key) -> np.ndarray:
@@ -176,7 +188,8 @@ def walk_schedule(n: int, sched: Schedule, seed: int, entity: int, gen: int):
     T = np.zeros(1, dtype=np.int32)
     lo = np.zeros(1, dtype=np.int32)
     hi = np.zeros(1, dtype=np.int32)
-    rc = lib().orc_walk_schedule(n, *sched.rule_args(), seed, entity, gen, _p(T), _p(lo), _p(hi))
+    r = sched.rule()
+    rc = lib().orc_walk_schedule(n, ctypes.byref(r), seed, entity, gen, _p(T), _p(lo), _p(hi))
     if rc != 0:
         raise ValueError("invalid walk schedule")
     return int(T[0]), int(lo[0]), int(hi[0])
@@ -189,8 +202,11 @@ def random_start(n: int, seed: int, walk: int) -> np.ndarray:
 
 
 def tabu_walk(start, seed: int, entity: int, gen: int, steps: int, lo: int, hi: int,
-              aspiration: int = 1, recompute: bool = False, want_trace: bool = False):
-    """One walk; returns (best, best_e, final_e, trace, trace_e)."""
+              aspiration: int = 1, recompute: bool = False, want_trace: bool = False,
+              want_expiry: bool = False):
+    """One walk; returns (best, best_e, final_e, trace, trace_e), and with
+    want_expiry a sixth entry: the tabuList value the move of step t receives
+    (the last step at which it is tabu), one per step."""
     s = _seq(start)
     n = len(s)
     best = np.zeros(n, dtype=np.int8)
@@ -198,13 +214,17 @@ def tabu_walk(start, seed: int, entity: int, gen: int, steps: int, lo: int, hi: 
     fe = np.zeros(1, dtype=np.int64)
     tr = np.zeros(max(steps, 1), dtype=np.int16) if want_trace else None
     te = np.zeros(max(steps, 1), dtype=np.int64) if want_trace else None
+    tx = np.zeros(max(steps, 1), dtype=np.int64) if want_expiry else None
     rc = lib().orc_tabu_walk(n, _p(s), seed, entity, gen, steps, lo, hi, aspiration,
                              1 if recompute else 0, _p(best), _p(be), _p(fe),
-                             None if tr is None else _p(tr), None if te is None else _p(te))
+                             None if tr is None else _p(tr), None if te is None else _p(te),
+                             None if tx is None else _p(tx))
     if rc != 0:
         raise ValueError("walk failed (invalid arguments or no admissible move)")
     if want_trace:
         tr, te = tr[:steps], te[:steps]
+    if want_expiry:
+        return best, int(be[0]), int(fe[0]), tr, te, tx[:steps]
     return best, int(be[0]), int(fe[0]), tr, te
 
 
@@ -218,9 +238,9 @@ def tabu_batch(W: int, sched: Schedule, seed: int, ns=None, n_uniform: int = 0,
     best = np.zeros((W, stride), dtype=np.int8)
     be = np.zeros(W, dtype=np.int64)
     fe = np.zeros(W, dtype=np.int64)
+    r = sched.rule()
     rc = lib().orc_tabu_batch(W, None if nsa is None else _p(nsa), n_uniform,
-                              None if st is None else _p(st), stride, seed,
-                              *sched.rule_args(), sched.aspiration,
+                              None if st is None else _p(st), stride, seed, ctypes.byref(r),
                               _p(best), _p(be), _p(fe), nthreads)
     if rc != 0:
         raise ValueError("tabu batch failed")
@@ -246,14 +266,15 @@ class MemeticState:
         """Alg. 1 generations (children == 0), or the batched-generation
         variant with `children` children per generation (1 reproduces Alg. 1
         through the batched code)."""
+        r = sched.rule()
         if children == 0:
             done = lib().orc_memetic_advance(
-                self.n, self.K, p_comb, p_mut, *sched.rule_args(), sched.aspiration,
+                self.n, self.K, p_comb, p_mut, ctypes.byref(r),
                 self.seed, self.pop_id, self.gen, n_gens, target, _p(self.pop),
                 _p(self.popE), _p(self.best), _p(self.best_e), _p(self.hit_gen))
         else:
             done = lib().orc_memetic_advance_batched(
-                self.n, self.K, children, p_comb, p_mut, *sched.rule_args(), sched.aspiration,
+                self.n, self.K, children, p_comb, p_mut, ctypes.byref(r),
                 self.seed, self.pop_id, self.gen, n_gens, target, _p(self.pop),
                 _p(self.popE), _p(self.best), _p(self.best_e), _p(self.hit_gen))
         if done < 0:

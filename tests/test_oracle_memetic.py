@@ -9,6 +9,7 @@ early-stop generation is the first one at which the target holds, and no run
 beats the exhaustive optimum.
 """
 import numpy as np
+import pytest
 
 from oracle import oracle as O
 from tests import npref
@@ -207,7 +208,7 @@ def test_batched_invariants_and_resume():
         assert st.bestE <= st.popE.min()
     full.advance(12, MEM, O.P_COMB_090, O.p_mut_inv_n(n), children=B)
     assert full.bestE == st.bestE and np.array_equal(full.pop, st.pop)
-    # mutation words of child b come from index 32 b + i/4: with every
+    # mutation words of child b come from index 64 b + i/4: with every
     # other draw fixed, a different B changes the children after the first
     other = O.MemeticState(n, K, 11, 2)
     other.advance(12, MEM, O.P_COMB_090, O.p_mut_inv_n(n), children=B - 1)
@@ -231,3 +232,159 @@ def test_batched_target_counts_generations():
     stop = base.copy()
     stop.advance(40, MEM, O.P_COMB_090, O.p_mut_inv_n(n), target=target, children=B)
     assert stop.hit == first and stop.gen == first and stop.bestE <= target
+
+
+# ---------------------------------------------------------------------------
+# The generation's draws: parents, cut, sampled member and replaced slot.
+# ---------------------------------------------------------------------------
+ZERO_WALK = O.Schedule(O.STEPS_FIXED, 0, O.TENURE_LINEAR, 0, 1, 0, 0, 1, 0, 1)
+M32 = 0xFFFFFFFF
+
+
+def _gen_words(seed, pid, g):
+    # words w0..w7 of generation g: draws (pid, g, 0 | 1, GEN), pure-Python Philox
+    key = [seed & M32, seed >> 32]
+    return (npref.philox([pid, g, 0, O.TAG_GEN], key) +
+            npref.philox([pid, g, 1, O.TAG_GEN], key))
+
+
+@pytest.mark.parametrize("n,K,p_comb", [(8, 30, 0xFFFFFFFF), (8, 30, O.P_COMB_090),
+                                        (13, 7, 0xFFFFFFFF), (40, 100, O.P_COMB_090)])
+def test_generation_rebuilt_from_draws(n, K, p_comb):
+    # Mutation off and zero-step walks: each child is the crossover of two
+    # tournament winners (lower energy wins, a tie goes to the first draw)
+    # cut at 1 + ((w5 (N-1)) >> 32), or the member (w1 K) >> 32 when
+    # w0 >= p_comb; it replaces member (w6 K) >> 32 (readings of Alg. 1's
+    # selectParents, Combine and replacement).  The population is rebuilt
+    # here generation by generation with numpy energies and compared exactly.
+    seed, pid, G = 123457, 3, 400
+    st = O.MemeticState(n, K, seed, pid)
+    pop = st.pop.astype(np.int64)
+    popE = npref.energies_rows(pop)
+    bestE = int(popE.min())
+    # how often a plausible misreading would have changed the child
+    tie_matters = cut_matters = 0
+    for g in range(G):
+        w = _gen_words(seed, pid, g)
+
+        def tour(u, v):
+            i, j = (u * K) >> 32, (v * K) >> 32
+            return i if popE[i] <= popE[j] else j
+
+        if w[0] < p_comb:
+            a, b = tour(w[1], w[2]), tour(w[3], w[4])
+            cut = 1 + ((w[5] * (n - 1)) >> 32)
+            child = np.concatenate([pop[a, :cut], pop[b, cut:]])
+            i, j = (w[1] * K) >> 32, (w[2] * K) >> 32
+            if i != j and popE[i] == popE[j] and not np.array_equal(pop[i, :cut], pop[j, :cut]):
+                tie_matters += 1
+            alt = (w[5] * n) >> 32  # the cut over [0, N) instead of [1, N-1]
+            if alt != cut and not np.array_equal(pop[a, min(alt, cut):max(alt, cut)],
+                                                 pop[b, min(alt, cut):max(alt, cut)]):
+                cut_matters += 1
+        else:
+            child = pop[(w[1] * K) >> 32].copy()
+        e = npref.energy(child)
+        bestE = min(bestE, e)
+        r = (w[6] * K) >> 32
+        pop[r], popE[r] = child, e
+        assert st.advance(1, ZERO_WALK, p_comb, 0) == 1
+        assert np.array_equal(st.pop, pop), g
+        assert np.array_equal(st.popE, popE) and st.bestE == bestE, g
+    if p_comb == 0xFFFFFFFF and n == 8:
+        assert tie_matters > 20 and cut_matters > 20
+
+
+def _two_member_trials(n, m0, m1, e0, e1, trials, seed=99):
+    # K = 2 with members m0, m1 restored before every generation, crossover
+    # forced, mutation off, zero-step walks: the children of `trials`
+    # consecutive generations.  The tournament reads only the energy array,
+    # so the members get the stand-in energies e0, e1 (< floor(N/2), below
+    # every real energy); the child's slot is the one whose energy changed.
+    st = O.MemeticState(n, 2, seed, 0)
+    base = np.stack([m0, m1]).astype(np.int8)
+    out = np.zeros((trials, n), dtype=np.int8)
+    for t in range(trials):
+        st.pop[:] = base
+        st.popE[:] = [e0, e1]
+        st.best[:] = m0
+        st.best_e[0] = min(e0, e1)
+        st.advance(1, ZERO_WALK, 0xFFFFFFFF, 0)
+        r = [k for k in range(2) if st.popE[k] != (e0, e1)[k]]
+        assert len(r) == 1 and st.popE[r[0]] == npref.energy(st.pop[r[0]])
+        out[t] = st.pop[r[0]]
+    return out
+
+
+def test_tournament_prefers_lower_energy():
+    # Binary tournament with replacement between a better and a worse
+    # member: the better one wins unless both draws name the worse one, so
+    # each parent is the better member with probability 3/4 (a reversed
+    # comparison gives 1/4, no comparison 1/2).  The members differ at every
+    # position, so the child's first entry names the first parent and its
+    # last entry the second (the cut lies in 1..N-1).
+    n = 24
+    rng = np.random.default_rng(4)
+    m0 = (1 - 2 * rng.integers(0, 2, n)).astype(np.int8)
+    trials = 6000
+    kids = _two_member_trials(n, m0, -m0, 0, 1, trials)
+    first = np.mean(kids[:, 0] == m0[0])
+    second = np.mean(kids[:, n - 1] == m0[n - 1])
+    sd = np.sqrt(0.75 * 0.25 / trials)
+    assert abs(first - 0.75) < 5 * sd and abs(second - 0.75) < 5 * sd, (first, second)
+    # the two tournaments draw independently
+    both = np.mean((kids[:, 0] == m0[0]) & (kids[:, n - 1] == m0[n - 1]))
+    assert abs(both - 0.5625) < 5 * np.sqrt(0.5625 * 0.4375 / trials), both
+
+
+def test_crossover_cut_uniform():
+    # Two members of equal energy that differ everywhere: every tournament is
+    # a tie, so the parents are two independent uniform picks; half the
+    # children are copies, and when the parents differ the cut -- the first
+    # position taken from the second parent -- is uniform over 1..N-1 (a cut
+    # drawn over 0..N-1 or 1..N would add copies: cut 0 or N).
+    n = 6
+    rng = np.random.default_rng(8)
+    m0 = (1 - 2 * rng.integers(0, 2, n)).astype(np.int8)
+    trials = 20000
+    kids = _two_member_trials(n, m0, -m0, 1, 1, trials)
+    copies = np.all(kids == m0, axis=1) | np.all(kids == -m0, axis=1)
+    frac = copies.mean()
+    assert abs(frac - 0.5) < 5 * np.sqrt(0.25 / trials), frac
+    splices = kids[~copies]
+    first = np.where(splices[:, :1] == m0[0], m0, -m0)  # the first parent
+    cuts = np.argmax(splices != first, axis=1)  # first entry of the second parent
+    assert cuts.min() >= 1
+    hist = np.bincount(cuts, minlength=n)[1:n]
+    exp = len(splices) / (n - 1)
+    chi2 = float(np.sum((hist - exp) ** 2 / exp))
+    assert chi2 < 25, hist  # 4 degrees of freedom
+
+
+def test_replacement_slot_uniform():
+    # Sampling only (no crossover), zero-step walks, K distinct members with
+    # distinct energies: the child is a copy, and the slot it lands in is
+    # uniform over the K members.  The slot is seen as the member whose row
+    # changed (or none, when a member was copied onto itself).
+    n, K, trials = 30, 8, 8000
+    st = O.MemeticState(n, K, 5, 1)
+    assert len({tuple(r) for r in st.pop}) == K
+    base, baseE = st.pop.copy(), st.popE.copy()
+    hits = np.zeros(K, dtype=np.int64)
+    same = 0
+    for _ in range(trials):
+        st.pop[:] = base
+        st.popE[:] = baseE
+        st.advance(1, ZERO_WALK, 0, 0)
+        changed = [k for k in range(K) if not np.array_equal(st.pop[k], base[k])]
+        assert len(changed) <= 1
+        if changed:
+            hits[changed[0]] += 1
+        else:
+            same += 1
+    # sampled member and slot are independent uniform picks: a copy onto
+    # itself has probability 1/K, every other slot (K-1)/K^2
+    assert abs(same / trials - 1 / K) < 5 * np.sqrt((1 / K) * (1 - 1 / K) / trials)
+    exp = trials * (K - 1) / K / K
+    chi2 = float(np.sum((hits - exp) ** 2 / exp))
+    assert chi2 < 30, hits  # 7 degrees of freedom

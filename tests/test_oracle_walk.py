@@ -180,3 +180,81 @@ def test_tabu_batch_matches_single_walks():
         b1, e1, f1, _, _ = O.tabu_walk(s, 55, w, 0, T, lo, hi, 1)
         assert np.array_equal(best[w, :n], b1) and be[w] == e1 and fe[w] == f1
         assert not best[w, n:].any()
+
+
+# ---------------------------------------------------------------------------
+# Tenure: the tabuList entry of each move, and the admissible set it defines.
+# ---------------------------------------------------------------------------
+M32 = 0xFFFFFFFF
+
+
+@pytest.mark.parametrize("n,lo,hi,asp", [(9, 0, 4, 0), (20, 1, 3, 1), (33, 3, 6, 0), (64, 6, 12, 1),
+                                         (130, 13, 26, 1)])
+def test_tenure_expiry_exact(n, lo, hi, asp):
+    # The move of step t stays tabu through step t + lo + ((u1 (hi-lo+1)) >> 32),
+    # u1 word 1 of draw (entity, gen, t, STEP) (pure-Python Philox here), and
+    # each step takes a minimum over exactly the moves whose entry is below t
+    # (plus, with aspiration, those beating the walk's best), by numpy energies.
+    seed, ent, gen = 2024, 5, 7
+    steps = min(6 * n, 200)
+    s = O.random_start(n, seed, ent)
+    best, be, fe, tr, te, tx = O.tabu_walk(s, seed, ent, gen, steps, lo, hi, asp,
+                                           want_trace=True, want_expiry=True)
+    key = [seed & M32, seed >> 32]
+    tabu = np.zeros(n, dtype=np.int64)
+    cur = s.astype(np.int64).copy()
+    bestE = npref.energy(cur)
+    for t in range(1, steps + 1):
+        u1 = npref.philox([ent, gen, t, O.TAG_STEP], key)[1]
+        assert tx[t - 1] == t + lo + ((u1 * (hi - lo + 1)) >> 32), t
+        i = int(tr[t - 1])
+        cand = npref.flip_energies(cur)
+        adm = (tabu < t) | (bool(asp) & (cand < bestE))
+        assert adm[i] and cand[i] == cand[adm].min(), t
+        cur[i] = -cur[i]
+        tabu[i] = tx[t - 1]
+        bestE = min(bestE, int(cand[i]))
+    assert be == bestE
+
+
+def test_tenure_uniform():
+    # tenures tabuList - t over many steps are uniform over [lo, hi]
+    n, lo, hi = 40, 2, 9
+    taus = []
+    for w in range(30):
+        s = O.random_start(n, 11, w)
+        *_, tx = O.tabu_walk(s, 11, w, 0, 120, lo, hi, 1, want_trace=True, want_expiry=True)
+        taus.append(tx - np.arange(1, 121))
+    taus = np.concatenate(taus)
+    assert taus.min() >= lo and taus.max() <= hi
+    hist = np.bincount(taus - lo, minlength=hi - lo + 1)
+    exp = len(taus) / (hi - lo + 1)
+    chi2 = float(np.sum((hist - exp) ** 2 / exp))
+    assert chi2 < 30, hist  # 7 degrees of freedom
+
+
+# ---------------------------------------------------------------------------
+# Walk length drawn from a range (Sec. III.B: randInt[N/2, 3N/2]).
+# ---------------------------------------------------------------------------
+def test_steps_range_rule():
+    # RANGE(1/2, 3/2) is Sec. III.B's statement; Alg. 4's
+    # randomInt(0, N) + floor(N/2) (the PAPER rule) spans the same integers,
+    # floor(3N/2) - floor(N/2) = N, and both take the same draw: they agree
+    # walk for walk at every N
+    paper = O.Schedule(O.STEPS_PAPER, 0, O.TENURE_LINEAR, 0, 1, 1, 1, 10, 1, 1)
+    rng_ = O.Schedule(O.STEPS_RANGE, 0, O.TENURE_LINEAR, 0, 1, 1, 1, 10, 1, 1, 1, 2, 3, 2)
+    for n in range(3, 257):
+        for e in range(3):
+            assert O.walk_schedule(n, rng_, 9, e, n) == O.walk_schedule(n, paper, 9, e, n)
+    # RANGE(1, 2): T uniform over [N, 2N], both ends included
+    two = O.Schedule(O.STEPS_RANGE, 0, O.TENURE_LINEAR, 1, 10, 0, 1, 5, 0, 1, 1, 1, 2, 1)
+    n = 10
+    Ts = np.array([O.walk_schedule(n, two, 5, e, 0)[0] for e in range(11000)])
+    assert Ts.min() == n and Ts.max() == 2 * n
+    hist = np.bincount(Ts - n, minlength=n + 1)
+    chi2 = float(np.sum((hist - 1000) ** 2 / 1000))
+    assert chi2 < 35, hist  # 10 degrees of freedom
+    # an empty range is invalid
+    bad = O.Schedule(O.STEPS_RANGE, 0, O.TENURE_LINEAR, 0, 1, 0, 0, 1, 0, 1, 2, 1, 1, 1)
+    with pytest.raises(ValueError):
+        O.walk_schedule(12, bad, 1, 0, 0)
