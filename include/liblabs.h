@@ -194,6 +194,32 @@ int labs_tabu_batch(labs_handle *h, const labs_tabu_params *p,
                     int32_t *best_e, int32_t *final_e, int16_t *trace,
                     int32_t trace_stride, void *stream);
 
+/*
+ * labs_tabu_batch for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * same arguments, same results, but no device or pinned host memory is
+ * allocated or freed by the call.  Its queue heads, per-walk lengths and
+ * processing order live in a fixed device array of LABS_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each device for the life of the process.
+ *   ns_host   HOST int32 [walks] or NULL; with per-walk lengths at most
+ *             LABS_NOALLOC_MAX_WALKS walks (LABS_E_INVAL beyond; a batch of
+ *             one length has no limit).  The lengths are copied by a
+ *             transfer enqueued on `stream`: keep the array unchanged until
+ *             the stream has passed this call.
+ * Every call on a device shares that device's array (the handle's side
+ * streams run the length classes of a mixed batch): calls that overlap in
+ * time on one device -- from any handle or stream -- race and must be
+ * ordered by the caller.
+ */
+#define LABS_NOALLOC_MAX_WALKS 65536
+#define LABS_NOALLOC_SCRATCH_BYTES (1024 + 8 * LABS_NOALLOC_MAX_WALKS)
+int labs_tabu_batch_noalloc(labs_handle *h, const labs_tabu_params *p,
+                            const int8_t *starts, int32_t start_stride,
+                            const int32_t *ns_host, int32_t n_uniform, int64_t walks,
+                            uint64_t seed, int8_t *best_seq, int32_t out_stride,
+                            int32_t *best_e, int32_t *final_e, int16_t *trace,
+                            int32_t trace_stride, void *stream);
+
 /* Set (launch != NULL) or clear (NULL: back to the tuned/default choice) the
  * launch configuration used by labs_tabu_batch on this handle. */
 int labs_set_launch(labs_handle *h, const labs_launch *launch);

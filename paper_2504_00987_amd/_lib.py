@@ -14,10 +14,12 @@ LIB_PATH = os.path.join(HERE, "liblabs.so")
 
 LABS_OK, LABS_E_INVAL, LABS_E_NOMEM, LABS_E_HIP, LABS_E_CANCELLED, LABS_E_NOTFOUND, LABS_E_AGAIN = range(7)
 MIN_N, MAX_N, MAX_K = 3, 256, 128
+NOALLOC_MAX_WALKS = 65536
 
 EXPORTED = [
     "labs_create", "labs_destroy", "labs_last_error", "labs_status_name", "labs_version",
     "labs_energy_batch", "labs_skew_deviation_batch", "labs_bruteforce_min", "labs_tabu_batch",
+    "labs_tabu_batch_noalloc",
     "labs_set_launch", "labs_get_launch",
     "labs_autotune", "labs_memetic_run", "labs_server_create", "labs_server_submit",
     "labs_server_poll", "labs_server_cancel", "labs_server_stats", "labs_server_destroy",
@@ -78,6 +80,7 @@ def load():
     L.labs_bruteforce_min.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i64), P]
     L.labs_tabu_batch.argtypes = [P, ctypes.POINTER(TabuParams), P, i32, P, i32, i64, u64,
                                   P, i32, P, P, P, i32, P]
+    L.labs_tabu_batch_noalloc.argtypes = L.labs_tabu_batch.argtypes
     L.labs_set_launch.argtypes = [P, ctypes.POINTER(Launch)]
     L.labs_get_launch.argtypes = [P, i32, ctypes.POINTER(Launch)]
     L.labs_autotune.argtypes = [P, ctypes.POINTER(TabuParams), i32, i32, i64, u64,

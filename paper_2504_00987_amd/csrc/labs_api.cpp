@@ -258,6 +258,7 @@ int labs_create(labs_handle **out, int device) {
         h->max_children_wide = prepare_memetic_kernels();
         ok = h->max_children_wide >= 0;
     }
+    if (ok) ok = noalloc_scratch_address(device, &h->scratch) == hipSuccess;
     if (!ok) {
         labs_destroy(h);
         return LABS_E_HIP;
@@ -416,7 +417,7 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
                     int32_t start_stride, const int32_t *ns_host, int32_t n_uniform, int64_t W,
                     uint64_t seed, int8_t *best_seq, int32_t out_stride, int32_t *best_e,
                     int32_t *final_e, int16_t *trace, int32_t trace_stride, hipStream_t s,
-                    const labs_launch *force) {
+                    const labs_launch *force, void *scratch) {
     if (!p) return fail(h, LABS_E_INVAL, "null params");
     if (W < 0) return fail(h, LABS_E_INVAL, "walks < 0");
     if (W == 0) return LABS_OK;
@@ -426,8 +427,12 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
 
     // Lengths: validate every distinct N and find the longest.
     int n_min = n_uniform, n_max = n_uniform;
-    std::vector<char> seen(LABS_MAX_N + 1, 0);
+    char seen[LABS_MAX_N + 1] = {};
     if (ns_host) {
+        if (scratch && W > kNoAllocMaxWalks)
+            return fail(h, LABS_E_INVAL,
+                        "walks=%lld with per-walk lengths exceeds the allocation-free limit %lld",
+                        (long long)W, (long long)kNoAllocMaxWalks);
         n_min = LABS_MAX_N + 1;
         n_max = 0;
         for (int64_t i = 0; i < W; ++i) {
@@ -464,14 +469,34 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
     // Workspace: [queue heads (32 words per class)] [ns (W int32)] [order (W int32)].
     // The GPU orders its reuse after the previous call's kernels; the host
     // only waits for the previous copy out of the pinned staging buffer.
+    // With `scratch` (the allocation-free entry point) the same layout lives
+    // in the fixed device scratch, the lengths are copied straight from the
+    // caller's array and the order is built on the device.
     constexpr size_t kHeads = 32 * sizeof(uint32_t) * kWalkClasses;
-    const size_t bytes = kHeads + (ns_host ? 2 * (size_t)W * sizeof(int32_t) : 0);
-    int rc = ws_acquire(h, s, bytes);
-    if (rc) return rc;
+    static_assert(kHeads <= kNoAllocHeadBytes, "queue heads fit the fixed scratch");
+    int rc = LABS_OK;
     TabuLaunchArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.counter = (uint32_t *)h->ws.ptr;
-    if (ns_host) {
+    if (scratch) {
+        a.counter = (uint32_t *)scratch;
+    } else {
+        const size_t bytes = kHeads + (ns_host ? 2 * (size_t)W * sizeof(int32_t) : 0);
+        if ((rc = ws_acquire(h, s, bytes))) return rc;
+        a.counter = (uint32_t *)h->ws.ptr;
+    }
+    if (ns_host && scratch) {
+        int32_t *dn = (int32_t *)((char *)scratch + kNoAllocHeadBytes);
+        hipError_t e = hipMemcpyAsync(dn, ns_host, (size_t)W * sizeof(int32_t),
+                                      hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = launch_order_by_length(dn, W, dn + kNoAllocMaxWalks, s);
+        if (e != hipSuccess) return hip_fail(h, e, "per-walk lengths to the fixed scratch");
+        a.ns = dn;
+        a.order = dn + kNoAllocMaxWalks;
+        int64_t count[kWalkClasses] = {};
+        for (int64_t i = 0; i < W; ++i) ++count[walk_class(ns_host[i])];
+        int64_t end = 0;
+        for (int c = 0; c < kWalkClasses; ++c) a.class_end[c] = end += count[c];
+    } else if (ns_host) {
         if ((rc = stage_acquire(h, 2 * (size_t)W * sizeof(int32_t)))) return rc;
         int32_t *pn = (int32_t *)h->pin.ptr;
         int32_t *po = pn + W;
@@ -547,7 +572,7 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
         if (e == hipSuccess) e = hipStreamWaitEvent(s, sides.join[i], 0);
     }
     if (e != hipSuccess) return hip_fail(h, e, "join from side streams");
-    return ws_release(h, s);
+    return scratch ? LABS_OK : ws_release(h, s);
 }
 
 }  // namespace liblabs
@@ -562,6 +587,20 @@ extern "C" int labs_tabu_batch(labs_handle *h, const labs_tabu_params *p, const 
     return tabu_batch_impl(h, p, starts, start_stride, ns_host, n_uniform, walks, seed, best_seq,
                            out_stride, best_e, final_e, trace, trace_stride,
                            (hipStream_t)stream, nullptr);
+}
+
+extern "C" int labs_tabu_batch_noalloc(labs_handle *h, const labs_tabu_params *p,
+                                       const int8_t *starts, int32_t start_stride,
+                                       const int32_t *ns_host, int32_t n_uniform, int64_t walks,
+                                       uint64_t seed, int8_t *best_seq, int32_t out_stride,
+                                       int32_t *best_e, int32_t *final_e, int16_t *trace,
+                                       int32_t trace_stride, void *stream) {
+    if (!h) return LABS_E_INVAL;
+    h->last_error.clear();
+    if (!h->scratch) return fail(h, LABS_E_HIP, "no fixed scratch on this device");
+    return tabu_batch_impl(h, p, starts, start_stride, ns_host, n_uniform, walks, seed, best_seq,
+                           out_stride, best_e, final_e, trace, trace_stride,
+                           (hipStream_t)stream, nullptr, h->scratch);
 }
 
 extern "C" int labs_autotune(labs_handle *h, const labs_tabu_params *p, int32_t n_min,

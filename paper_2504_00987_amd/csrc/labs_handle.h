@@ -47,6 +47,7 @@ struct labs_handle {
     hipEvent_t ws_event = nullptr;     // completion of the last device-workspace user
     hipEvent_t stage_event = nullptr;  // completion of the last copy out of `pin`
     int max_children_wide = 0;         // batched children per generation at N > 128
+    void *scratch = nullptr;           // this device's allocation-free scratch
     bool ws_event_valid = false;
     bool stage_event_valid = false;
     liblabs::DevBuf ws;                   // tabu workspace: queue head, ns, order
@@ -77,7 +78,7 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
                     int32_t start_stride, const int32_t *ns_host, int32_t n_uniform, int64_t W,
                     uint64_t seed, int8_t *best_seq, int32_t out_stride, int32_t *best_e,
                     int32_t *final_e, int16_t *trace, int32_t trace_stride, hipStream_t s,
-                    const labs_launch *force);
+                    const labs_launch *force, void *scratch = nullptr);
 int check_memetic(labs_handle *h, const labs_memetic_params *p);
 // Children per generation against what the device fits (classes: bit c set
 // when a replica of memetic_class c is present).

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/liblabs.h"
+
 namespace liblabs {
 
 struct RuleParams {
@@ -110,6 +112,21 @@ struct MemeticLaunchArgs {
     MemeticStateDev st;
     uint32_t *any_hit;       // set to 1 when a replica reaches its target
 };
+
+// Fixed device scratch of the allocation-free tabu batch: queue heads, then
+// per-walk lengths and the processing order for at most kNoAllocMaxWalks
+// walks of per-walk lengths (a batch of one length needs the heads only).
+constexpr int64_t kNoAllocMaxWalks = LABS_NOALLOC_MAX_WALKS;
+constexpr size_t kNoAllocHeadBytes = 1024;
+constexpr size_t kNoAllocScratchBytes =
+    kNoAllocHeadBytes + 2 * (size_t)kNoAllocMaxWalks * sizeof(int32_t);
+static_assert(kNoAllocScratchBytes == LABS_NOALLOC_SCRATCH_BYTES, "scratch size as declared");
+constexpr int kMaxDevices = 64;
+// Device address of that scratch on `device`, which the caller has made
+// current; looked up once per device (hipGetSymbolAddress) and kept.
+hipError_t noalloc_scratch_address(int device, void **ptr);
+// Longest-first processing order of W walks from their device lengths.
+hipError_t launch_order_by_length(const int32_t *ns, int64_t W, int32_t *order, hipStream_t s);
 
 hipError_t launch_energy(const int8_t *seqs, const int32_t *ns, int32_t n_uniform,
                          int32_t stride, int64_t count, int32_t *out, hipStream_t s);

@@ -6,8 +6,12 @@
 //                   draining a longest-first work queue; one instantiation
 //                   per length class
 //   fill_u32_kernel device-side fill (queue heads, flags), capturable
+//   order_by_length_kernel  longest-first processing order built on the
+//                   device (the allocation-free entry point's lengths)
 #include <algorithm>
+#include <mutex>
 
+#include "../../include/liblabs.h"
 #include "labs_device.hpp"
 #include "labs_internal.h"
 
@@ -207,7 +211,63 @@ __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t count) {
     if (i < count) p[i] = v;
 }
 
+// Processing order of W walks, longest first, from their lengths in device
+// memory (LABS_MIN_N <= ns[w] <= LABS_MAX_N, checked by the host): one
+// workgroup counts the lengths in LDS, turns the counts into the first
+// position of each length (descending N), then every walk takes the next
+// position of its length.  Walks of one length land in an order that
+// depends on the atomics' timing; results do not depend on the order.
+constexpr int kOrderThreads = 1024;
+__global__ __launch_bounds__(kOrderThreads) void order_by_length_kernel(
+    const int32_t *__restrict__ ns, int64_t W, int32_t *__restrict__ order) {
+    __shared__ int32_t next[LABS_MAX_N + 1];
+    for (int n = threadIdx.x; n <= LABS_MAX_N; n += kOrderThreads) next[n] = 0;
+    __syncthreads();
+    for (int64_t w = threadIdx.x; w < W; w += kOrderThreads) atomicAdd(&next[ns[w]], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t pos = 0;
+        for (int n = LABS_MAX_N; n >= 0; --n) {
+            const int32_t c = next[n];
+            next[n] = pos;
+            pos += c;
+        }
+    }
+    __syncthreads();
+    for (int64_t w = threadIdx.x; w < W; w += kOrderThreads)
+        order[atomicAdd(&next[ns[w]], 1)] = (int32_t)w;
+}
+
+// Scratch of the allocation-free tabu batch: the queue heads
+// (kNoAllocHeadBytes), then the per-walk lengths and the processing order
+// (kNoAllocMaxWalks int32 each).  Each device holds its own copy for the
+// life of the process; host code reaches it only through the address
+// returned by noalloc_scratch_address, never through this name.
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
 }  // namespace
+
+hipError_t noalloc_scratch_address(int device, void **ptr) {
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        // the caller has made `device` current
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
+
+hipError_t launch_order_by_length(const int32_t *ns, int64_t W, int32_t *order, hipStream_t s) {
+    if (W <= 0) return hipSuccess;
+    hipLaunchKernelGGL(order_by_length_kernel, dim3(1), dim3(kOrderThreads), 0, s, ns, W, order);
+    return hipGetLastError();
+}
 
 hipError_t launch_energy(const int8_t *seqs, const int32_t *ns, int32_t n_uniform,
                          int32_t stride, int64_t count, int32_t *out, hipStream_t s) {

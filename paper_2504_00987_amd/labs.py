@@ -121,7 +121,11 @@ class Labs:
 
     def tabu_batch(self, rules: Rules, walks: int, seed: int, ns=None, n_uniform: int = 0,
                    starts: torch.Tensor | None = None, out_stride: int | None = None,
-                   trace_stride: int = 0, out=None, stream=None) -> TabuResult:
+                   trace_stride: int = 0, out=None, stream=None,
+                   noalloc: bool = False) -> TabuResult:
+        """Independent tabu walks (labs_tabu_batch; with ``noalloc`` the
+        allocation-free labs_tabu_batch_noalloc, whose per-walk lengths are
+        read by a copy on the stream: the array is kept alive on the result)."""
         dev = torch.device("cuda", self.device)
         ns_arr = None
         if ns is not None:
@@ -142,12 +146,15 @@ class Labs:
             out_stride = best.shape[1]
             trace_stride = 0 if tr is None else tr.shape[1]
         p = tabu_params(rules)
-        self._check(self.L.labs_tabu_batch(
+        fn = self.L.labs_tabu_batch_noalloc if noalloc else self.L.labs_tabu_batch
+        self._check(fn(
             self.h, ctypes.byref(p), _ptr(starts), 0 if starts is None else starts.shape[1],
             None if ns_arr is None else ns_arr.ctypes.data_as(ctypes.c_void_p), n_uniform,
             walks, ctypes.c_uint64(seed & (2**64 - 1)), _ptr(best), out_stride, _ptr(be),
             _ptr(fe), _ptr(tr), trace_stride, _stream(stream)))
-        return TabuResult(best, be, fe, tr)
+        res = TabuResult(best, be, fe, tr)
+        res._lengths = ns_arr  # read by a copy on the stream in the allocation-free form
+        return res
 
     def set_launch(self, waves_per_group: int | None = None, persistent: int = 0,
                    groups_per_cu: int = 0):
