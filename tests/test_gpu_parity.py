@@ -375,6 +375,126 @@ def test_memetic_target_and_stop_all(lb):
         assert g == (st.gen if st.hit >= 0 and st.hit <= stop else stop)
 
 
+def _oracle_stop_all(n_list, K, rules, G, seed, target, chunk, children=0):
+    """The oracle's replicas under the global termination flag (Alg. 3): every
+    replica stops at the end of the generation chunk in which the first one
+    reached the target (the first chunk runs even when an initial population
+    already does); a replica that hit earlier stopped at its own hit."""
+    ref = _oracle_memetic(n_list, K, rules, G, seed, target=target, children=children)
+    hits = [st.hit for st in ref if st.hit >= 0]
+    if not hits:
+        return ref, G
+    stop = min(G, max(chunk, -(-min(hits) // chunk) * chunk))
+    return _oracle_memetic(n_list, K, rules, stop, seed, target=target, children=children), stop
+
+
+@pytest.mark.parametrize("n", [20, 33, 64, 65, 120])
+def test_memetic_paper_literal_stop_all(lb, n):
+    # the configuration the small-N time-to-solution experiment times: the
+    # paper's own walk rules (Alg. 4's walk length, Sec. III.B's tenure
+    # floor(T/10)..floor(3T/25), no aspiration), a target and the global
+    # termination flag, in every execution mode
+    rules = I.RULES_PAPER_LITERAL
+    pops, K, G = 8, 100, 160
+    seed = 7000 + n
+    # a target two replicas reach within the first half of the budget
+    base = _oracle_memetic([n] * pops, K, rules, G // 2, seed)
+    target = sorted(st.bestE for st in base)[1]
+    for mode, chunk, waves in ((0, 16, 0), (1, 7, 1), (2, 16, 0), (2, 5, 1)):
+        ref, stop = _oracle_stop_all([n] * pops, K, rules, G, seed, target, chunk)
+        say(f"memetic paper-literal N={n} target {target} mode {mode} chunk {chunk} "
+            f"waves {waves}: stop at {stop}")
+        res = lb.memetic_run(K, rules, G, pops, seed, n_uniform=n, target=target, mode=mode,
+                             chunk=chunk, stop_all=1, waves_per_replica=waves)
+        assert stop < G  # some replica hits, and the flag cuts the others short
+        for p, st in enumerate(ref):
+            assert res.hit_gen[p].item() == st.hit
+            assert res.gens_done[p].item() == st.gen
+            assert res.best_e[p].item() == st.bestE
+            assert np.array_equal(res.best_seq[p, :n].cpu().numpy(), st.best)
+
+
+def _deep_n120():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "memetic_n120_deep.txt")
+    rows = {"full": {}, "long": {}, "hist": {}}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        if line.startswith("hist "):
+            _, p, g, e = line.split()
+            rows["hist"].setdefault(int(p), []).append((int(g), int(e)))
+            continue
+        sec, p, g, e, h = line.split()
+        v = int(h, 16)
+        seq = np.array([-1 if (v >> i) & 1 else 1 for i in range(120)], dtype=np.int8)
+        rows[sec][(int(p), int(g))] = (int(e), seq)
+    return rows
+
+
+@pytest.mark.parametrize("mode,chunk,waves", [(2, 64, 0), (2, 64, 1), (0, 64, 0)])
+def test_memetic_n120_deep_full_width(lb, mode, chunk, waves):
+    # all 256 replicas of the N=120 configuration for 1000 generations against
+    # the oracle's stored results (written by tests/golden/make_memetic_n120.py)
+    wl = I.MEMETIC_N120
+    want = _deep_n120()["full"]
+    say(f"memetic N=120: 256 replicas x 1000 generations, mode {mode}, waves {waves}")
+    res = lb.memetic_run(wl.K, wl.rules, 1000, wl.pops, wl.seed, n_uniform=wl.n, mode=mode,
+                         chunk=chunk, waves_per_replica=waves)
+    be, bs = res.best_e.cpu().numpy(), res.best_seq.cpu().numpy()
+    assert len(want) == wl.pops
+    for p in range(wl.pops):
+        e, seq = want[(p, 1000)]
+        assert be[p] == e and np.array_equal(bs[p, :120], seq)
+    assert (res.gens_done.cpu().numpy() == 1000).all()
+
+
+@pytest.mark.parametrize("gens", [25000, 50000, 100000])
+def test_memetic_n120_deep_long(lb, gens):
+    # replicas 0..3 of the N=120 configuration through its whole budget of
+    # 10^5 generations, checked against the oracle's stored results at a
+    # quarter and at the end; the persistent form the benchmark times, two
+    # wavefronts each
+    wl = I.MEMETIC_N120
+    want = _deep_n120()["long"]
+    say(f"memetic N=120: 4 replicas x {gens} generations, persistent")
+    res = lb.memetic_run(wl.K, wl.rules, gens, 4, wl.seed, n_uniform=wl.n, mode=2, chunk=64)
+    for p in range(4):
+        e, seq = want[(p, gens)]
+        assert res.best_e[p].item() == e
+        assert np.array_equal(res.best_seq[p, :120].cpu().numpy(), seq)
+        assert res.gens_done[p].item() == gens
+
+
+def test_memetic_n120_deep_hit_generations(lb):
+    # with a target the four replicas all reach, each stops at the generation
+    # at which the oracle's best first fell to it (one of its improvements)
+    wl = I.MEMETIC_N120
+    hist = _deep_n120()["hist"]
+    target = max(h[-1][1] for h in hist.values())
+    say(f"memetic N=120: 4 replicas, target {target}")
+    res = lb.memetic_run(wl.K, wl.rules, 100000, 4, wl.seed, n_uniform=wl.n, mode=2, chunk=64,
+                         target=target)
+    for p in range(4):
+        g, e = next((g, e) for g, e in hist[p] if e <= target)
+        assert res.hit_gen[p].item() == g and res.gens_done[p].item() == g
+        assert res.best_e[p].item() == e
+
+
+def test_memetic_n120_deep_long_other_forms(lb):
+    # the full budget in the graph form and with one wavefront per replica
+    wl = I.MEMETIC_N120
+    want = _deep_n120()["long"]
+    for mode, chunk, waves in ((1, 64, 0), (2, 256, 1)):
+        say(f"memetic N=120: 4 replicas x 100000 generations, mode {mode}, waves {waves}")
+        res = lb.memetic_run(wl.K, wl.rules, 100000, 4, wl.seed, n_uniform=wl.n, mode=mode,
+                             chunk=chunk, waves_per_replica=waves)
+        for p in range(4):
+            e, seq = want[(p, 100000)]
+            assert res.best_e[p].item() == e
+            assert np.array_equal(res.best_seq[p, :120].cpu().numpy(), seq)
+
+
 @pytest.mark.parametrize("mode,chunk,waves", [(1, 3, 1), (2, 64, 0)])
 def test_memetic_n120_prefix(lb, mode, chunk, waves):
     # the N=120 configuration at full width (256 replicas of K=100) for its
