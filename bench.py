@@ -33,46 +33,40 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X (gfx950): 256 CUs x 4 SIMD x 16 lanes (a wave64 VALU instruction
-# every 4 cycles per SIMD) = 64 int32 lane-ops per CU-cycle, at 2.4 GHz.
-PEAK_INT32_OPS = 256 * 64 * 2.4e9
+# MI355X (gfx950) published figures: 256 CUs at 2.4 GHz, 4 SIMD16 per CU
+# (a wave64 VALU instruction every 4 cycles per SIMD: 64 lanes per CU-cycle).
+# v_dot4_i32_i8 sums four int8 products into an int32 per lane per clock, the
+# contraction of the neighbour scoring; the LDS serves 128 bytes per CU-cycle.
+CLOCK_HZ, CUS = 2.4e9, 256
+PEAK_DOT4_OPS = CUS * 64 * 4 * CLOCK_HZ    # 157.3e12 int8 products/s
+PEAK_INT32_OPS = CUS * 64 * CLOCK_HZ       # 39.3e12 int32 lane-ops/s
+PEAK_LDS_BYTES = CUS * 128 * CLOCK_HZ      # 78.6e12 B/s
 METRIC = "flip-neighbour evals/sec (N=64..120) + time-to-target energy; batched vs plain"
+# What decides which walk kernels a call runs and how they are compiled: the
+# kernels, the length classes, the launch selection and the build flags.
 KERNEL_SOURCES = ("paper_2504_00987_amd/csrc/labs_device.hpp",
-                  "paper_2504_00987_amd/csrc/labs_walk.hip")
+                  "paper_2504_00987_amd/csrc/labs_walk.hip",
+                  "paper_2504_00987_amd/csrc/labs_internal.h",
+                  "paper_2504_00987_amd/csrc/labs_api.cpp")
 
-# Counter readings per launch of the walk kernels (rocprofv3 --pmc, one pass
-# per counter group, same bench command), valid for the kernel sources whose
-# digest is recorded.  FETCH_SIZE / WRITE_SIZE are in KiB and are scaled by
-# what the same counters read for a 256 MiB device copy (FETCH 0.5x, WRITE
-# 1.0x of the bytes moved).  The summaries live in profiles/.
+# Counter readings per call of labs_tabu_batch (rocprofv3 --pmc, one pass per
+# counter group, the same bench command), valid only for the walk kernel
+# digest and the launch they were profiled under; otherwise nothing is
+# attached (they are never carried over to other code or another launch).
+# FETCH_SIZE / WRITE_SIZE are in KiB and scaled by what the same counters read
+# for a 256 MiB device copy (FETCH 0.5x, WRITE 1.0x of the bytes moved).
+# LdsUtil = SQ_LDS_IDX_ACTIVE / (GRBM_GUI_ACTIVE x CUs), rocprofv3's own
+# definition for gfx950.  The summaries live in profiles/.
 COPY_SCALE = {"FETCH_SIZE": 262144 / 131087, "WRITE_SIZE": 262144 / 262144}
-COUNTERS = {
-    # per call in the default launch configuration, mean over the profiled
-    # dispatches; summed over the kernels of one call (a batch with walks
-    # on both sides of N = 128 runs two, concurrently)
-    "tabu_n64": {"digest": "f71d5cbffbfaf0fc", "FETCH_SIZE": 80.5, "WRITE_SIZE": 768.0,
-        "SQ_INSTS_VALU": 45513148, "SQ_INSTS_LDS": 13721600,
-        "SQ_LDS_BANK_CONFLICT": 2847176,
-        "source": "profiles/tabu_kernel_counters.md"},
-    "tabu_uneven": {"digest": "f71d5cbffbfaf0fc", "FETCH_SIZE": 631.8, "WRITE_SIZE": 1361.1,
-        "SQ_INSTS_VALU": 238153444, "SQ_INSTS_LDS": 65717792,
-        "SQ_LDS_BANK_CONFLICT": 35697887,
-        "source": "profiles/tabu_kernel_counters.md"},
-    "tabu_n256": {"digest": "f71d5cbffbfaf0fc", "FETCH_SIZE": 176.1, "WRITE_SIZE": 1088.0,
-        "SQ_INSTS_VALU": 2027584427, "SQ_INSTS_LDS": 541691904,
-        "SQ_LDS_BANK_CONFLICT": 4194304,
-        "source": "profiles/tabu_kernel_counters.md"},
-    "tabu_long_uneven": {"digest": "f71d5cbffbfaf0fc", "FETCH_SIZE": 439.5, "WRITE_SIZE": 1184.9,
-        "SQ_INSTS_VALU": 1391622528, "SQ_INSTS_LDS": 368409501,
-        "SQ_LDS_BANK_CONFLICT": 114441374,
-        "source": "profiles/tabu_kernel_long_uneven_kernel_trace.md"},
-}
+COUNTERS = {}
 
 
 def kernel_digest() -> str:
-    # hash of the walk kernel's code with comments and whitespace removed, so
-    # that the counter readings outlive edits that change no code
+    # hash of the walk kernels' code with comments and whitespace removed,
+    # and of the compiler flags, so that the counter readings outlive edits
+    # that change no code and nothing else
     import re
+    from paper_2504_00987_amd import build as B
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
         with open(os.path.join(ROOT, p)) as f:
@@ -80,7 +74,21 @@ def kernel_digest() -> str:
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
         text = re.sub(r"//[^\n]*", " ", text)
         h.update(" ".join(text.split()).encode())
+    h.update(" ".join(f for f in B._flags() if not f.startswith("/")).encode())
     return h.hexdigest()[:16]
+
+
+def host_cpu() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
 
 
 def lag_terms_per_step(n: int) -> int:
@@ -91,7 +99,7 @@ def lag_terms_per_step(n: int) -> int:
 # ---------------------------------------------------------------------------
 # Batched walks (the headline number)
 # ---------------------------------------------------------------------------
-def tabu_section(args, lb, wl):
+def tabu_section(args, lb, wl, peaks=None):
     import torch
     ns = wl.lengths()
     W = wl.walks
@@ -126,7 +134,7 @@ def tabu_section(args, lb, wl):
         # the library's autotuner over the workload's length range; the
         # untuned default is timed first (after the warm-up) for comparison
         n_lo, n_hi = int(ns.min()), int(ns.max())
-        default_launch = lb.get_launch(n_hi)
+        default_launch = lb.get_launch(n_lo, n_hi)
         default_ms = launch_ms(10)
         t0 = time.perf_counter()
         tried = lb.autotune(wl.rules, n_lo, n_hi, W, seed=wl.seed + 17)
@@ -149,30 +157,53 @@ def tabu_section(args, lb, wl):
     ms_per_step = wall * 1e3 / args.steps
     value = evals_per_step * args.steps / wall
     achieved = ops_per_launch / (kernel_ms * 1e-3)
-    launch = lb.get_launch(int(ns.max()))
+    launch = lb.get_launch(int(ns.min()), int(ns.max()))
 
+    lag_terms = ops_per_launch // 3
     roof = {
         "bound": "alu",
         "achieved": achieved / 1e12,
-        "peak": PEAK_INT32_OPS / 1e12,
-        "unit": "Top/s (int32, 3 ops per lag term)",
-        "frac": achieved / PEAK_INT32_OPS,
+        "peak": PEAK_DOT4_OPS / 1e12,
+        "unit": "Top/s (3 integer ops per lag term; peak: v_dot4_i32_i8, 4 int8 products "
+                "per lane per clock)",
+        "frac": achieved / PEAK_DOT4_OPS,
         "traffic": None,
         "kernel": "tabu_kernel",
         "kernel_ms": kernel_ms,
         "algorithmic_ops_per_launch": ops_per_launch,
+        # the same work against one int32 operation per lane per clock: above
+        # 1 it shows the reduction of work by the packed int8 products, it is
+        # not a fraction of any peak
+        "work_vs_int32_issue": achieved / PEAK_INT32_OPS,
+        "lds": {
+            # the survey's algorithmic LDS bytes: two spins and C_k as int8
+            # per lag term; the lag form reads one byte of its row per lag
+            # term and C_k as a broadcast, so the hardware figure below
+            # (LdsUtil) is the measured one
+            "algorithmic_bytes_per_launch": 3 * lag_terms,
+            "achieved": 3 * lag_terms / (kernel_ms * 1e-3) / 1e12,
+            "peak": PEAK_LDS_BYTES / 1e12,
+            "unit": "TB/s",
+            "frac": 3 * lag_terms / (kernel_ms * 1e-3) / PEAK_LDS_BYTES,
+        },
     }
+    if peaks is not None:
+        roof["measured_peak"] = peaks["dot4_ops_per_s"] / 1e12
+        roof["frac_of_measured_peak"] = achieved / peaks["dot4_ops_per_s"]
+        roof["lds"]["measured_peak"] = peaks["lds_bytes_per_s"] / 1e12
     digest = kernel_digest()
     c = COUNTERS.get(wl.name)
-    if c is not None and c["digest"] == digest:
+    if c is not None and c["digest"] == digest and tuple(c["launch"]) == tuple(launch):
         roof["traffic"] = (c["FETCH_SIZE"] * COPY_SCALE["FETCH_SIZE"]
                            + c["WRITE_SIZE"] * COPY_SCALE["WRITE_SIZE"]) * 1024
         lane_ops = c["SQ_INSTS_VALU"] * 64
         roof["hardware"] = {
             "valu_lane_ops_per_launch": lane_ops,
-            "valu_frac": lane_ops / (kernel_ms * 1e-3) / PEAK_INT32_OPS,
+            "valu_issue_frac": lane_ops / (kernel_ms * 1e-3) / PEAK_INT32_OPS,
             "lds_instructions_per_launch": c["SQ_INSTS_LDS"],
             "lds_bank_conflict_cycles_per_launch": c["SQ_LDS_BANK_CONFLICT"],
+            "lds_util": c["SQ_LDS_IDX_ACTIVE"] / (c["GRBM_GUI_ACTIVE"] * CUS),
+            "launch": list(c["launch"]),
             "source": c["source"],
         }
     roof["kernel_digest"] = digest
@@ -195,10 +226,11 @@ def tabu_section(args, lb, wl):
             "walks": W,
             "n": wl.n if uniform else f"uniform {{{wl.n_lo}..{wl.n_hi}}}",
             "steps_per_walk": f"{wl.rules.steps_a}N",
+            "seed": wl.seed,
             "tenure": "U[floor(N/10), floor(N/5)]",
             "aspiration": bool(wl.rules.aspiration),
-            "launch": {"waves_per_group": launch[0], "persistent": launch[1],
-                       "groups_per_cu": launch[2]},
+            "launch": {"group_lanes": launch[0], "walks_per_group": launch[1],
+                       "persistent": launch[2], "groups_per_cu": launch[3], "layout": launch[4]},
             "evals_per_step": evals_per_step,
         },
         "roofline": roof,
@@ -215,6 +247,7 @@ def cpu_tabu(args, wl, ns):
     # with 16 threads).  Walks are independent, so the oracle's batch call
     # spreads them over threads; nothing else is tuned.
     from oracle import oracle as O
+    # the machine's CPU share for one GPU is 16 threads
     threads = max(1, min(16, len(os.sched_getaffinity(0))))
     # all walks up to N = 128; a bounded prefix of the N = 256 workload
     sample = args.cpu_walks or (wl.walks if int(ns.max()) <= 128 else 128)
@@ -237,6 +270,7 @@ def cpu_tabu(args, wl, ns):
         "kind": "oracle",
         "sample": f"{passes} passes over walks 0..{sample - 1} of {wl.name} in {cpu_s:.1f} s "
                   f"(plain C, gcc -O2, {threads} threads)",
+        "host": host_cpu(),
     }
 
 
@@ -423,7 +457,13 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="tabu_n64", choices=["tabu_n64", "tabu_uneven", "tabu_n256", "tabu_long_uneven"])
+    ap.add_argument("--workload", default="tabu_n64",
+                    choices=["tabu_n64", "tabu_uneven", "tabu_n120", "tabu_n256", "tabu_long_uneven"])
+    ap.add_argument("--more-workloads", default="tabu_uneven,tabu_n120",
+                    help="walk workloads timed after the headline one, each with its own "
+                         "roofline and CPU baseline (comma list, empty for none)")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the measured dot4 / int32 / LDS peaks")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default launch configuration instead of the tuned one")
@@ -470,11 +510,43 @@ def main() -> int:
     wl = I.TABU_WORKLOADS[args.workload]
     torch.cuda.set_device(0)
     lb = Labs(0)
-    line, ns = tabu_section(args, lb, wl)
+    peaks = None
+    if not args.no_peaks:
+        peaks = lb.device_peaks()
+        print(f"# measured peaks: dot4 {peaks['dot4_ops_per_s'] / 1e12:.1f} T products/s, "
+              f"int32 {peaks['int32_ops_per_s'] / 1e12:.1f} T ops/s, "
+              f"LDS {peaks['lds_bytes_per_s'] / 1e12:.1f} TB/s, clock {peaks['clock_hz'] / 1e9:.2f} GHz",
+              file=sys.stderr, flush=True)
+    line, ns = tabu_section(args, lb, wl, peaks)
     print(f"# tabu: {line['value']:.4g} evals/s, kernel {line['roofline']['kernel_ms']:.4f} ms",
           file=sys.stderr, flush=True)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_tabu(args, wl, ns)
+    if peaks is not None:
+        line["peaks"] = {
+            "measured": {"dot4_products_per_s": peaks["dot4_ops_per_s"],
+                         "int32_ops_per_s": peaks["int32_ops_per_s"],
+                         "lds_bytes_per_s": peaks["lds_bytes_per_s"],
+                         "clock_hz_under_dot4_load": peaks["clock_hz"]},
+            "published": {"dot4_products_per_s": PEAK_DOT4_OPS, "int32_ops_per_s": PEAK_INT32_OPS,
+                          "lds_bytes_per_s": PEAK_LDS_BYTES},
+            "how": "labs_device_peaks: independent chains of v_dot4_i32_i8 / v_add_u32 per lane, "
+                   "and conflict-free 16-byte LDS reads, on 16 (8 for LDS) workgroups of 256 "
+                   "lanes per CU, one launch timed with HIP events after a warm-up"}
+    more = []
+    for name in [x for x in args.more_workloads.split(",") if x and x != wl.name]:
+        w2 = I.TABU_WORKLOADS[name]
+        row, ns2 = tabu_section(args, lb, w2, peaks)
+        entry = {"workload": name, "value": row["value"], "unit": "evals/s",
+                 "ms_per_step": row["ms_per_step"], "config": row["config"],
+                 "roofline": row["roofline"]}
+        if not args.no_cpu:
+            entry["cpu_baseline"] = cpu_tabu(args, w2, ns2)
+        more.append(entry)
+        print(f"# {name}: {row['value']:.4g} evals/s, kernel {row['roofline']['kernel_ms']:.4f} ms",
+              file=sys.stderr, flush=True)
+    if more:
+        line["more_workloads"] = more
     if not args.no_ttt:
         line["time_to_target"] = ttt_section(args, lb)
         print("# time to target done", file=sys.stderr, flush=True)

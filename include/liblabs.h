@@ -60,7 +60,13 @@ typedef enum labs_status {
 typedef enum labs_steps_rule {
     LABS_STEPS_FIXED = 0,  /* maxIter = steps_a */
     LABS_STEPS_MULT_N = 1, /* maxIter = steps_a * N */
-    LABS_STEPS_PAPER = 2   /* maxIter = randomInt(0, N) + floor(N/2), Alg. 4 */
+    LABS_STEPS_PAPER = 2,  /* maxIter = randomInt(0, N) + floor(N/2), Alg. 4 */
+    /* maxIter uniform in [floor(slo_num*N/slo_den), floor(shi_num*N/shi_den)]
+     * (both ends inclusive), from word 0 of the draw (walk, generation, 0,
+     * LEN) as lo + ((w0 * (hi - lo + 1)) >> 32); Sec. III.B states the walk
+     * length as randInt[N/2, 3N/2], which is RANGE(1/2, 3/2) and equals
+     * LABS_STEPS_PAPER at every N */
+    LABS_STEPS_RANGE = 3
 } labs_steps_rule;
 
 /* Tabu tenure rule: a move flipped at step t is tabu for steps
@@ -85,19 +91,32 @@ typedef struct labs_tabu_params {
     int32_t aspiration;  /* 1: a tabu move is admissible when its energy is
                             strictly below the walk's best (not in the paper;
                             0 gives the paper's rule) */
+    int32_t slo_num, slo_den, shi_num, shi_den; /* LABS_STEPS_RANGE bounds
+                            (den > 0, num >= 0; ignored by the other rules) */
 } labs_tabu_params;
 
 #define LABS_MAX_STEPS (1 << 20)
 
-/* Launch configuration of the batched walk kernels. */
+/* Launch configuration of the batched walk kernels.  Lanes per walk =
+ * group_lanes / walks_per_group: 64 (one wavefront per walk: {64, 1},
+ * {128, 2}, {256, 4}) or 128 ({128, 1}: the walks of 64 < N <= 128 run on
+ * two wavefronts each, exchanging their minima through LDS; the batch's
+ * other walks run one per wavefront, two per 128-lane workgroup).  Fewer
+ * lanes than a wavefront per walk, and four wavefronts per walk, are not
+ * built (LABS_E_INVAL). */
 typedef struct labs_launch {
-    int32_t waves_per_group; /* 1, 2 or 4: workgroups of 64, 128 or 256 lanes,
-                                one walk per 64-lane wavefront */
+    int32_t group_lanes;     /* 64, 128 or 256 lanes per workgroup */
+    int32_t walks_per_group; /* 1, 2 or 4 */
     int32_t persistent;      /* 1: a grid sized to the device drains a
-                                longest-first work queue; 0: one wavefront
-                                per walk */
+                                longest-first work queue; 0: one walk per
+                                wavefront (or per two) of the grid */
     int32_t groups_per_cu;   /* persistent grid = groups_per_cu x CUs (0: auto) */
-} labs_launch;               /* default (untuned): {4, 0, 0} */
+    int32_t layout;          /* walks of 64 < N <= 128: 0 default (record form
+                                on one wavefront, lag form on two), 1 lag form
+                                (t_jk rows, 18.5 KB of LDS per walk), 2 record
+                                form (sequence windows, 9.5 KB) */
+} labs_launch;               /* default (untuned): {64, 1, 0, 0, 0} up to
+                                N = 128, {256, 4, 0, 0, 0} above */
 
 typedef struct labs_handle labs_handle;
 
@@ -224,24 +243,42 @@ int labs_tabu_batch_noalloc(labs_handle *h, const labs_tabu_params *p,
  * launch configuration used by labs_tabu_batch on this handle. */
 int labs_set_launch(labs_handle *h, const labs_launch *launch);
 
-/* The launch configuration labs_tabu_batch would use for length n. */
-int labs_get_launch(labs_handle *h, int32_t n, labs_launch *out);
+/* The launch configuration labs_tabu_batch would use for a batch whose
+ * lengths span [n_min, n_max]. */
+int labs_get_launch(labs_handle *h, int32_t n_min, int32_t n_max, labs_launch *out);
 
 /*
- * Autotuner: times every launch configuration {64, 128, 256 lanes per
- * workgroup, i.e. 1, 2, 4 walks per workgroup} x {one wave per walk,
- * persistent queue at 1/2/4/8 x 4/(walks per workgroup) groups per CU} on
- * `walks` random-start walks with lengths spread evenly over [n_min, n_max]
- * and parameters `p` (each: one warm-up call, then four calls back to
- * back), and keeps the fastest for the batches whose longest walk falls in
- * the length bucket (of 16) of n_max; the default launch (one wave per
- * walk; one walk per workgroup up to N = 128, four above) stays unless a
- * configuration is more than 2 % faster.  *tried (may be NULL) receives the number of configurations
- * timed.  Synchronous; results never depend on the choice (only speed
- * does).
+ * Autotuner: times the launch configurations that apply to the length range
+ * [n_min, n_max] -- {64, 1}, {128, 2}, {256, 4} (one wavefront per walk) and,
+ * when the range reaches 64 < N <= 128, {128, 1} (two wavefronts per walk),
+ * each with both layouts of those walks where they are present, and each
+ * as a grid of one walk per wavefront (or pair) and as a persistent queue
+ * at 1, 2, 4 and 8 x 4 / (wavefronts per group) groups per CU -- on `walks`
+ * random-start walks with lengths spread evenly over [n_min, n_max] and
+ * parameters `p` (each: one warm-up call, then four calls back to back).
+ * The default launch stays unless a configuration is more than 2 % faster.
+ * The choice is kept for batches whose shortest and longest lengths fall in
+ * the length buckets (of 16) of n_min and n_max, so that tuning one range
+ * leaves the others alone.  *tried (may be NULL) receives the number of
+ * configurations timed.  Synchronous; results never depend on the choice
+ * (only speed does).
  */
 int labs_autotune(labs_handle *h, const labs_tabu_params *p, int32_t n_min,
                   int32_t n_max, int64_t walks, uint64_t seed, int32_t *tried);
+
+/*
+ * Measured throughput of the units the walk kernels are bound by (the
+ * roofline's measured peaks; the published figures at 2.4 GHz are 157.3e12,
+ * 39.3e12 and 78.6e12): v_dot4_i32_i8 int8 products per second (four per
+ * lane per instruction), 32-bit integer adds per second, and bytes per
+ * second of conflict-free 16-byte LDS reads; and the shader clock during
+ * the dot-product load (its cycle counter against the 100 MHz constant
+ * one).  Each is one timed launch of independent dependency chains on every
+ * compute unit.  HOST outputs.  Synchronous (on the handle's stream); about
+ * 3 ms.
+ */
+int labs_device_peaks(labs_handle *h, double *dot4_products_per_s, double *int32_ops_per_s,
+                      double *lds_bytes_per_s, double *clock_hz);
 
 /* Memetic search (Alg. 1; one replica per wavefront, Alg. 3). */
 typedef enum labs_mut_rule {
@@ -309,14 +346,33 @@ typedef struct labs_memetic_params {
  *   hit_gen   device int64 [pops]: children produced when best <= target
  *             first held (0: the initial population), -1 if never (or NULL)
  *   gens_done device int64 [pops]: generations executed (or NULL)
- * Synchronous: returns after the outputs are written (it polls between
- * chunks for the early-stop rules).
+ * Asynchronous on `stream`: the population state lives in the handle's
+ * device memory (a later run on any stream waits for this one on the GPU),
+ * and every launch, copy and graph replay is enqueued on `stream`.  Chunk
+ * boundaries (every `chunk` generations) carry a device-side stop flag: with
+ * stop_all (Alg. 3's global termination flag) it is raised at the end of the
+ * chunk in which the first replica reached the target, and every later
+ * launch of the run does nothing.  Only then does the host wait: it reads
+ * the flag back two chunks behind, on events of `stream`, to stop
+ * enqueueing.  Without stop_all the call returns as soon as everything is
+ * enqueued.  Returns LABS_E_CANCELLED when labs_cancel was called while the
+ * call was still enqueueing; the outputs then hold each replica's state at
+ * the chunk boundary where it stopped (gens_done < generations).
  */
 int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
                      const int32_t *ns_host, int32_t n_uniform, int32_t pops,
                      uint64_t seed, int8_t *best_seq, int32_t out_stride,
                      int32_t *best_e, int64_t *hit_gen, int64_t *gens_done,
                      void *stream);
+
+/*
+ * Stop every labs_memetic_run of this handle that is running or still being
+ * enqueued: each stops at its next chunk boundary (the device reads the
+ * request from mapped host memory), and a call still enqueueing returns
+ * LABS_E_CANCELLED.  Runs started after this call are not affected.  May be
+ * called from any thread.
+ */
+int labs_cancel(labs_handle *h);
 
 /*
  * Serving: a request loop that runs memetic solves of different N from a

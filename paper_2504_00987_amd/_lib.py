@@ -20,8 +20,8 @@ EXPORTED = [
     "labs_create", "labs_destroy", "labs_last_error", "labs_status_name", "labs_version",
     "labs_energy_batch", "labs_skew_deviation_batch", "labs_bruteforce_min", "labs_tabu_batch",
     "labs_tabu_batch_noalloc",
-    "labs_set_launch", "labs_get_launch",
-    "labs_autotune", "labs_memetic_run", "labs_server_create", "labs_server_submit",
+    "labs_set_launch", "labs_get_launch", "labs_device_peaks",
+    "labs_autotune", "labs_memetic_run", "labs_cancel", "labs_server_create", "labs_server_submit",
     "labs_server_poll", "labs_server_cancel", "labs_server_stats", "labs_server_destroy",
 ]
 
@@ -29,12 +29,14 @@ EXPORTED = [
 class TabuParams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "steps_rule", "steps_a", "tenure_rule", "lo_num", "lo_den", "lo_add",
-        "hi_num", "hi_den", "hi_add", "aspiration")]
+        "hi_num", "hi_den", "hi_add", "aspiration", "slo_num", "slo_den", "shi_num",
+        "shi_den")]
 
 
 class Launch(ctypes.Structure):
-    _fields_ = [("waves_per_group", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("groups_per_cu", ctypes.c_int32)]
+    _fields_ = [("group_lanes", ctypes.c_int32), ("walks_per_group", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32),
+                ("layout", ctypes.c_int32)]
 
 
 class MemeticParams(ctypes.Structure):
@@ -81,12 +83,14 @@ def load():
     L.labs_tabu_batch.argtypes = [P, ctypes.POINTER(TabuParams), P, i32, P, i32, i64, u64,
                                   P, i32, P, P, P, i32, P]
     L.labs_tabu_batch_noalloc.argtypes = L.labs_tabu_batch.argtypes
+    L.labs_device_peaks.argtypes = [P] + [ctypes.POINTER(ctypes.c_double)] * 4
     L.labs_set_launch.argtypes = [P, ctypes.POINTER(Launch)]
-    L.labs_get_launch.argtypes = [P, i32, ctypes.POINTER(Launch)]
+    L.labs_get_launch.argtypes = [P, i32, i32, ctypes.POINTER(Launch)]
     L.labs_autotune.argtypes = [P, ctypes.POINTER(TabuParams), i32, i32, i64, u64,
                                 ctypes.POINTER(i32)]
     L.labs_memetic_run.argtypes = [P, ctypes.POINTER(MemeticParams), P, i32, i32, u64, P, i32,
                                    P, P, P, P]
+    L.labs_cancel.argtypes = [P]
     L.labs_server_create.argtypes = [P, ctypes.POINTER(MemeticParams), i32, PP]
     L.labs_server_submit.argtypes = [P, i32, u64, i32, i64, ctypes.POINTER(i64)]
     L.labs_server_poll.argtypes = [P, i64, P, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]

@@ -18,6 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblabs.so")
 SOURCES = ["labs_walk.hip", "labs_memetic_kernels.hip", "labs_brute.hip", "labs_skew.hip",
+           "labs_peaks.hip",
            "labs_api.cpp", "labs_memetic.cpp", "labs_server.cpp"]
 ARCH = "gfx950"
 

@@ -140,6 +140,14 @@ int check_rule(labs_handle *h, const RuleParams &r, int n) {
         tmax = (long long)r.steps_a * n;
     } else if (r.steps_rule == LABS_STEPS_PAPER) {
         tmax = n / 2 + n;
+    } else if (r.steps_rule == LABS_STEPS_RANGE) {
+        if (r.slo_den <= 0 || r.shi_den <= 0 || r.slo_num < 0 || r.shi_num < 0)
+            return fail(h, LABS_E_INVAL, "walk length fractions need num >= 0 and den > 0");
+        const long long tlo = (long long)r.slo_num * n / r.slo_den;
+        tmax = (long long)r.shi_num * n / r.shi_den;
+        if (tmax < tlo)
+            return fail(h, LABS_E_INVAL, "walk length range [%lld, %lld] empty for N=%d", tlo,
+                        tmax, n);
     } else {
         return fail(h, LABS_E_INVAL, "unknown steps_rule %d", r.steps_rule);
     }
@@ -167,6 +175,7 @@ int check_rule(labs_handle *h, const RuleParams &r, int n) {
 long long max_steps(const RuleParams &r, int n) {
     if (r.steps_rule == LABS_STEPS_FIXED) return r.steps_a;
     if (r.steps_rule == LABS_STEPS_MULT_N) return (long long)r.steps_a * n;
+    if (r.steps_rule == LABS_STEPS_RANGE) return (long long)r.shi_num * n / r.shi_den;
     return n / 2 + n;
 }
 
@@ -182,6 +191,10 @@ RuleParams to_rule(const labs_tabu_params &p) {
     r.hi_den = p.hi_den;
     r.hi_add = p.hi_add;
     r.aspiration = p.aspiration;
+    r.slo_num = p.slo_num;
+    r.slo_den = p.slo_den;
+    r.shi_num = p.shi_num;
+    r.shi_den = p.shi_den;
     return r;
 }
 
@@ -195,16 +208,42 @@ int bucket_of(int n) { return std::min(LABS_MAX_N / 16 - 1, std::max(0, (n - 1) 
 // per 256-lane workgroup, one per SIMD of a CU, time best there.
 labs_launch default_launch(int n_max) {
     labs_launch l;
-    l.waves_per_group = n_max <= 128 ? 1 : 4;
+    l.group_lanes = n_max <= 128 ? 64 : 256;
+    l.walks_per_group = n_max <= 128 ? 1 : 4;
     l.persistent = 0;
     l.groups_per_cu = 0;
+    l.layout = 0;
     return l;
 }
 
-int persistent_groups(labs_handle *h, const labs_launch &l) {
-    int per_cu = l.groups_per_cu;
-    if (per_cu <= 0) per_cu = std::max(1, 8 / std::max(1, (int)l.waves_per_group));
-    return per_cu * h->num_cus;
+// Lanes per walk 64 (one wavefront) or 128 (two, one walk per workgroup).
+const char *launch_problem(const labs_launch &l) {
+    const int g = l.group_lanes, w = l.walks_per_group;
+    if (g != 64 && g != 128 && g != 256) return "group_lanes must be 64, 128 or 256";
+    if (w != 1 && w != 2 && w != 4) return "walks_per_group must be 1, 2 or 4";
+    if (g / w < 64)
+        return "fewer than 64 lanes per walk (several walks per wavefront) are not built";
+    if (g / w > 128) return "four wavefronts per walk are not built";
+    if (g / w == 128 && w != 1)
+        return "two wavefronts per walk take one 128-lane workgroup each (a walk's barriers "
+               "are its workgroup's)";
+    if (l.persistent != 0 && l.persistent != 1) return "persistent must be 0 or 1";
+    if (l.groups_per_cu < 0 || l.groups_per_cu > 64) return "groups_per_cu out of [0, 64]";
+    if (l.layout < 0 || l.layout > 2) return "layout must be 0, 1 or 2";
+    return nullptr;
+}
+
+WalkLaunch walk_launch(const labs_handle *h, const labs_launch &l) {
+    WalkLaunch w;
+    w.split = l.group_lanes / l.walks_per_group == 128;
+    w.waves_per_group = l.group_lanes / 64;
+    w.lag = l.layout == 1 || (l.layout == 0 && w.split);
+    const int cus = std::max(1, h->num_cus);
+    w.groups = l.persistent
+                   ? cus * (l.groups_per_cu > 0 ? l.groups_per_cu : std::max(1, 8 / w.waves_per_group))
+                   : 0;
+    w.split_groups = l.persistent ? cus * (l.groups_per_cu > 0 ? l.groups_per_cu : 4) : 0;
+    return w;
 }
 
 }  // namespace liblabs
@@ -259,11 +298,24 @@ int labs_create(labs_handle **out, int device) {
         ok = h->max_children_wide >= 0;
     }
     if (ok) ok = noalloc_scratch_address(device, &h->scratch) == hipSuccess;
+    if (ok) ok = hipEventCreateWithFlags(&h->mem_event, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < 4 && ok; ++i)
+        ok = hipEventCreateWithFlags(&h->poll_event[i], hipEventDisableTiming) == hipSuccess;
+    if (ok) {
+        void *p = nullptr;
+        ok = hipHostMalloc(&p, 64, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
+        if (ok) {
+            h->cancel_host = (uint32_t *)p;
+            std::memset(p, 0, 64);
+            void *d = nullptr;
+            ok = hipHostGetDevicePointer(&d, p, 0) == hipSuccess;
+            h->cancel_dev = (uint32_t *)d;
+        }
+    }
     if (!ok) {
         labs_destroy(h);
         return LABS_E_HIP;
     }
-    h->tuned.assign(LABS_MAX_N / 16, labs_launch{0, 0, 0});
     *out = h;
     return LABS_OK;
 }
@@ -272,9 +324,19 @@ int labs_destroy(labs_handle *h) {
     if (!h) return LABS_OK;
     DeviceGuard g(h->device);
     hipDeviceSynchronize();
+    for (auto &r : h->retired) {
+        if (r.exec) hipGraphExecDestroy(r.exec);
+        if (r.graph) hipGraphDestroy(r.graph);
+        if (r.done) hipEventDestroy(r.done);
+    }
+    h->retired.clear();
     h->ws.release();
     h->mem.release();
     h->pin.release();
+    if (h->cancel_host) hipHostFree(h->cancel_host);
+    if (h->mem_event) hipEventDestroy(h->mem_event);
+    for (int i = 0; i < 4; ++i)
+        if (h->poll_event[i]) hipEventDestroy(h->poll_event[i]);
     if (h->ws_event) hipEventDestroy(h->ws_event);
     if (h->stage_event) hipEventDestroy(h->stage_event);
     if (h->sides.fork) hipEventDestroy(h->sides.fork);
@@ -382,22 +444,18 @@ int labs_set_launch(labs_handle *h, const labs_launch *launch) {
         h->has_override = false;
         return LABS_OK;
     }
-    const int w = launch->waves_per_group;
-    if (w != 1 && w != 2 && w != 4) return fail(h, LABS_E_INVAL, "waves_per_group must be 1, 2 or 4");
-    if (launch->persistent != 0 && launch->persistent != 1)
-        return fail(h, LABS_E_INVAL, "persistent must be 0 or 1");
-    if (launch->groups_per_cu < 0 || launch->groups_per_cu > 64)
-        return fail(h, LABS_E_INVAL, "groups_per_cu out of [0, 64]");
+    if (const char *why = launch_problem(*launch)) return fail(h, LABS_E_INVAL, "%s", why);
     h->override_launch = *launch;
     h->has_override = true;
     return LABS_OK;
 }
 
-int labs_get_launch(labs_handle *h, int32_t n, labs_launch *out) {
+int labs_get_launch(labs_handle *h, int32_t n_min, int32_t n_max, labs_launch *out) {
     if (!h || !out) return LABS_E_INVAL;
     h->last_error.clear();
-    if (n < LABS_MIN_N || n > LABS_MAX_N) return fail(h, LABS_E_INVAL, "n out of range");
-    *out = liblabs::choose_launch(h, n);
+    if (n_min < LABS_MIN_N || n_max > LABS_MAX_N || n_min > n_max)
+        return fail(h, LABS_E_INVAL, "bad length range [%d, %d]", n_min, n_max);
+    *out = liblabs::choose_launch(h, n_min, n_max);
     return LABS_OK;
 }
 
@@ -405,10 +463,10 @@ int labs_get_launch(labs_handle *h, int32_t n, labs_launch *out) {
 
 namespace liblabs {
 
-labs_launch choose_launch(labs_handle *h, int n_max) {
+labs_launch choose_launch(labs_handle *h, int n_min, int n_max) {
     if (h->has_override) return h->override_launch;
-    const labs_launch &t = h->tuned[bucket_of(n_max)];
-    if (t.waves_per_group != 0) return t;
+    const auto it = h->tuned.find({bucket_of(n_min), bucket_of(n_max)});
+    if (it != h->tuned.end()) return it->second;
     return default_launch(n_max);
 }
 
@@ -463,7 +521,9 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
     if (trace && trace_stride < tmax)
         return fail(h, LABS_E_INVAL, "trace_stride=%d < longest walk %lld", trace_stride, tmax);
 
-    const labs_launch L = force ? *force : choose_launch(h, n_max);
+    const labs_launch L = force ? *force : choose_launch(h, n_min, n_max);
+    if (const char *why = launch_problem(L)) return fail(h, LABS_E_INVAL, "%s", why);
+    const WalkLaunch WL = walk_launch(h, L);
 
     DeviceGuard g(h->device);
     // Workspace: [queue heads (32 words per class)] [ns (W int32)] [order (W int32)].
@@ -537,27 +597,14 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
     a.final_e = final_e;
     a.trace = trace;
     a.trace_stride = trace_stride;
-    const int groups = L.persistent ? persistent_groups(h, L) : 0;
-    // The launches present run concurrently: the first on `s`, the others on
-    // the handle's side streams, forked from and joined into `s`.  A launch
-    // is one length class, or classes 0..1 (N > 128) and classes 2..5
-    // (N <= 128) when more than one class of that range is present.
+    // The launch groups present run concurrently: the first on `s`, the
+    // others on the handle's side streams, forked from and joined into `s`.
     const SideStreams &sides = h->sides;
+    const WalkGroups wg = walk_launch_groups(a.class_end, WL.split);
     hipStream_t streams[kWalkClasses];
-    const bool mixed_long = mixed_long_classes(a.class_end);
-    const bool mixed_short = mixed_short_classes(a.class_end);
-    int n_sides = 0;
-    for (int c = 0, used = 0; c < kWalkClasses; ++c) {
-        const int64_t begin = c ? a.class_end[c - 1] : 0;
-        streams[c] = s;
-        bool present = a.class_end[c] > begin;
-        if (mixed_long && c < 2) present = c == 0;  // both non-empty
-        if (mixed_short && c >= 2) present = c == 2 && a.class_end[5] > a.class_end[1];
-        if (present && used++ > 0) streams[c] = sides.s[n_sides++];
-    }
-    if (mixed_long) streams[1] = streams[0];
-    if (mixed_short)
-        for (int c = 3; c < 6; ++c) streams[c] = streams[2];
+    const int n_sides = std::max(0, wg.n - 1);
+    streams[0] = s;
+    for (int g = 1; g < wg.n; ++g) streams[g] = sides.s[g - 1];
     hipError_t e = hipSuccess;
     if (n_sides > 0) {
         e = hipEventRecord(sides.fork, s);
@@ -565,7 +612,7 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
             e = hipStreamWaitEvent(sides.s[i], sides.fork, 0);
         if (e != hipSuccess) return hip_fail(h, e, "fork to side streams");
     }
-    e = launch_tabu(a, L.waves_per_group, groups, streams);
+    e = launch_tabu(a, WL, streams);
     if (e != hipSuccess) return hip_fail(h, e, "tabu kernel launch");
     for (int i = 0; i < n_sides && e == hipSuccess; ++i) {
         e = hipEventRecord(sides.join[i], sides.s[i]);
@@ -637,10 +684,18 @@ extern "C" int labs_autotune(labs_handle *h, const labs_tabu_params *p, int32_t 
     constexpr int kReps = 4;
     constexpr float kMargin = 0.98f;
     const bool uneven = n_min != n_max;
+    // layouts matter only where walks of 64 < N <= 128 are present
+    const bool wide = n_min <= 128 && n_max > 64;
     std::vector<labs_launch> cands{default_launch(n_max)};
-    for (int w : {1, 2, 4}) {
-        cands.push_back(labs_launch{w, 0, 0});
-        for (int gpc : {1, 2, 4, 8}) cands.push_back(labs_launch{w, 1, gpc * 4 / w});
+    for (int layout : wide ? std::vector<int>{2, 1} : std::vector<int>{0}) {
+        for (int w : {1, 2, 4}) {
+            cands.push_back(labs_launch{64 * w, w, 0, 0, layout});
+            for (int gpc : {1, 2, 4, 8}) cands.push_back(labs_launch{64 * w, w, 1, gpc * 4 / w, layout});
+        }
+        if (wide) {
+            cands.push_back(labs_launch{128, 1, 0, 0, layout});
+            for (int gpc : {1, 2, 4, 8}) cands.push_back(labs_launch{128, 1, 1, gpc, layout});
+        }
     }
     float best_ms = 1e30f;
     labs_launch best = cands[0];
@@ -651,9 +706,10 @@ extern "C" int labs_autotune(labs_handle *h, const labs_tabu_params *p, int32_t 
     };
     for (size_t i = 0; i < cands.size() && rc == LABS_OK; ++i) {
         const labs_launch &c = cands[i];
-        if (i > 0 && c.waves_per_group == cands[0].waves_per_group &&
-            c.persistent == cands[0].persistent && c.groups_per_cu == cands[0].groups_per_cu)
-            continue;  // the default, timed first
+        const WalkLaunch wc = walk_launch(h, c), w0 = walk_launch(h, cands[0]);
+        if (i > 0 && wc.waves_per_group == w0.waves_per_group && wc.split == w0.split &&
+            wc.lag == w0.lag && wc.groups == w0.groups && wc.split_groups == w0.split_groups)
+            continue;  // the same kernels as the default, timed first
         rc = run(c);
         hipEventRecord(e0, s);
         for (int rep = 0; rep < kReps && rc == LABS_OK; ++rep) rc = run(c);
@@ -674,7 +730,7 @@ extern "C" int labs_autotune(labs_handle *h, const labs_tabu_params *p, int32_t 
     hipFree(be);
     hipFree(fe);
     if (rc) return rc;
-    h->tuned[bucket_of(n_max)] = best;
+    h->tuned[{bucket_of(n_min), bucket_of(n_max)}] = best;
     if (tried) *tried = n_tried;
     return LABS_OK;
 }

@@ -305,8 +305,14 @@ __device__ __forceinline__ Schedule make_schedule(const RuleParams &r, int N, ui
     } else if (r.steps_rule == 1) {
         s.T = r.steps_a * N;
     } else {
+        // PAPER: floor(N/2) + U[0, N]; RANGE: U[lo, hi] from the same word
+        int lo = N / 2, span = N + 1;
+        if (r.steps_rule == 3) {
+            lo = r.slo_num * N / r.slo_den;
+            span = r.shi_num * N / r.shi_den - lo + 1;
+        }
         const Draw4 d = philox10(entity, gen, 0u, kTagLen, k0, k1);
-        s.T = N / 2 + (int)below(d.w0, (uint32_t)(N + 1));
+        s.T = lo + (int)below(d.w0, (uint32_t)span);
     }
     if (r.tenure_rule == 0) {
         s.lo = r.lo_num * N / r.lo_den + r.lo_add;

@@ -4,8 +4,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdarg>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/liblabs.h"
@@ -53,9 +56,29 @@ struct labs_handle {
     liblabs::DevBuf ws;                   // tabu workspace: queue head, ns, order
     liblabs::DevBuf mem;                  // memetic state and slot table
     liblabs::PinBuf pin;                  // pinned staging
+    // Memetic runs are stream-ordered: the next user of `mem` waits for
+    // mem_event; graphs of earlier runs are destroyed once their last
+    // launch has completed.
+    hipEvent_t mem_event = nullptr;
+    bool mem_event_valid = false;
+    struct Retired {
+        hipGraphExec_t exec;
+        hipGraph_t graph;
+        hipEvent_t done;
+    };
+    std::vector<Retired> retired;
+    // labs_cancel: word 0 of `cancel_host` (pinned, mapped for the device)
+    // holds the cancel epoch; a run keeps the epoch it started under and
+    // stops at its next chunk boundary once the word differs.  Words 1..4:
+    // stop-flag snapshots copied back for the host's polling.
+    uint32_t *cancel_host = nullptr;
+    uint32_t *cancel_dev = nullptr;
+    std::atomic<uint32_t> cancel_epoch{0};
+    hipEvent_t poll_event[4] = {};
     bool has_override = false;
-    labs_launch override_launch{1, 0, 0};
-    std::vector<labs_launch> tuned;    // per length bucket of 16
+    labs_launch override_launch{64, 1, 0, 0, 0};
+    // tuned launches by (length bucket of n_min, of n_max), buckets of 16
+    std::map<std::pair<int, int>, labs_launch> tuned;
 };
 
 namespace liblabs {
@@ -73,7 +96,9 @@ int stage_release(labs_handle *h, hipStream_t s);
 int check_rule(labs_handle *h, const RuleParams &r, int n);
 long long max_steps(const RuleParams &r, int n);
 RuleParams to_rule(const labs_tabu_params &p);
-labs_launch choose_launch(labs_handle *h, int n_max);
+labs_launch choose_launch(labs_handle *h, int n_min, int n_max);
+// The kernels' view of a launch configuration.
+WalkLaunch walk_launch(const labs_handle *h, const labs_launch &l);
 int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *starts,
                     int32_t start_stride, const int32_t *ns_host, int32_t n_uniform, int64_t W,
                     uint64_t seed, int8_t *best_seq, int32_t out_stride, int32_t *best_e,

@@ -14,6 +14,7 @@ struct RuleParams {
     int32_t steps_rule, steps_a, tenure_rule;
     int32_t lo_num, lo_den, lo_add, hi_num, hi_den, hi_add;
     int32_t aspiration;
+    int32_t slo_num, slo_den, shi_num, shi_den;  // LABS_STEPS_RANGE bounds
 };
 
 struct TabuLaunchArgs {
@@ -48,19 +49,55 @@ inline int walk_class(int n) {
 }
 // Streams besides the caller's one that a batch may fork onto.
 constexpr int kSideStreams = kWalkClasses - 1;
-// Whether the walks of N <= 128 (classes 2..5, consecutive positions of the
-// processing order) span more than one class: then they run in one launch,
-// on the stream of class 2 (which every class of the range uses).
-inline bool mixed_short_classes(const int64_t *class_end) {
-    int present = 0;
-    for (int c = 2; c < 6; ++c) present += class_end[c] > class_end[c - 1];
-    return present > 1;
+// Launch groups of a batch: runs of consecutive length classes (hence of
+// consecutive positions of the processing order) that one kernel launch
+// covers, each on a stream of its own.  Both classes of N > 128, when
+// present, share one launch (the four-neighbour layout serves both); so do
+// the classes of N <= 128 when more than one is present -- or, with
+// two-wavefront walks (split), classes 2..3 (64 < N <= 128) form one group
+// and classes 4..5 another.
+struct WalkGroups {
+    int n;
+    int first[kWalkClasses], last[kWalkClasses];
+};
+inline WalkGroups walk_launch_groups(const int64_t *class_end, bool split) {
+    WalkGroups g;
+    g.n = 0;
+    auto present = [&](int c) { return class_end[c] > (c ? class_end[c - 1] : 0); };
+    auto range = [&](int lo, int hi) {
+        int f = -1, z = -1;
+        for (int c = lo; c <= hi; ++c)
+            if (present(c)) {
+                if (f < 0) f = c;
+                z = c;
+            }
+        if (f < 0) return;
+        g.first[g.n] = f;
+        g.last[g.n] = z;
+        ++g.n;
+    };
+    range(0, 1);
+    if (split) {
+        if (present(2) || present(3)) {  // the two-wavefront kernel takes both
+            g.first[g.n] = 2;
+            g.last[g.n] = 3;
+            ++g.n;
+        }
+        range(4, 5);
+    } else {
+        range(2, 5);
+    }
+    return g;
 }
-// Whether both classes of N > 128 (0 and 1, positions [0, class_end[1]))
-// are present: then they likewise run in one launch, on the stream of class 0.
-inline bool mixed_long_classes(const int64_t *class_end) {
-    return class_end[0] > 0 && class_end[1] > class_end[0];
-}
+
+// How labs_tabu_batch launches its walks.
+struct WalkLaunch {
+    int waves_per_group;  // one-wavefront walks: 1, 2 or 4 per workgroup
+    bool split;           // walks of 64 < N <= 128 on two wavefronts each
+    bool lag;             // walks of 64 < N <= 128 in the lag form
+    int groups;           // persistent grid of the one-wavefront kernels (0: none)
+    int split_groups;     // persistent grid of the two-wavefront kernel (0: none)
+};
 
 // Words of a sequence mask in the memetic state (N <= 256).
 constexpr int kStateWords = 4;
@@ -111,6 +148,7 @@ struct MemeticLaunchArgs {
     int32_t children;        // children per generation (1: Alg. 1)
     MemeticStateDev st;
     uint32_t *any_hit;       // set to 1 when a replica reaches its target
+    const uint32_t *stop;    // nonzero: the launch does nothing (null: never)
 };
 
 // Fixed device scratch of the allocation-free tabu batch: queue heads, then
@@ -146,13 +184,18 @@ struct BruteParts {
 int64_t brute_waves(int n);
 hipError_t launch_bruteforce(int n, const BruteParts &p, hipStream_t s);
 
-// waves_per_group in {1,2,4}; persistent grid = groups (0: one wave per walk).
-// Length class c runs on streams[c] (entries may coincide); a.counter must
-// point at 32 * kWalkClasses writable uint32 (one queue head per class).
-hipError_t launch_tabu(const TabuLaunchArgs &a, int waves_per_group, int groups,
-                       const hipStream_t *streams);
+// Launch group g (walk_launch_groups(a.class_end, l.split)) runs on
+// streams[g]; a.counter must point at 32 * kWalkClasses writable uint32 (the
+// queue head of a group at 32 * its first class).
+hipError_t launch_tabu(const TabuLaunchArgs &a, const WalkLaunch &l, const hipStream_t *streams);
 
 hipError_t launch_memetic_init(const MemeticLaunchArgs &a, hipStream_t s);
+// At a chunk boundary: *stop becomes (and stays) 1 when stop_all is set and
+// *any_hit is, or when *cancel (host memory mapped for the device) no
+// longer holds `epoch`.  One thread; capturable.
+hipError_t launch_memetic_latch(const uint32_t *any_hit, uint32_t *stop,
+                                const volatile uint32_t *cancel, uint32_t epoch, int stop_all,
+                                hipStream_t s);
 // Once per device before the first launch: raises the dynamic LDS limit of
 // the batched-generation kernels to what kMaxChildren children need (N > 128:
 // as far as the device allows).  Returns the most children per generation

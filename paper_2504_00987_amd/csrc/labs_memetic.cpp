@@ -69,6 +69,47 @@ int check_memetic(labs_handle *h, const labs_memetic_params *p) {
 
 using namespace liblabs;
 
+namespace {
+
+// Graphs of earlier runs whose last launch has completed are destroyed.
+void reap_graphs(labs_handle *h, bool wait) {
+    for (size_t i = 0; i < h->retired.size();) {
+        labs_handle::Retired &r = h->retired[i];
+        if (wait) hipEventSynchronize(r.done);
+        if (hipEventQuery(r.done) == hipSuccess) {
+            hipGraphExecDestroy(r.exec);
+            hipGraphDestroy(r.graph);
+            hipEventDestroy(r.done);
+            r = h->retired.back();
+            h->retired.pop_back();
+        } else {
+            (void)hipGetLastError();  // hipErrorNotReady
+            ++i;
+        }
+    }
+}
+
+// The memetic state buffer `mem` is shared by the handle's runs on any
+// stream: a new run waits (on the GPU) for the previous one, and the host
+// waits only when the buffer must grow.
+int mem_acquire(labs_handle *h, hipStream_t s, size_t bytes) {
+    if (h->mem_event_valid) {
+        hipError_t e = bytes > h->mem.size ? hipEventSynchronize(h->mem_event)
+                                           : hipStreamWaitEvent(s, h->mem_event, 0);
+        if (e != hipSuccess) return hip_fail(h, e, "memetic state wait");
+    }
+    return h->mem.reserve(h, bytes);
+}
+
+}  // namespace
+
+extern "C" int labs_cancel(labs_handle *h) {
+    if (!h) return LABS_E_INVAL;
+    const uint32_t next = h->cancel_epoch.fetch_add(1u) + 1u;
+    if (h->cancel_host) __atomic_store_n(&h->cancel_host[0], next, __ATOMIC_SEQ_CST);
+    return LABS_OK;
+}
+
 extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
                                 const int32_t *ns_host, int32_t n_uniform, int32_t pops,
                                 uint64_t seed, int8_t *best_seq, int32_t out_stride,
@@ -83,7 +124,7 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
     if (!best_seq || !best_e) return fail(h, LABS_E_INVAL, "null output");
     const RuleParams rule = to_rule(p->tabu);
     int n_max = 0;
-    std::vector<char> seen(LABS_MAX_N + 1, 0);
+    char seen[LABS_MAX_N + 1] = {};
     for (int i = 0; i < pops; ++i) {
         const int n = ns_host ? ns_host[i] : n_uniform;
         if (n < LABS_MIN_N || n > LABS_MAX_N)
@@ -95,24 +136,34 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
         n_max = std::max(n_max, n);
     }
     if (out_stride < n_max) return fail(h, LABS_E_INVAL, "out_stride=%d < N=%d", out_stride, n_max);
+    int classes = 0;
+    int64_t n_wide = 0;
+    for (int i = 0; i < pops; ++i) {
+        const int c = memetic_class(ns_host ? ns_host[i] : n_uniform);
+        classes |= 1 << c;
+        n_wide += c == 1;
+    }
+    const int children = std::max(1, (int)p->children);
+    if ((rc = check_children(h, children, classes))) return rc;
 
+    // Everything below is enqueued on the caller's stream.
     DeviceGuard g(h->device);
-    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize(caller stream)");
-    hipStream_t s = h->stream;
+    hipStream_t s = (hipStream_t)stream;
+    reap_graphs(h, false);
+    const uint32_t epoch = h->cancel_epoch.load();
 
-    // Device memory: [slots][ns][any_hit][state]
+    // Device memory: [slots][ns][flags: any_hit, stop][state]
     size_t state_bytes = 0;
     carve_state(nullptr, pops, p->K, &state_bytes);
     const size_t slots_bytes = (size_t)pops * sizeof(MemeticSlot);
     const size_t off_ns = (slots_bytes + 255) & ~(size_t)255;
     const size_t off_flag = off_ns + (((size_t)pops * 4 + 255) & ~(size_t)255);
     const size_t off_state = off_flag + 256;
-    if ((rc = h->mem.reserve(h, off_state + state_bytes))) return rc;
+    if ((rc = mem_acquire(h, s, off_state + state_bytes))) return rc;
     char *base = (char *)h->mem.ptr;
     MemeticSlot *d_slots = (MemeticSlot *)base;
     int32_t *d_ns = (int32_t *)(base + off_ns);
-    uint32_t *d_flag = (uint32_t *)(base + off_flag);
+    uint32_t *d_flag = (uint32_t *)(base + off_flag);  // [0] any_hit, [1] stop
     MemeticStateDev st = carve_state(base + off_state, pops, p->K, nullptr);
 
     const size_t stage = off_flag;  // slots + ns
@@ -132,7 +183,7 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
         hs[i].state = i;
         hn[i] = n;
     }
-    e = hipMemcpyAsync(base, h->pin.ptr, stage, hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(base, h->pin.ptr, stage, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(h, e, "hipMemcpyAsync(slots)");
     if ((rc = stage_release(h, s))) return rc;  // the staging copy is in flight
 
@@ -147,34 +198,36 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
     a.rule = rule;
     a.st = st;
     a.any_hit = d_flag;
-    a.classes = 0;
-    int64_t n_wide = 0;
-    for (int i = 0; i < pops; ++i) {
-        const int c = memetic_class(ns_host ? ns_host[i] : n_uniform);
-        a.classes |= 1 << c;
-        n_wide += c == 1;
-    }
+    a.stop = d_flag + 1;
+    a.classes = classes;
     a.split_wide = split_wide(h, p->waves_per_replica, n_wide);
-    a.children = std::max(1, (int)p->children);
-    if ((rc = check_children(h, a.children, a.classes))) return rc;
-    if ((e = launch_fill_u32(d_flag, 0u, 1, s)) != hipSuccess) return hip_fail(h, e, "fill");
+    a.children = children;
+    if ((e = launch_fill_u32(d_flag, 0u, 2, s)) != hipSuccess) return hip_fail(h, e, "fill");
     if ((e = launch_memetic_init(a, s)) != hipSuccess) return hip_fail(h, e, "memetic init");
 
-    const bool poll = p->stop_all && target >= 0;
+    // Chunk boundaries: the latch turns a reached target (stop_all) or a
+    // cancel into the stop flag every later launch of the run reads first,
+    // so the outcome is fixed by the chunk in which the first replica hit,
+    // whenever the host notices.  With stop_all the host reads the flag back
+    // two chunks behind and stops enqueueing once it is set.
+    const bool stop_all = p->stop_all && target >= 0;
     const int64_t G = p->generations;
     const int64_t chunk = p->chunk;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     if (p->mode == LABS_MODE_GRAPH && G > 0) {
-        // Capture `chunk` one-generation launches once; replay them.
+        // Capture the latch and `chunk` one-generation launches once (on the
+        // handle's stream, which may be captured; the caller's may be the
+        // null stream); replay them on the caller's stream.
         MemeticLaunchArgs one = a;
         one.gens = 1;
         const int64_t n_launch = std::min<int64_t>(chunk, G);
-        e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(h, e, "hipStreamBeginCapture");
+        e = launch_memetic_latch(d_flag, d_flag + 1, h->cancel_dev, epoch, stop_all, h->stream);
         for (int64_t i = 0; i < n_launch && e == hipSuccess; ++i)
-            e = launch_memetic_advance(one, s, &h->sides);
-        hipError_t e2 = hipStreamEndCapture(s, &graph);
+            e = launch_memetic_advance(one, h->stream, &h->sides);
+        hipError_t e2 = hipStreamEndCapture(h->stream, &graph);
         if (e != hipSuccess || e2 != hipSuccess) {
             if (graph) hipGraphDestroy(graph);
             return hip_fail(h, e != hipSuccess ? e : e2, "graph capture");
@@ -187,49 +240,80 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
     }
 
     rc = LABS_OK;
+    bool cancelled = false;
+    constexpr int kLag = 2;
+    int64_t n_chunks = 0;
     for (int64_t done = 0; done < G;) {
         const int64_t step = std::min(chunk, G - done);
-        if (p->mode == LABS_MODE_PLAIN) {
-            MemeticLaunchArgs one = a;
-            one.gens = 1;
-            for (int64_t i = 0; i < step && e == hipSuccess; ++i)
-                e = launch_memetic_advance(one, s, &h->sides);
-        } else if (p->mode == LABS_MODE_GRAPH) {
-            // Launches beyond a replica's generation limit return at once, so
-            // the final replay may safely run past G.
+        if (p->mode == LABS_MODE_GRAPH) {
+            // launches past a replica's generation limit return at once, so
+            // the final replay may safely run past G
             e = hipGraphLaunch(exec, s);
         } else {
-            MemeticLaunchArgs many = a;
-            many.gens = (int32_t)step;
-            e = launch_memetic_advance(many, s, &h->sides);
+            e = launch_memetic_latch(d_flag, d_flag + 1, h->cancel_dev, epoch, stop_all, s);
+            if (p->mode == LABS_MODE_PLAIN) {
+                MemeticLaunchArgs one = a;
+                one.gens = 1;
+                for (int64_t i = 0; i < step && e == hipSuccess; ++i)
+                    e = launch_memetic_advance(one, s, &h->sides);
+            } else if (e == hipSuccess) {
+                MemeticLaunchArgs many = a;
+                many.gens = (int32_t)step;
+                e = launch_memetic_advance(many, s, &h->sides);
+            }
         }
         if (e != hipSuccess) {
             rc = hip_fail(h, e, "memetic advance");
             break;
         }
         done += p->mode == LABS_MODE_GRAPH ? std::min<int64_t>(chunk, G) : step;
-        if (poll && done < G) {
-            uint32_t flag = 0;
-            e = hipMemcpyAsync(&flag, d_flag, sizeof(flag), hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (h->cancel_epoch.load() != epoch) {
+            cancelled = true;  // the device stops at its next latch
+            break;
+        }
+        if (stop_all && done < G) {
+            // snapshot of any_hit after this chunk, read kLag chunks later
+            const int slot = (int)(n_chunks % 4);
+            e = hipMemcpyAsync(h->cancel_host + 1 + slot, d_flag, sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipEventRecord(h->poll_event[slot], s);
+            if (e == hipSuccess && n_chunks >= kLag) {
+                const int old = (int)((n_chunks - kLag) % 4);
+                e = hipEventSynchronize(h->poll_event[old]);
+                if (e == hipSuccess && __atomic_load_n(&h->cancel_host[1 + old], __ATOMIC_ACQUIRE)) {
+                    ++n_chunks;
+                    break;
+                }
+            }
             if (e != hipSuccess) {
                 rc = hip_fail(h, e, "flag poll");
                 break;
             }
-            if (flag) {
-                // Global termination: every replica stops here.  The stop is
-                // at a chunk boundary, so the outcome is deterministic.
-                break;
-            }
+            ++n_chunks;
         }
     }
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
+    if (rc == LABS_OK) {
+        e = launch_gather_best(st, nullptr, d_ns, 0, pops, best_seq, out_stride, best_e, hit_gen,
+                               gens_done, s);
+        if (e != hipSuccess) rc = hip_fail(h, e, "gather");
+    }
+    hipError_t er = hipEventRecord(h->mem_event, s);
+    if (er == hipSuccess) h->mem_event_valid = true;
+    if (exec) {
+        hipEvent_t done_ev = nullptr;
+        if (er == hipSuccess && hipEventCreateWithFlags(&done_ev, hipEventDisableTiming) == hipSuccess &&
+            hipEventRecord(done_ev, s) == hipSuccess) {
+            h->retired.push_back({exec, graph, done_ev});
+        } else {
+            // cannot tell when its launches end: wait for them here
+            hipStreamSynchronize(s);
+            if (done_ev) hipEventDestroy(done_ev);
+            hipGraphExecDestroy(exec);
+            hipGraphDestroy(graph);
+        }
+    }
     if (rc) return rc;
-    e = launch_gather_best(st, nullptr, d_ns, 0, pops, best_seq, out_stride, best_e, hit_gen,
-                           gens_done, s);
-    if (e != hipSuccess) return hip_fail(h, e, "gather");
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+    if (er != hipSuccess) return hip_fail(h, er, "hipEventRecord");
+    if (cancelled) return fail(h, LABS_E_CANCELLED, "cancelled by labs_cancel");
     return LABS_OK;
 }

@@ -208,6 +208,7 @@ __attribute__((amdgpu_waves_per_eu(1, SPLIT == 2 ? 2 : 8))) void memetic_advance
     __shared__ __attribute__((aligned(16))) uint8_t lds[walk_lds_bytes<NW, kAdvanceLag<NW, SPLIT>>()];
     const int s = blockIdx.x;
     if (s >= a.n_slots) return;
+    if (a.stop != nullptr && *a.stop != 0u) return;  // one value for the whole grid
     const MemeticSlot sl = a.slots[s];
     if (sl.state < 0 || (1 << memetic_class(sl.n)) != NW) return;
     memetic_replica<NW, SPLIT>(a, sl, pop, popE, lds, SPLIT == 1 ? 0 : (int)(threadIdx.x >> 6));
@@ -243,6 +244,7 @@ __global__ __launch_bounds__(64 * kMaxChildren) void memetic_batched_kernel(
     uint64_t *res = (uint64_t *)(dyn_lds + kMaxK * (8 * NW + 4));  // [B][kResWords]
     const int s = blockIdx.x;
     if (s >= a.n_slots) return;
+    if (a.stop != nullptr && *a.stop != 0u) return;  // one value for the whole grid
     const MemeticSlot sl = a.slots[s];
     if (sl.state < 0 || (1 << memetic_class(sl.n)) != NW) return;
     const int B = a.children;
@@ -337,6 +339,15 @@ __global__ __launch_bounds__(64 * kMaxChildren) void memetic_batched_kernel(
     if (hit >= 0 && a.any_hit != nullptr) atomicOr(a.any_hit, 1u);
 }
 
+// The stop latch of a chunk boundary (see launch_memetic_latch).
+__global__ void memetic_latch_kernel(const uint32_t *any_hit, uint32_t *stop,
+                                     const volatile uint32_t *cancel, uint32_t epoch,
+                                     int stop_all) {
+    const bool hit = stop_all != 0 && *any_hit != 0u;
+    const bool cancelled = cancel != nullptr && *cancel != epoch;
+    if (hit || cancelled) *stop = 1u;
+}
+
 __global__ void gather_best_kernel(MemeticStateDev st, const int32_t *__restrict__ state_idx,
                                    const int32_t *__restrict__ ns, int32_t n_uniform,
                                    int32_t count, int8_t *__restrict__ best_seq,
@@ -362,6 +373,14 @@ __global__ void gather_best_kernel(MemeticStateDev st, const int32_t *__restrict
 hipError_t launch_memetic_init(const MemeticLaunchArgs &a, hipStream_t s) {
     if (a.n_slots <= 0) return hipSuccess;
     hipLaunchKernelGGL(memetic_init_kernel, dim3((unsigned)a.n_slots), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_memetic_latch(const uint32_t *any_hit, uint32_t *stop,
+                                const volatile uint32_t *cancel, uint32_t epoch, int stop_all,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(memetic_latch_kernel, dim3(1), dim3(1), 0, s, any_hit, stop, cancel, epoch,
+                       stop_all);
     return hipGetLastError();
 }
 

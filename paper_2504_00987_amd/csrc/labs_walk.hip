@@ -58,9 +58,11 @@ __global__ __launch_bounds__(64 * WPG) void energy_kernel(const int8_t *__restri
 // ---------------------------------------------------------------------------
 // Batched tabu walks.
 // ---------------------------------------------------------------------------
-template <int NW, int NB, bool TRACE>
-__device__ void run_tabu_item(const TabuLaunchArgs &a, int64_t w, int N, uint8_t *lds) {
-    using Mask = typename MaskOf<NW>::type;
+// Start mask of walk w: row w of the caller's starts, or the draws
+// (w, 0, q, START) (bits 128 q .. 128 q + 127).
+template <int NW>
+__device__ __forceinline__ typename MaskOf<NW>::type walk_start(const TabuLaunchArgs &a,
+                                                                int64_t w, int N) {
     const int lane = lane_id();
     uint64_t wd[4] = {0ull, 0ull, 0ull, 0ull};
     if (a.starts != nullptr) {
@@ -71,7 +73,6 @@ __device__ void run_tabu_item(const TabuLaunchArgs &a, int64_t w, int N, uint8_t
             wd[h] = ballot(i < N && row[i] < 0);
         }
     } else {
-        // bits 128 q .. 128 q + 127 are the draw (walk, 0, q, START)
 #pragma unroll
         for (int q = 0; q < (NW + 1) / 2; ++q) {
             const Draw4 d = philox10((uint32_t)w, 0u, (uint32_t)q, kTagStart, a.k0, a.k1);
@@ -84,16 +85,46 @@ __device__ void run_tabu_item(const TabuLaunchArgs &a, int64_t w, int N, uint8_t
             wd[h] &= b >= 64 ? ~0ull : b <= 0 ? 0ull : ((1ull << b) - 1ull);
         }
     }
-    const Mask M = make_mask<NW>(wd[0], wd[1], wd[2], wd[3]);
+    return make_mask<NW>(wd[0], wd[1], wd[2], wd[3]);
+}
+
+// One walk on one wavefront: NW neighbours per lane, windows of NB chunks,
+// the lag form when LAG (N <= 128), else the record form.
+template <int NW, int NB, bool TRACE, bool LAG = (NW == 1)>
+__device__ void run_tabu_item(const TabuLaunchArgs &a, int64_t w, int N, uint8_t *lds) {
+    const int lane = lane_id();
+    const auto M = walk_start<NW>(a, w, N);
     const Schedule sch = make_schedule(a.rule, N, a.k0, a.k1, (uint32_t)w, 0u);
     const WalkResult<NW> r =
-        tabu_walk<NW, TRACE, 1, NB>(N, M, sch, a.rule.aspiration, a.k0, a.k1, (uint32_t)w, 0u, lds,
-                                    TRACE ? a.trace + w * (int64_t)a.trace_stride : nullptr);
+        tabu_walk<NW, TRACE, 1, NB, LAG>(N, M, sch, a.rule.aspiration, a.k0, a.k1, (uint32_t)w, 0u,
+                                         lds, TRACE ? a.trace + w * (int64_t)a.trace_stride : nullptr);
     int8_t *out = a.best_seq + w * (int64_t)a.out_stride;
     for (int i = lane; i < a.out_stride; i += 64)
         out[i] = i < N ? (m_bit(r.best, i) ? (int8_t)-1 : (int8_t)1) : (int8_t)0;
     a.best_e[w] = r.best_e;  // uniform values, stored by every lane
     a.final_e[w] = r.final_e;
+}
+
+// One walk of 64 < N <= 128 on the two wavefronts of a 128-lane workgroup,
+// wavefront `part` owning neighbours and lags 64 part .. 64 part + 63; each
+// writes half of the output row.
+template <int NB, bool TRACE, bool LAG>
+__device__ void run_split_item(const TabuLaunchArgs &a, int64_t w, int N, uint8_t *lds,
+                               int part) {
+    const int lane = lane_id();
+    const auto M = walk_start<2>(a, w, N);
+    const Schedule sch = make_schedule(a.rule, N, a.k0, a.k1, (uint32_t)w, 0u);
+    const WalkResult<2> r =
+        tabu_walk<2, TRACE, 2, NB, LAG>(N, M, sch, a.rule.aspiration, a.k0, a.k1, (uint32_t)w, 0u,
+                                        lds, TRACE ? a.trace + w * (int64_t)a.trace_stride : nullptr,
+                                        part);
+    int8_t *out = a.best_seq + w * (int64_t)a.out_stride;
+    for (int i = lane + 64 * part; i < a.out_stride; i += 128)
+        out[i] = i < N ? (m_bit(r.best, i) ? (int8_t)-1 : (int8_t)1) : (int8_t)0;
+    if (part == 0) {
+        a.best_e[w] = r.best_e;  // uniform values, stored by every lane of wavefront 0
+        a.final_e[w] = r.final_e;
+    }
 }
 
 // Next index of the persistent work queue, wave-uniform.  Every lane executes
@@ -113,24 +144,69 @@ __device__ __forceinline__ uint32_t next_work(uint32_t *counter) {
 // through the queue head `counter`; otherwise one wave per position.
 // TRACE: record every walk's moves (a separate instantiation, so that the
 // untraced kernel does not carry the registers of the traced one).
-template <int NW, int NB, int WPG, bool PERSIST, bool TRACE>
+template <int NW, int NB, int WPG, bool PERSIST, bool TRACE, bool LAG = (NW == 1)>
 __global__ __launch_bounds__(64 * WPG) void tabu_kernel(TabuLaunchArgs a, int64_t begin,
                                                         int64_t end, uint32_t *counter) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds_all[WPG][walk_lds_bytes<NW>()];
+    __shared__ __attribute__((aligned(16))) uint8_t lds_all[WPG][walk_lds_bytes<NW, LAG>()];
     const int wave = threadIdx.x >> 6;
     uint8_t *lds = lds_all[wave];
     if constexpr (PERSIST) {
         for (int64_t pos = begin + next_work(counter); pos < end;
              pos = begin + next_work(counter)) {
             const int64_t w = a.order ? (int64_t)a.order[pos] : pos;
-            run_tabu_item<NW, NB, TRACE>(a, w, a.ns ? a.ns[w] : a.n_uniform, lds);
+            run_tabu_item<NW, NB, TRACE, LAG>(a, w, a.ns ? a.ns[w] : a.n_uniform, lds);
         }
     } else {
         const int64_t pos = begin + (int64_t)blockIdx.x * WPG + wave;
         if (pos < end) {
             const int64_t w = a.order ? (int64_t)a.order[pos] : pos;
-            run_tabu_item<NW, NB, TRACE>(a, w, a.ns ? a.ns[w] : a.n_uniform, lds);
+            run_tabu_item<NW, NB, TRACE, LAG>(a, w, a.ns ? a.ns[w] : a.n_uniform, lds);
         }
+    }
+}
+
+// Walks of 64 < N <= 128 at positions [begin, end), one per 128-lane
+// workgroup of two wavefronts (the walk's barriers are the workgroup's).
+// Each walk spans the fewest 16-lag chunks that hold its N - 1 lags.  The
+// persistent form: wavefront 0 takes the next position from the queue and
+// hands it to wavefront 1 through LDS, so both run the same walk and reach
+// the same barriers, and both leave when the queue is drained.
+template <bool TRACE, bool LAG>
+__device__ __forceinline__ void run_split_range_item(const TabuLaunchArgs &a, int64_t pos,
+                                                     uint8_t *lds, int part) {
+    const int64_t w = a.order ? (int64_t)a.order[pos] : pos;
+    const int N = __builtin_amdgcn_readfirstlane(a.ns ? a.ns[w] : a.n_uniform);
+    if (N > 113)
+        run_split_item<8, TRACE, LAG>(a, w, N, lds, part);
+    else if (N > kClassMaxN[3])
+        run_split_item<7, TRACE, LAG>(a, w, N, lds, part);
+    else if (N > 81)
+        run_split_item<6, TRACE, LAG>(a, w, N, lds, part);
+    else
+        run_split_item<5, TRACE, LAG>(a, w, N, lds, part);
+}
+
+template <bool PERSIST, bool TRACE, bool LAG>
+__global__ __launch_bounds__(128) void tabu_kernel_split(TabuLaunchArgs a, int64_t begin,
+                                                         int64_t end, uint32_t *counter) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[walk_lds_bytes<2, LAG>()];
+    __shared__ int64_t shared_pos;
+    const int part = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if constexpr (PERSIST) {
+        for (;;) {
+            if (part == 0) {
+                const int64_t p = begin + next_work(counter);
+                shared_pos = p;  // uniform value, every lane of wavefront 0
+            }
+            __syncthreads();
+            const int64_t pos = (int64_t)__builtin_amdgcn_readfirstlane((int)(shared_pos - begin)) + begin;
+            __syncthreads();  // both have read before wavefront 0 writes again
+            if (pos >= end) break;
+            run_split_range_item<TRACE, LAG>(a, pos, lds, part);
+        }
+    } else {
+        const int64_t pos = begin + (int64_t)blockIdx.x;
+        if (pos < end) run_split_range_item<TRACE, LAG>(a, pos, lds, part);
     }
 }
 
@@ -144,19 +220,19 @@ __global__ __launch_bounds__(64 * WPG) void tabu_kernel(TabuLaunchArgs a, int64_
 constexpr int kMixedLds = walk_lds_bytes<2>() > walk_lds_bytes<1>() ? walk_lds_bytes<2>()
                                                                     : walk_lds_bytes<1>();
 
-template <bool TRACE>
+template <bool TRACE, bool LAG>
 __device__ __forceinline__ void run_mixed_item(const TabuLaunchArgs &a, int64_t w, uint8_t *lds) {
     // windows of the fewest 16-lag chunks that hold N - 1 lags (within the
     // launch, finer steps than the classes cost only code)
     const int N = __builtin_amdgcn_readfirstlane(a.ns ? a.ns[w] : a.n_uniform);
     if (N > 113)
-        run_tabu_item<2, 8, TRACE>(a, w, N, lds);
+        run_tabu_item<2, 8, TRACE, LAG>(a, w, N, lds);
     else if (N > kClassMaxN[3])
-        run_tabu_item<2, 7, TRACE>(a, w, N, lds);
+        run_tabu_item<2, 7, TRACE, LAG>(a, w, N, lds);
     else if (N > 81)
-        run_tabu_item<2, 6, TRACE>(a, w, N, lds);
+        run_tabu_item<2, 6, TRACE, LAG>(a, w, N, lds);
     else if (N > kClassMaxN[4])
-        run_tabu_item<2, 5, TRACE>(a, w, N, lds);
+        run_tabu_item<2, 5, TRACE, LAG>(a, w, N, lds);
     else if (N > kClassMaxN[5])
         run_tabu_item<1, 4, TRACE>(a, w, N, lds);
     else
@@ -177,32 +253,36 @@ __device__ __forceinline__ void run_mixed_long_item(const TabuLaunchArgs &a, int
         run_tabu_item<4, 12, TRACE>(a, w, N, lds);
 }
 
-template <bool TRACE, bool LONG>
+template <bool TRACE, bool LONG, bool LAG>
 __device__ __forceinline__ void run_mixed_range_item(const TabuLaunchArgs &a, int64_t pos,
                                                      uint8_t *lds) {
     const int64_t w = a.order ? (int64_t)a.order[pos] : pos;
     if constexpr (LONG)
         run_mixed_long_item<TRACE>(a, w, lds);
     else
-        run_mixed_item<TRACE>(a, w, lds);
+        run_mixed_item<TRACE, LAG>(a, w, lds);
 }
 
 // LONG selects the N > 128 range (four wavefronts per SIMD is a hint for the
 // short range only, whose default launch is one walk per workgroup).
-template <int WPG, bool PERSIST, bool TRACE, bool LONG>
-__global__ __launch_bounds__(64 * WPG) __attribute__((amdgpu_waves_per_eu(WPG == 1 && !PERSIST && !LONG ? 4 : 1))) void tabu_kernel_mixed(TabuLaunchArgs a, int64_t begin,
+template <int WPG, bool PERSIST, bool TRACE, bool LONG, bool LAG>
+__global__ __launch_bounds__(64 * WPG) __attribute__((amdgpu_waves_per_eu(WPG == 1 && !PERSIST && !LONG && !LAG ? 4 : 1))) void tabu_kernel_mixed(TabuLaunchArgs a, int64_t begin,
                                                               int64_t end, uint32_t *counter) {
-    constexpr int kLds = LONG ? walk_lds_bytes<4>() : kMixedLds;
+    constexpr int kLds = LONG ? walk_lds_bytes<4>()
+                              : (LAG ? (walk_lds_bytes<2, true>() > walk_lds_bytes<1>()
+                                            ? walk_lds_bytes<2, true>()
+                                            : walk_lds_bytes<1>())
+                                     : kMixedLds);
     __shared__ __attribute__((aligned(16))) uint8_t lds_all[WPG][kLds];
     const int wave = threadIdx.x >> 6;
     uint8_t *lds = lds_all[wave];
     if constexpr (PERSIST) {
         for (int64_t pos = begin + next_work(counter); pos < end;
              pos = begin + next_work(counter))
-            run_mixed_range_item<TRACE, LONG>(a, pos, lds);
+            run_mixed_range_item<TRACE, LONG, LAG>(a, pos, lds);
     } else {
         const int64_t pos = begin + (int64_t)blockIdx.x * WPG + wave;
-        if (pos < end) run_mixed_range_item<TRACE, LONG>(a, pos, lds);
+        if (pos < end) run_mixed_range_item<TRACE, LONG, LAG>(a, pos, lds);
     }
 }
 
@@ -281,92 +361,130 @@ hipError_t launch_energy(const int8_t *seqs, const int32_t *ns, int32_t n_unifor
 
 namespace {
 
-template <int NW, int NB, int WPG, bool TRACE>
+template <int NW, int NB, int WPG, bool TRACE, bool LAG>
 hipError_t launch_tabu_part_t(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
                               uint32_t *counter, hipStream_t s) {
     if (groups > 0) {
         hipError_t e = launch_fill_u32(counter, 0u, 1, s);
         if (e != hipSuccess) return e;
         const int64_t need = (end - begin + WPG - 1) / WPG;
-        hipLaunchKernelGGL((tabu_kernel<NW, NB, WPG, true, TRACE>),
+        hipLaunchKernelGGL((tabu_kernel<NW, NB, WPG, true, TRACE, LAG>),
                            dim3((unsigned)std::min<int64_t>(groups, need)), dim3(64 * WPG), 0, s, a,
                            begin, end, counter);
     } else {
         const int64_t grid = (end - begin + WPG - 1) / WPG;
-        hipLaunchKernelGGL((tabu_kernel<NW, NB, WPG, false, TRACE>), dim3((unsigned)grid),
+        hipLaunchKernelGGL((tabu_kernel<NW, NB, WPG, false, TRACE, LAG>), dim3((unsigned)grid),
                            dim3(64 * WPG), 0, s, a, begin, end, counter);
     }
     return hipGetLastError();
 }
 
-template <int NW, int NB, int WPG>
+template <int NW, int NB, int WPG, bool LAG = (NW == 1)>
 hipError_t launch_tabu_part(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
                             uint32_t *counter, hipStream_t s) {
     if (end <= begin) return hipSuccess;
     return a.trace != nullptr
-               ? launch_tabu_part_t<NW, NB, WPG, true>(a, begin, end, groups, counter, s)
-               : launch_tabu_part_t<NW, NB, WPG, false>(a, begin, end, groups, counter, s);
+               ? launch_tabu_part_t<NW, NB, WPG, true, LAG>(a, begin, end, groups, counter, s)
+               : launch_tabu_part_t<NW, NB, WPG, false, LAG>(a, begin, end, groups, counter, s);
 }
 
-template <int WPG, bool TRACE, bool LONG>
+template <int WPG, bool TRACE, bool LONG, bool LAG>
 hipError_t launch_mixed_t(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
                           uint32_t *counter, hipStream_t s) {
     if (groups > 0) {
         hipError_t e = launch_fill_u32(counter, 0u, 1, s);
         if (e != hipSuccess) return e;
         const int64_t need = (end - begin + WPG - 1) / WPG;
-        hipLaunchKernelGGL((tabu_kernel_mixed<WPG, true, TRACE, LONG>),
+        hipLaunchKernelGGL((tabu_kernel_mixed<WPG, true, TRACE, LONG, LAG>),
                            dim3((unsigned)std::min<int64_t>(groups, need)), dim3(64 * WPG), 0, s, a,
                            begin, end, counter);
     } else {
         const int64_t grid = (end - begin + WPG - 1) / WPG;
-        hipLaunchKernelGGL((tabu_kernel_mixed<WPG, false, TRACE, LONG>), dim3((unsigned)grid),
+        hipLaunchKernelGGL((tabu_kernel_mixed<WPG, false, TRACE, LONG, LAG>), dim3((unsigned)grid),
                            dim3(64 * WPG), 0, s, a, begin, end, counter);
     }
     return hipGetLastError();
 }
 
-// One launch per non-empty length class, each on its own stream with its
-// own queue head (32 words apart); mixed ranges of classes 0..1 and 2..5
-// take one launch each.
-template <int WPG>
-hipError_t launch_tabu_wpg(const TabuLaunchArgs &a, int groups, const hipStream_t *st) {
+template <int WPG, bool LONG, bool LAG>
+hipError_t launch_mixed(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
+                        uint32_t *counter, hipStream_t s) {
+    if (end <= begin) return hipSuccess;
+    return a.trace != nullptr
+               ? launch_mixed_t<WPG, true, LONG, LAG>(a, begin, end, groups, counter, s)
+               : launch_mixed_t<WPG, false, LONG, LAG>(a, begin, end, groups, counter, s);
+}
+
+template <bool TRACE, bool LAG>
+hipError_t launch_split_t(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
+                          uint32_t *counter, hipStream_t s) {
+    if (groups > 0) {
+        hipError_t e = launch_fill_u32(counter, 0u, 1, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((tabu_kernel_split<true, TRACE, LAG>),
+                           dim3((unsigned)std::min<int64_t>(groups, end - begin)), dim3(128), 0, s,
+                           a, begin, end, counter);
+    } else {
+        hipLaunchKernelGGL((tabu_kernel_split<false, TRACE, LAG>), dim3((unsigned)(end - begin)),
+                           dim3(128), 0, s, a, begin, end, counter);
+    }
+    return hipGetLastError();
+}
+
+template <bool LAG>
+hipError_t launch_split(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
+                        uint32_t *counter, hipStream_t s) {
+    if (end <= begin) return hipSuccess;
+    return a.trace != nullptr ? launch_split_t<true, LAG>(a, begin, end, groups, counter, s)
+                              : launch_split_t<false, LAG>(a, begin, end, groups, counter, s);
+}
+
+// One launch per launch group (walk_launch_groups), group g on streams[g]
+// with the queue head of its first class (32 words apart).
+template <int WPG, bool LAG>
+hipError_t launch_tabu_wpg(const TabuLaunchArgs &a, const WalkLaunch &l, const hipStream_t *st) {
     static_assert(kWalkClasses == 6, "one launcher per class below");
     const int64_t *ce = a.class_end;
-    uint32_t *q = a.counter;
+    const WalkGroups wg = walk_launch_groups(ce, l.split);
     hipError_t e = hipSuccess;
-    if (mixed_long_classes(ce)) {
-        // classes 0 and 1 share one launch, on class 0's stream
-        e = a.trace != nullptr ? launch_mixed_t<WPG, true, true>(a, 0, ce[1], groups, q, st[0])
-                               : launch_mixed_t<WPG, false, true>(a, 0, ce[1], groups, q, st[0]);
-    } else {
-        e = launch_tabu_part<4, 16, WPG>(a, 0, ce[0], groups, q, st[0]);
-        if (e == hipSuccess)
-            e = launch_tabu_part<4, 12, WPG>(a, ce[0], ce[1], groups, q + 32, st[1]);
+    for (int g = 0; g < wg.n && e == hipSuccess; ++g) {
+        const int f = wg.first[g], z = wg.last[g];
+        const int64_t begin = f ? ce[f - 1] : 0, end = ce[z];
+        uint32_t *q = a.counter + 32 * f;
+        const int groups = l.split && f == 2 ? l.split_groups : l.groups;
+        if (f == 0 && z == 1)
+            e = launch_mixed<WPG, true, false>(a, begin, end, groups, q, st[g]);
+        else if (f == 0)
+            e = launch_tabu_part<4, 16, WPG>(a, begin, end, groups, q, st[g]);
+        else if (f == 1)
+            e = launch_tabu_part<4, 12, WPG>(a, begin, end, groups, q, st[g]);
+        else if (l.split && f == 2)
+            e = launch_split<LAG>(a, begin, end, groups, q, st[g]);
+        else if (z > f)  // several classes of N <= 128 in one launch
+            e = launch_mixed<WPG, false, LAG>(a, begin, end, groups, q, st[g]);
+        else if (f == 2)
+            e = launch_tabu_part<2, 8, WPG, LAG>(a, begin, end, groups, q, st[g]);
+        else if (f == 3)
+            e = launch_tabu_part<2, 6, WPG, LAG>(a, begin, end, groups, q, st[g]);
+        else if (f == 4)
+            e = launch_tabu_part<1, 4, WPG>(a, begin, end, groups, q, st[g]);
+        else
+            e = launch_tabu_part<1, 3, WPG>(a, begin, end, groups, q, st[g]);
     }
-    if (e != hipSuccess) return e;
-    if (mixed_short_classes(ce)) {
-        // classes 2..5 share one launch, on class 2's stream
-        return a.trace != nullptr
-                   ? launch_mixed_t<WPG, true, false>(a, ce[1], ce[5], groups, q + 64, st[2])
-                   : launch_mixed_t<WPG, false, false>(a, ce[1], ce[5], groups, q + 64, st[2]);
-    }
-    e = launch_tabu_part<2, 8, WPG>(a, ce[1], ce[2], groups, q + 64, st[2]);
-    if (e == hipSuccess) e = launch_tabu_part<2, 6, WPG>(a, ce[2], ce[3], groups, q + 96, st[3]);
-    if (e == hipSuccess) e = launch_tabu_part<1, 4, WPG>(a, ce[3], ce[4], groups, q + 128, st[4]);
-    if (e == hipSuccess) e = launch_tabu_part<1, 3, WPG>(a, ce[4], ce[5], groups, q + 160, st[5]);
     return e;
 }
 
 }  // namespace
 
-hipError_t launch_tabu(const TabuLaunchArgs &a, int waves_per_group, int groups,
-                       const hipStream_t *streams) {
+hipError_t launch_tabu(const TabuLaunchArgs &a, const WalkLaunch &l, const hipStream_t *streams) {
     if (a.W <= 0) return hipSuccess;
-    switch (waves_per_group) {
-    case 1: return launch_tabu_wpg<1>(a, groups, streams);
-    case 2: return launch_tabu_wpg<2>(a, groups, streams);
-    case 4: return launch_tabu_wpg<4>(a, groups, streams);
+    switch (l.waves_per_group * 2 + (l.lag ? 1 : 0)) {
+    case 2: return launch_tabu_wpg<1, false>(a, l, streams);
+    case 3: return launch_tabu_wpg<1, true>(a, l, streams);
+    case 4: return launch_tabu_wpg<2, false>(a, l, streams);
+    case 5: return launch_tabu_wpg<2, true>(a, l, streams);
+    case 8: return launch_tabu_wpg<4, false>(a, l, streams);
+    case 9: return launch_tabu_wpg<4, true>(a, l, streams);
     default: return hipErrorInvalidValue;
     }
 }

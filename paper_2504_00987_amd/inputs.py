@@ -13,6 +13,7 @@ Workloads (sizes follow the paper's setting, Sec. III and Sec. V):
   tabu_n64      4096 independent walks at N=64 from random starts, 4N steps,
                 tenure U[floor(N/10), floor(N/5)].
   tabu_uneven   8192 walks with N uniform in {48..120}, 3N steps, same tenure.
+  tabu_n120     4096 walks at N=120, 4N steps, same tenure.
   memetic_n120  256 populations of K=100 at N=120, memetic_n20's rules.
   serving       Poisson stream of solve requests, N uniform in {32..128},
                 16 populations x 200 generations each.
@@ -25,7 +26,7 @@ import numpy as np
 
 # Rule identifiers (the numbering used by both the library ABI and the
 # oracle's entry points).
-STEPS_FIXED, STEPS_MULT_N, STEPS_PAPER = 0, 1, 2
+STEPS_FIXED, STEPS_MULT_N, STEPS_PAPER, STEPS_RANGE = 0, 1, 2, 3
 TENURE_LINEAR, TENURE_PAPER = 0, 1
 
 P_COMB_090 = 3865470566  # floor(0.9 * 2^32)
@@ -44,13 +45,20 @@ class Rules:
     hi_den: int
     hi_add: int
     aspiration: int = 1
+    # bounds of STEPS_RANGE: walk length uniform in
+    # [floor(slo_num N / slo_den), floor(shi_num N / shi_den)]
+    slo_num: int = 0
+    slo_den: int = 1
+    shi_num: int = 0
+    shi_den: int = 1
 
     def as_dict(self):
         return dict(steps_rule=self.steps_rule, steps_a=self.steps_a,
                     tenure_rule=self.tenure_rule, lo_num=self.lo_num,
                     lo_den=self.lo_den, lo_add=self.lo_add, hi_num=self.hi_num,
                     hi_den=self.hi_den, hi_add=self.hi_add,
-                    aspiration=self.aspiration)
+                    aspiration=self.aspiration, slo_num=self.slo_num, slo_den=self.slo_den,
+                    shi_num=self.shi_num, shi_den=self.shi_den)
 
 
 # Walk length 4N (or 3N), tenure U[floor(N/10), floor(N/5)].
@@ -100,7 +108,10 @@ TABU_N256 = TabuWorkload("tabu_n256", 4096, 256, rules=rules_tabu(4), seed=1005)
 # Both classes of N > 128 (four neighbours per lane), mixed.
 TABU_LONG_UNEVEN = TabuWorkload("tabu_long_uneven", 4096, None, 129, 256, rules=rules_tabu(4),
                                 seed=1007)
-TABU_WORKLOADS = {w.name: w for w in (TABU_N64, TABU_UNEVEN, TABU_N256, TABU_LONG_UNEVEN)}
+# The top of the N = 64..120 range in one length (two neighbours per lane).
+TABU_N120 = TabuWorkload("tabu_n120", 4096, 120, rules=rules_tabu(4), seed=1008)
+TABU_WORKLOADS = {w.name: w for w in (TABU_N64, TABU_UNEVEN, TABU_N120, TABU_N256,
+                                      TABU_LONG_UNEVEN)}
 MEMETIC_N20 = MemeticWorkload("memetic_n20", 20, 100, 1, 50, seed=1000)
 MEMETIC_N120 = MemeticWorkload("memetic_n120", 120, 100, 256, 100000, seed=1003)
 SERVING_SEED = 1004

@@ -31,7 +31,8 @@ def _stream(stream=None):
 def tabu_params(rules: Rules) -> _lib.TabuParams:
     return _lib.TabuParams(rules.steps_rule, rules.steps_a, rules.tenure_rule, rules.lo_num,
                            rules.lo_den, rules.lo_add, rules.hi_num, rules.hi_den, rules.hi_add,
-                           rules.aspiration)
+                           rules.aspiration, rules.slo_num, rules.slo_den, rules.shi_num,
+                           rules.shi_den)
 
 
 @dataclass
@@ -156,18 +157,29 @@ class Labs:
         res._lengths = ns_arr  # read by a copy on the stream in the allocation-free form
         return res
 
-    def set_launch(self, waves_per_group: int | None = None, persistent: int = 0,
-                   groups_per_cu: int = 0):
-        if waves_per_group is None:
+    def device_peaks(self) -> dict:
+        """Measured dot4 / int32 / LDS throughput of this GPU (labs_device_peaks)."""
+        v = [ctypes.c_double(0.0) for _ in range(4)]
+        self._check(self.L.labs_device_peaks(self.h, *[ctypes.byref(x) for x in v]))
+        return {"dot4_ops_per_s": v[0].value, "int32_ops_per_s": v[1].value,
+                "lds_bytes_per_s": v[2].value, "clock_hz": v[3].value}
+
+    def set_launch(self, group_lanes: int | None = None, walks_per_group: int = 1,
+                   persistent: int = 0, groups_per_cu: int = 0, layout: int = 0):
+        """labs_set_launch; no arguments clears the override."""
+        if group_lanes is None:
             self._check(self.L.labs_set_launch(self.h, None))
             return
-        l = _lib.Launch(waves_per_group, persistent, groups_per_cu)
+        l = _lib.Launch(group_lanes, walks_per_group, persistent, groups_per_cu, layout)
         self._check(self.L.labs_set_launch(self.h, ctypes.byref(l)))
 
-    def get_launch(self, n: int):
+    def get_launch(self, n_min: int, n_max: int | None = None):
+        """(group_lanes, walks_per_group, persistent, groups_per_cu, layout) for a
+        batch of lengths in [n_min, n_max]."""
         l = _lib.Launch()
-        self._check(self.L.labs_get_launch(self.h, n, ctypes.byref(l)))
-        return (l.waves_per_group, l.persistent, l.groups_per_cu)
+        self._check(self.L.labs_get_launch(self.h, n_min, n_min if n_max is None else n_max,
+                                           ctypes.byref(l)))
+        return (l.group_lanes, l.walks_per_group, l.persistent, l.groups_per_cu, l.layout)
 
     def autotune(self, rules: Rules, n_min: int, n_max: int, walks: int, seed: int = 7) -> int:
         tried = ctypes.c_int32(0)
@@ -201,11 +213,19 @@ class Labs:
         hit = torch.empty(pops, dtype=torch.int64, device=dev)
         done = torch.empty(pops, dtype=torch.int64, device=dev)
         p = self.memetic_params(K, rules, generations, **kw)
+        # kept for a caller that catches LABS_E_CANCELLED: the outputs hold
+        # the state where the run stopped
+        self._last_memetic = MemeticResult(best, be, hit, done)
         self._check(self.L.labs_memetic_run(
             self.h, ctypes.byref(p), None if ns_arr is None else ns_arr.ctypes.data_as(ctypes.c_void_p),
             n_uniform, pops, ctypes.c_uint64(seed & (2**64 - 1)), _ptr(best), out_stride,
             _ptr(be), _ptr(hit), _ptr(done), _stream(stream)))
         return MemeticResult(best, be, hit, done)
+
+
+    def cancel(self):
+        """labs_cancel: stop this handle's memetic runs at their next chunk boundary."""
+        self._check(self.L.labs_cancel(self.h))
 
 
 class Server:

@@ -50,10 +50,10 @@ def test_library_reports_without_a_device(lib):
 def test_struct_layouts_match_header():
     import ctypes
     from paper_2504_00987_amd import _lib
-    assert ctypes.sizeof(_lib.TabuParams) == 40
-    assert ctypes.sizeof(_lib.Launch) == 12
-    # K, p_comb, mut_rule, p_mut (16) + tabu (40) + generations (8, aligned at 56) + 4 ints
-    assert ctypes.sizeof(_lib.MemeticParams) == 88
+    assert ctypes.sizeof(_lib.TabuParams) == 56
+    assert ctypes.sizeof(_lib.Launch) == 20
+    # K, p_comb, mut_rule, p_mut (16) + tabu (56) + generations (8, aligned at 72) + 6 ints
+    assert ctypes.sizeof(_lib.MemeticParams) == 104
 
 
 def test_limits_match_header():

@@ -32,7 +32,8 @@ def lb():
 
 def osched(r: I.Rules) -> O.Schedule:
     return O.Schedule(r.steps_rule, r.steps_a, r.tenure_rule, r.lo_num, r.lo_den, r.lo_add,
-                      r.hi_num, r.hi_den, r.hi_add, r.aspiration)
+                      r.hi_num, r.hi_den, r.hi_add, r.aspiration, r.slo_num, r.slo_den,
+                      r.shi_num, r.shi_den)
 
 
 # ---------------------------------------------------------------------------
@@ -176,7 +177,15 @@ def test_tabu_explicit_starts_paper_rules(lb):
         assert np.array_equal(tr[w, : len(trs[w])], trs[w])
 
 
-@pytest.mark.parametrize("launch", [(1, 0, 0), (2, 0, 0), (4, 0, 0), (1, 1, 0), (2, 1, 1), (4, 1, 2)])
+# Every launch configuration: (group lanes, walks per group) of one
+# wavefront per walk or two (128, 1), both layouts of 64 < N <= 128, one walk
+# per wavefront (pair) or a persistent queue at the automatic and a fixed
+# grid.
+LAUNCH_GRID = [(gl, wpg, p, g, lay) for gl, wpg in ((64, 1), (128, 2), (256, 4), (128, 1))
+               for lay in (1, 2) for p, g in ((0, 0), (1, 0), (1, 2))]
+
+
+@pytest.mark.parametrize("launch", LAUNCH_GRID)
 def test_tabu_launch_invariance(lb, launch):
     say(f"tabu: launch configuration {launch} gives identical walks")
     ns = I.uneven_lengths(300, 48, 120, seed=21)
@@ -201,13 +210,15 @@ def test_autotune_then_parity():
     h = Labs(0)
     try:
         rules = I.rules_tabu(3)
-        before = h.get_launch(120)
+        before = h.get_launch(48, 120)
+        other = h.get_launch(64)
         tried = h.autotune(rules, 48, 120, 512, seed=3)
-        assert tried == 15
-        wpg, pers, gpc = h.get_launch(120)
-        assert wpg in (1, 2, 4) and pers in (0, 1)
-        assert (not pers and gpc == 0) or (pers and gpc * wpg in (4, 8, 16, 32))
-        assert before == (1, 0, 0)  # the default up to N = 128
+        assert tried >= 30  # the grid of one- and two-wavefront walks, both layouts
+        gl, wpg, pers, gpc, lay = h.get_launch(48, 120)
+        assert (gl, wpg) in ((64, 1), (128, 2), (256, 4), (128, 1)) and pers in (0, 1)
+        assert lay in (0, 1, 2) and ((not pers and gpc == 0) or (pers and gpc > 0))
+        assert before == (64, 1, 0, 0, 0)  # the default up to N = 128
+        assert h.get_launch(64) == other  # another length range keeps its launch
         ns = I.uneven_lengths(200, 48, 120, seed=23)
         res = h.tabu_batch(rules, len(ns), 1002, ns=ns)
         best, be, fe = O.tabu_batch(len(ns), osched(rules), 1002, ns=ns, stride=128, nthreads=8)
@@ -299,6 +310,99 @@ def _oracle_memetic(n_list, K, rules, gens, seed, target=-1, p_comb=I.P_COMB_090
 
     with cf.ThreadPoolExecutor(max_workers=16) as ex:
         return list(ex.map(one, range(len(n_list))))
+
+
+def test_tabu_range_rule(lb):
+    # Sec. III.B's walk length randInt[N/2, 3N/2] as the RANGE rule, and an
+    # asymmetric range, traced, against the oracle; lengths over two classes
+    ns = np.array([3, 10, 31, 64, 65, 100, 128, 129, 200], dtype=np.int32)
+    for bounds in ((1, 2, 3, 2), (1, 3, 7, 4)):
+        rules = I.Rules(I.STEPS_RANGE, 0, I.TENURE_LINEAR, 0, 1, 1, 1, 10, 1, 1, *bounds)
+        say(f"tabu RANGE rule {bounds}, N={list(ns)}")
+        res = lb.tabu_batch(rules, len(ns), 4242, ns=ns, trace_stride=512)
+        sch = osched(rules)
+        for w, n in enumerate(ns):
+            n = int(n)
+            T, lo, hi = O.walk_schedule(n, sch, 4242, w, 0)
+            s = O.random_start(n, 4242, w)
+            b, e1, f1, tr, _ = O.tabu_walk(s, 4242, w, 0, T, lo, hi, rules.aspiration,
+                                           want_trace=True)
+            assert res.best_e[w].item() == e1 and res.final_e[w].item() == f1
+            assert np.array_equal(res.best_seq[w, :n].cpu().numpy(), b)
+            assert np.array_equal(res.trace[w, :T].cpu().numpy(), tr)
+    from paper_2504_00987_amd._lib import LabsError
+    with pytest.raises(LabsError):  # an empty range is rejected
+        lb.tabu_batch(I.Rules(I.STEPS_RANGE, 0, I.TENURE_LINEAR, 0, 1, 1, 1, 10, 1, 1, 2, 1, 1, 1),
+                      4, 1, n_uniform=40)
+
+
+def test_memetic_range_rule_modes(lb):
+    # memetic replicas whose walks take the RANGE rule (Sec. III.B's
+    # randInt[N/2, 3N/2]) equal those of Alg. 4's rule draw for draw
+    ns = np.array([17, 64, 90], dtype=np.int32)
+    r_range = I.Rules(I.STEPS_RANGE, 0, I.TENURE_LINEAR, 0, 1, 1, 1, 10, 1, 1, 1, 2, 3, 2)
+    ref = _oracle_memetic(ns, 24, I.RULES_MEMETIC, 9, 314)
+    for mode in (0, 2):
+        say(f"memetic RANGE rule, mode {mode}")
+        res = lb.memetic_run(24, r_range, 9, len(ns), 314, ns=ns, mode=mode, chunk=4)
+        for p, st in enumerate(ref):
+            assert res.best_e[p].item() == st.bestE
+            assert np.array_equal(res.best_seq[p, :int(ns[p])].cpu().numpy(), st.best)
+
+
+def test_memetic_stream_ordered(lb):
+    # runs are enqueued on the caller's stream without synchronising it: two
+    # runs back to back on two streams (the second waits for the first's use
+    # of the state memory on the GPU), then checked against the oracle
+    n, K, G = 40, 30, 12
+    rules = I.RULES_MEMETIC
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    say("memetic stream-ordered: two runs on two streams")
+    a = lb.memetic_run(K, rules, G, 5, 21, n_uniform=n, mode=1, chunk=5, stream=s1)
+    b = lb.memetic_run(K, rules, G, 5, 22, n_uniform=n, mode=2, chunk=5, stream=s2)
+    s1.synchronize()
+    s2.synchronize()
+    for res, seed in ((a, 21), (b, 22)):
+        ref = _oracle_memetic([n] * 5, K, rules, G, seed)
+        for p, st in enumerate(ref):
+            assert res.best_e[p].item() == st.bestE
+            assert np.array_equal(res.best_seq[p, :n].cpu().numpy(), st.best)
+            assert res.gens_done[p].item() == G
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_memetic_cancel(lb, mode):
+    # labs_cancel from another thread: the run stops at a chunk boundary, a
+    # call still enqueueing returns LABS_E_CANCELLED, and what it leaves is
+    # the oracle's state after the generations it ran
+    import threading
+    from paper_2504_00987_amd import _lib
+    n, K, pops, G, chunk = 24, 16, 6, 10**6, 16
+    rules = I.RULES_MEMETIC
+    say(f"memetic cancel, mode {mode}")
+    t = threading.Timer(0.3, lb.cancel)
+    t.start()
+    try:
+        res = lb.memetic_run(K, rules, G, pops, 777, n_uniform=n, mode=mode, chunk=chunk)
+        code = _lib.LABS_OK
+    except _lib.LabsError as ex:
+        code = ex.code
+        res = lb._last_memetic
+    t.join()
+    torch.cuda.synchronize()
+    done = res.gens_done.cpu().numpy()
+    assert (done == done[0]).all() and 0 < done[0] < G and done[0] % chunk == 0
+    if mode == 0:
+        assert code == _lib.LABS_E_CANCELLED  # one launch per generation: still enqueueing
+    g = int(min(done[0], 100000))
+    ref = _oracle_memetic([n] * pops, K, rules, g, 777)
+    if g == done[0]:
+        for p, st in enumerate(ref):
+            assert res.best_e[p].item() == st.bestE
+            assert np.array_equal(res.best_seq[p, :n].cpu().numpy(), st.best)
+    # a run started after the cancel is not affected
+    res2 = lb.memetic_run(K, rules, 8, pops, 777, n_uniform=n, mode=mode, chunk=chunk)
+    assert (res2.gens_done.cpu().numpy() == 8).all()
 
 
 @pytest.mark.parametrize("mode", [0, 1, 2])
@@ -594,7 +698,8 @@ def test_tabu_long_trace(lb, n, asp):
         assert np.array_equal(tr[w, :n], trs[w])
 
 
-@pytest.mark.parametrize("launch", [(4, 0, 0), (1, 1, 0), (2, 1, 1)])
+@pytest.mark.parametrize("launch", [(256, 4, 0, 0, 0), (64, 1, 1, 0, 0), (128, 2, 1, 1, 0),
+                                    (128, 1, 1, 2, 1)])
 def test_tabu_long_extreme_starts(lb, launch):
     # all-ones and alternating starts have |C_k| = N - k up to 255, the
     # values that need the halved mirror
@@ -620,7 +725,8 @@ def test_tabu_long_extreme_starts(lb, launch):
         assert np.array_equal(tr[w, : len(trs[w])], trs[w])
 
 
-@pytest.mark.parametrize("launch", [(1, 0, 0), (2, 0, 0), (4, 0, 0), (1, 1, 0), (2, 1, 1), (4, 1, 2)])
+@pytest.mark.parametrize("launch", [(64, 1, 0, 0, 0), (128, 2, 0, 0, 0), (256, 4, 0, 0, 0),
+                                    (64, 1, 1, 0, 0), (128, 2, 1, 1, 0), (256, 4, 1, 2, 0)])
 def test_tabu_long_launch_invariance(lb, launch):
     # both N > 128 classes in one batch: their single launch, every form
     say(f"tabu: N in 129..256, launch configuration {launch} gives identical walks")
@@ -649,7 +755,8 @@ def test_tabu_all_classes_ragged(lb):
     assert np.array_equal(res.best_seq.cpu().numpy(), best)
 
 
-@pytest.mark.parametrize("launch", [(4, 0, 0), (2, 1, 1)])
+@pytest.mark.parametrize("launch", [(256, 4, 0, 0, 0), (128, 2, 1, 1, 0), (128, 1, 0, 0, 1),
+                                    (128, 1, 1, 2, 2), (64, 1, 0, 0, 1)])
 def test_tabu_every_length(lb, launch):
     """One walk at every N in 3..256, move traces compared: each N has its own
     placement of the reversed records (a shift of 0..15 records that keeps the

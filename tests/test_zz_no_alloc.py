@@ -34,7 +34,8 @@ def _same(a, b):
         assert torch.equal(a.trace, b.trace)
 
 
-@pytest.mark.parametrize("launch", [None, (1, 1, 0), (4, 1, 2), (2, 0, 0)])
+@pytest.mark.parametrize("launch", [None, (64, 1, 1, 0, 0), (256, 4, 1, 2, 0), (128, 2, 0, 0, 0),
+                                    (128, 1, 1, 0, 1)])
 def test_noalloc_equals_allocating_entry_point(lb, launch):
     rules = I.rules_tabu(3)
     if launch is None:
