@@ -163,6 +163,69 @@ int orc_bruteforce_min(int n, int64_t *emin, int64_t *count)
 }
 
 /* ------------------------------------------------------------------------- */
+/* Skew-symmetric subspace (Sec. II.C).                                       */
+/* ------------------------------------------------------------------------- */
+/* The skew-symmetric sequence of odd length n = 2c + 1 whose free spins
+ * s_0..s_c are given by code (bit i set <=> s_i = -1): the other half
+ * follows from s_{c+i} = (-1)^i s_{c-i}, i = 1..c (Sec. II.C, 0-based with
+ * the centre at c).  Returns -1 for even n or n outside [1, 63]. */
+int orc_skew_sequence(int n, uint64_t code, int8_t *s)
+{
+    if (n < 1 || n > 63 || (n & 1) == 0)
+        return -1;
+    int c = (n - 1) / 2;
+    for (int i = 0; i <= c; ++i)
+        s[i] = ((code >> i) & 1u) ? -1 : 1;
+    for (int i = 1; i <= c; ++i)
+        s[c + i] = (int8_t)((i & 1) ? -s[c - i] : s[c - i]);
+    return 0;
+}
+
+/* Exhaustive minimum of Eq. (2) over the 2^((n+1)/2) skew-symmetric
+ * sequences of odd length n (n <= 45): the minimum, how many of them attain
+ * it, and -- of those with s_0 = +1 -- the one whose free-spin code is the
+ * smallest integer.  Every sequence is built by orc_skew_sequence and
+ * scored from Eq. (2) directly; no symmetry is used. */
+int orc_skew_bruteforce_min(int n, int64_t *emin, int64_t *count, int8_t *argmin)
+{
+    if (n < 1 || n > 45 || (n & 1) == 0)
+        return -1;
+    int8_t s[45];
+    int c = (n - 1) / 2;
+    int64_t best = -1, cnt = 0;
+    uint64_t best_code = 0;
+    uint64_t total = 1ull << (c + 1);
+    for (uint64_t code = 0; code < total; ++code) {
+        orc_skew_sequence(n, code, s);
+        int64_t e = orc_energy(s, n);
+        if (best < 0 || e < best) {
+            best = e;
+            cnt = 1;
+            best_code = code;  /* ascending codes: the first is the smallest */
+        } else if (e == best) {
+            ++cnt;
+        }
+    }
+    /* of the attaining codes, the smallest with s_0 = +1 (bit 0 clear):
+     * negating every free spin negates the sequence, E unchanged, so the
+     * smallest attaining code with bit 0 set has a partner without it */
+    if (best_code & 1u) {
+        for (uint64_t code = 0; code < total; code += 2) {
+            orc_skew_sequence(n, code, s);
+            if (orc_energy(s, n) == best) {
+                best_code = code;
+                break;
+            }
+        }
+    }
+    *emin = best;
+    *count = cnt;
+    if (argmin)
+        orc_skew_sequence(n, best_code, argmin);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Neighbourhood energies.                                                    */
 /* ------------------------------------------------------------------------- */
 

@@ -53,6 +53,8 @@ def lib():
         L.orc_energy.restype = i64
         L.orc_energy_batch.argtypes = [P, P, i32, i32, i64, P]
         L.orc_bruteforce_min.argtypes = [ctypes.c_int, P, P]
+        L.orc_skew_sequence.argtypes = [ctypes.c_int, ctypes.c_uint64, P]
+        L.orc_skew_bruteforce_min.argtypes = [ctypes.c_int, P, P, P]
         L.orc_non_skew.argtypes = [P, ctypes.c_int]
         L.orc_skew_deviation.argtypes = [P, ctypes.c_int, ctypes.c_int]
         L.orc_neighbour_energies_recompute.argtypes = [P, ctypes.c_int, P]
@@ -157,6 +159,25 @@ def bruteforce_min(n: int):
     if lib().orc_bruteforce_min(n, _p(emin), _p(cnt)) != 0:
         raise ValueError("n out of range")
     return int(emin[0]), int(cnt[0])
+
+
+def skew_sequence(n: int, code: int) -> np.ndarray:
+    """The skew-symmetric sequence of odd length n with free spins s_0..s_c
+    from code (Sec. II.C)."""
+    s = np.zeros(n, dtype=np.int8)
+    if lib().orc_skew_sequence(n, code, _p(s)) != 0:
+        raise ValueError("n must be odd and in [1, 63]")
+    return s
+
+
+def skew_bruteforce_min(n: int):
+    """(E_min, count, argmin) over the skew-symmetric sequences of odd n."""
+    emin = np.zeros(1, dtype=np.int64)
+    cnt = np.zeros(1, dtype=np.int64)
+    arg = np.zeros(n, dtype=np.int8)
+    if lib().orc_skew_bruteforce_min(n, _p(emin), _p(cnt), _p(arg)) != 0:
+        raise ValueError("n must be odd and in [1, 45]")
+    return int(emin[0]), int(cnt[0]), arg
 
 
 def non_skew(t) -> int:

@@ -173,6 +173,69 @@ def test_skew_symmetric_odd_lags_vanish():
         assert all(C[k] == 0 for k in range(1, N, 2))
 
 
+# ---------------------------------------------------------------------------
+# The search restricted to skew-symmetric sequences (Sec. II.C)
+# ---------------------------------------------------------------------------
+def _numpy_skew_bruteforce(n):
+    """Every sequence of odd length n enumerated by numpy, kept when Eq. 4's
+    condition s_{c+i} = (-1)^i s_{c-i} holds; energies by numpy."""
+    c = (n - 1) // 2
+    codes = np.arange(1 << n, dtype=np.int64)
+    S = (1 - 2 * ((codes[:, None] >> np.arange(n)) & 1)).astype(np.int8)
+    keep = np.ones(len(S), dtype=bool)
+    for i in range(1, c + 1):
+        keep &= S[:, c + i] == (-1) ** i * S[:, c - i]
+    K, kc = S[keep], codes[keep]
+    e = npref.energies_rows(K)
+    m = int(e.min())
+    # of the minima with s_0 = +1, the one whose free spins s_0..s_c read as
+    # the smallest integer (bit i set <=> s_i = -1)
+    free = kc & ((1 << (c + 1)) - 1)
+    at = (e == m) & (K[:, 0] == 1)
+    arg = K[at][np.argmin(free[at])]
+    return m, int(np.sum(e == m)), arg, len(K)
+
+
+@pytest.mark.parametrize("n", [3, 5, 7, 9, 11, 13, 15, 17])
+def test_skew_bruteforce_against_numpy(n):
+    m, cnt, arg, size = _numpy_skew_bruteforce(n)
+    assert size == 2 ** ((n + 1) // 2)  # the subspace's size (Sec. II.C)
+    em, c, a = O.skew_bruteforce_min(n)
+    assert (em, c) == (m, cnt)
+    assert np.array_equal(a, arg)
+
+
+def test_skew_sequence_is_the_subspace():
+    # the code -> sequence map hits every skew-symmetric sequence once, and
+    # each has C_k = 0 at odd k
+    for n in (1, 3, 9, 15, 21):
+        c = (n - 1) // 2
+        seen = set()
+        for code in range(1 << (c + 1)):
+            s = O.skew_sequence(n, code)
+            assert all(s[c + i] == (-1) ** i * s[c - i] for i in range(1, c + 1))
+            assert all(s[i] == (-1 if (code >> i) & 1 else 1) for i in range(c + 1))
+            C = O.autocorrelation(s)
+            assert all(C[k] == 0 for k in range(1, n, 2))
+            seen.add(s.tobytes())
+        assert len(seen) == 1 << (c + 1)
+
+
+@pytest.mark.parametrize("n", [3, 5, 7, 9, 11, 13, 15, 17, 19, 21])
+def test_skew_minimum_against_unrestricted(n):
+    # restricting the space never helps; at the odd Barker lengths the
+    # optimum (E = floor(N/2)) is skew-symmetric, and at N = 19 no optimum is
+    # (the paper's point that odd N need not have skew-symmetric optima)
+    em, c, a = O.skew_bruteforce_min(n)
+    gm, gc = O.bruteforce_min(n)
+    assert em >= gm and O.energy(a) == em
+    if n in BARKER:
+        assert em == gm == n // 2
+    if n == 19:
+        assert em > gm
+    assert c % 2 == 0 and c <= gc or em > gm
+
+
 def test_congruences():
     rng = np.random.default_rng(9)
     for n in [3, 10, 33, 64, 101, 128]:
