@@ -187,6 +187,27 @@ int labs_bruteforce_min(labs_handle *h, int32_t n, int32_t *min_e, int64_t *coun
                         int8_t *argmin);
 
 /*
+ * The search restricted to skew-symmetric sequences (Sec. II.C): for odd
+ * n = 2c + 1, the exhaustive minimum of Eq. (2) over the 2^(c+1) sequences
+ * with s_{c+i} = (-1)^i s_{c-i} (0-based, centre c), whose C_k vanish for odd
+ * k.  The paper's point is that this subspace need not hold the optimum
+ * (Sec. II.C, Sec. VI); comparing the result with labs_bruteforce_min shows
+ * where it does not.  Negating every spin keeps a sequence skew-symmetric, so
+ * the 2^c sequences with s_0 = +1 are enumerated.
+ *   min_e   HOST int32: the minimum energy over the skew-symmetric subspace
+ *   count   HOST int64 (or NULL): how many of its 2^(c+1) sequences attain it
+ *   argmin  HOST int8 [n] (or NULL): of the attaining ones with s_0 = +1, the
+ *           one whose free spins s_0..s_c (bit i set <=> s_i = -1) form the
+ *           smallest integer
+ * Synchronous (on the handle's stream); LABS_E_INVAL for even n or n outside
+ * [3, LABS_MAX_SKEW_BRUTE_N].  Work grows like 2^(n/2) n: n = 75 takes about
+ * a second.
+ */
+#define LABS_MAX_SKEW_BRUTE_N 75
+int labs_skew_bruteforce_min(labs_handle *h, int32_t n, int32_t *min_e, int64_t *count,
+                             int8_t *argmin);
+
+/*
  * Independent tabu walks (Alg. 2; the thread-parallel form of Alg. 4, one
  * walk per 64-lane wavefront).  Walk w (0 <= w < walks) starts from row w
  * of `starts`, or -- when starts == NULL -- from the 128-bit draws

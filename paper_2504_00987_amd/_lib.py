@@ -18,7 +18,8 @@ NOALLOC_MAX_WALKS = 65536
 
 EXPORTED = [
     "labs_create", "labs_destroy", "labs_last_error", "labs_status_name", "labs_version",
-    "labs_energy_batch", "labs_skew_deviation_batch", "labs_bruteforce_min", "labs_tabu_batch",
+    "labs_energy_batch", "labs_skew_deviation_batch", "labs_bruteforce_min",
+    "labs_skew_bruteforce_min", "labs_tabu_batch",
     "labs_tabu_batch_noalloc",
     "labs_set_launch", "labs_get_launch", "labs_device_peaks",
     "labs_autotune", "labs_memetic_run", "labs_cancel", "labs_server_create", "labs_server_submit",
@@ -80,6 +81,7 @@ def load():
     L.labs_energy_batch.argtypes = [P, P, P, i32, i32, i64, P, P]
     L.labs_skew_deviation_batch.argtypes = [P, P, P, i32, i32, i64, P, P]
     L.labs_bruteforce_min.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i64), P]
+    L.labs_skew_bruteforce_min.argtypes = L.labs_bruteforce_min.argtypes
     L.labs_tabu_batch.argtypes = [P, ctypes.POINTER(TabuParams), P, i32, P, i32, i64, u64,
                                   P, i32, P, P, P, i32, P]
     L.labs_tabu_batch_noalloc.argtypes = L.labs_tabu_batch.argtypes

@@ -394,16 +394,17 @@ int labs_skew_deviation_batch(labs_handle *h, const int8_t *seqs, const int32_t 
     return LABS_OK;
 }
 
-int labs_bruteforce_min(labs_handle *h, int32_t n, int32_t *min_e, int64_t *count,
-                        int8_t *argmin) {
-    if (!h) return LABS_E_INVAL;
-    h->last_error.clear();
-    if (n < LABS_MIN_N || n > LABS_MAX_BRUTE_N)
-        return fail(h, LABS_E_INVAL, "n=%d out of [%d, %d]", n, LABS_MIN_N, LABS_MAX_BRUTE_N);
-    if (!min_e) return fail(h, LABS_E_INVAL, "null min_e");
+}  // extern "C"
+
+namespace liblabs {
+
+// Exhaustive minimum over all sequences of length n, or (skew) over the
+// skew-symmetric ones of odd length n; argmin from the smallest code.
+static int bruteforce_impl(labs_handle *h, int32_t n, bool skew, int32_t *min_e, int64_t *count,
+                           int8_t *argmin) {
     DeviceGuard g(h->device);
     hipStream_t s = h->stream;
-    const int64_t waves = brute_waves(n);
+    const int64_t waves = skew ? skew_brute_waves(n) : brute_waves(n);
     // Workspace: [out e | out count | out code (256 B)] [part e] [part count] [part code]
     const size_t off_e = 256, off_c = off_e + 8 * (size_t)waves, off_k = off_c + 8 * (size_t)waves;
     int rc = ws_acquire(h, s, off_k + 8 * (size_t)waves);
@@ -416,7 +417,7 @@ int labs_bruteforce_min(labs_handle *h, int32_t n, int32_t *min_e, int64_t *coun
     p.part_e = (int32_t *)(base + off_e);
     p.part_count = (int64_t *)(base + off_c);
     p.part_code = (uint64_t *)(base + off_k);
-    hipError_t e = launch_bruteforce(n, p, s);
+    hipError_t e = skew ? launch_skew_bruteforce(n, p, s) : launch_bruteforce(n, p, s);
     if (e != hipSuccess) return hip_fail(h, e, "exhaustive search launch");
     if ((rc = stage_acquire(h, 24))) return rc;
     e = hipMemcpyAsync(h->pin.ptr, base, 24, hipMemcpyDeviceToHost, s);
@@ -432,9 +433,41 @@ int labs_bruteforce_min(labs_handle *h, int32_t n, int32_t *min_e, int64_t *coun
     std::memcpy(&code, r + 16, 8);
     *min_e = me;
     if (count) *count = cnt;
-    if (argmin)
+    if (argmin && !skew)
         for (int i = 0; i < n; ++i) argmin[i] = ((code >> i) & 1ull) ? (int8_t)-1 : (int8_t)1;
+    if (argmin && skew) {
+        // free spins s_0..s_c from the code, then s_{c+i} = (-1)^i s_{c-i}
+        const int c = (n - 1) / 2;
+        for (int i = 0; i <= c; ++i) argmin[i] = ((code >> i) & 1ull) ? (int8_t)-1 : (int8_t)1;
+        for (int i = 1; i <= c; ++i)
+            argmin[c + i] = (int8_t)((i & 1) ? -argmin[c - i] : argmin[c - i]);
+    }
     return LABS_OK;
+}
+
+}  // namespace liblabs
+
+extern "C" {
+
+int labs_bruteforce_min(labs_handle *h, int32_t n, int32_t *min_e, int64_t *count,
+                        int8_t *argmin) {
+    if (!h) return LABS_E_INVAL;
+    h->last_error.clear();
+    if (n < LABS_MIN_N || n > LABS_MAX_BRUTE_N)
+        return fail(h, LABS_E_INVAL, "n=%d out of [%d, %d]", n, LABS_MIN_N, LABS_MAX_BRUTE_N);
+    if (!min_e) return fail(h, LABS_E_INVAL, "null min_e");
+    return bruteforce_impl(h, n, false, min_e, count, argmin);
+}
+
+int labs_skew_bruteforce_min(labs_handle *h, int32_t n, int32_t *min_e, int64_t *count,
+                             int8_t *argmin) {
+    if (!h) return LABS_E_INVAL;
+    h->last_error.clear();
+    if (n < LABS_MIN_N || n > LABS_MAX_SKEW_BRUTE_N || (n & 1) == 0)
+        return fail(h, LABS_E_INVAL, "n=%d must be odd and in [%d, %d]", n, LABS_MIN_N,
+                    LABS_MAX_SKEW_BRUTE_N);
+    if (!min_e) return fail(h, LABS_E_INVAL, "null min_e");
+    return bruteforce_impl(h, n, true, min_e, count, argmin);
 }
 
 int labs_set_launch(labs_handle *h, const labs_launch *launch) {

@@ -183,6 +183,10 @@ struct BruteParts {
 };
 int64_t brute_waves(int n);
 hipError_t launch_bruteforce(int n, const BruteParts &p, hipStream_t s);
+// The same over the skew-symmetric sequences of odd length n (Sec. II.C):
+// out_code receives the free-spin pattern (bit i set <=> s_i = -1, i <= c).
+int64_t skew_brute_waves(int n);
+hipError_t launch_skew_bruteforce(int n, const BruteParts &p, hipStream_t s);
 
 // Launch group g (walk_launch_groups(a.class_end, l.split)) runs on
 // streams[g]; a.counter must point at 32 * kWalkClasses writable uint32 (the

@@ -120,6 +120,18 @@ class Labs:
                                                seq.ctypes.data_as(ctypes.c_void_p)))
         return e.value, cnt.value, seq
 
+    def skew_bruteforce_min(self, n: int):
+        """Exhaustive minimum over the skew-symmetric sequences of odd length
+        n (Sec. II.C): (E_min, how many of the 2^((n+1)/2) attain it, the
+        attaining sequence with s_0 = +1 whose free spins form the smallest
+        integer)."""
+        e = ctypes.c_int32(0)
+        cnt = ctypes.c_int64(0)
+        seq = np.zeros(n, dtype=np.int8)
+        self._check(self.L.labs_skew_bruteforce_min(self.h, n, ctypes.byref(e), ctypes.byref(cnt),
+                                                    seq.ctypes.data_as(ctypes.c_void_p)))
+        return e.value, cnt.value, seq
+
     def tabu_batch(self, rules: Rules, walks: int, seed: int, ns=None, n_uniform: int = 0,
                    starts: torch.Tensor | None = None, out_stride: int | None = None,
                    trace_stride: int = 0, out=None, stream=None,

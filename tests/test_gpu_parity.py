@@ -123,6 +123,47 @@ def test_bruteforce_min(lb):
         lb.bruteforce_min(41)
 
 
+def test_skew_bruteforce_min(lb):
+    # the search restricted to skew-symmetric sequences (Sec. II.C) against
+    # the oracle's enumeration, then against the unrestricted exhaustive
+    # minimum on the GPU (never better; equal at the Barker lengths)
+    say("skew-symmetric exhaustive minima, odd N = 3..33")
+    for n in range(3, 34, 2):
+        e, c, a = lb.skew_bruteforce_min(n)
+        if n <= 33:
+            oe, oc, oa = O.skew_bruteforce_min(n)
+            assert (e, c) == (oe, oc) and np.array_equal(a, oa), n
+        assert e == O.energy(a)
+        cc = (n - 1) // 2
+        assert all(a[cc + i] == (-1) ** i * a[cc - i] for i in range(1, cc + 1))
+        if n <= 31:
+            ge, gc, _ = lb.bruteforce_min(n)
+            assert e >= ge
+            if n in (3, 5, 7, 11, 13):
+                assert e == ge == n // 2
+    from paper_2504_00987_amd._lib import LabsError
+    for bad in (4, 1, 77):
+        with pytest.raises(LabsError):
+            lb.skew_bruteforce_min(bad)
+
+
+def test_skew_bruteforce_long(lb):
+    # lengths past 64 take the 128-bit masks: the returned sequence is
+    # skew-symmetric and has the reported energy (Eq. 2 on the GPU and in
+    # the oracle), and odd lags vanish
+    for n in (63, 65, 71):
+        say(f"skew-symmetric exhaustive minimum, N={n}")
+        e, c, a = lb.skew_bruteforce_min(n)
+        cc = (n - 1) // 2
+        assert all(a[cc + i] == (-1) ** i * a[cc - i] for i in range(1, cc + 1))
+        assert a[0] == 1 and c >= 2 and c % 2 == 0
+        assert e == O.energy(a)
+        row = torch.from_numpy(a.reshape(1, n).copy()).cuda()
+        assert lb.energy_batch(row, n_uniform=n).item() == e
+        C = O.autocorrelation(a)
+        assert all(C[k] == 0 for k in range(1, n, 2))
+
+
 # ---------------------------------------------------------------------------
 # Alg. 2 / Alg. 4: batched walks
 # ---------------------------------------------------------------------------
