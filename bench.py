@@ -128,12 +128,15 @@ def tabu_section(args, lb, wl, peaks=None):
         torch.cuda.synchronize()
         return float(np.mean([a.elapsed_time(b) for a, b in ev]))
 
+    if args.launch:
+        # a fixed launch (the one a counter set was profiled under)
+        lb.set_launch(*[int(x) for x in args.launch.split(",")])
     for _ in range(args.warmup):
         lb.tabu_batch(wl.rules, W, wl.seed, out=out, stream=stream, **kw)
     torch.cuda.synchronize()
 
     tune = None
-    if not args.no_autotune:
+    if not args.launch and not args.no_autotune:
         # the library's autotuner over the workload's length range; the
         # untuned default is timed first (after the warm-up) for comparison
         n_lo, n_hi = int(ns.min()), int(ns.max())
@@ -197,8 +200,8 @@ def tabu_section(args, lb, wl, peaks=None):
         roof["lds"]["measured_peak"] = peaks["lds_bytes_per_s"] / 1e12
         roof["lds"]["frac_of_measured_peak"] = 3 * lag_terms / (kernel_ms * 1e-3) / peaks["lds_bytes_per_s"]
     digest = kernel_digest()
-    c = COUNTERS.get(wl.name)
-    if c is not None and c["digest"] == digest and tuple(c["launch"]) == tuple(launch):
+    c = COUNTERS.get((wl.name, tuple(launch)))
+    if c is not None and c["digest"] == digest:
         roof["traffic"] = (c["FETCH_SIZE"] * COPY_SCALE["FETCH_SIZE"]
                            + c["WRITE_SIZE"] * COPY_SCALE["WRITE_SIZE"]) * 1024
         lane_ops = c["SQ_INSTS_VALU"] * 64
@@ -472,6 +475,9 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default launch configuration instead of the tuned one")
+    ap.add_argument("--launch", default="",
+                    help="time this launch instead of the tuned one: group_lanes,walks_per_group,"
+                         "persistent,groups_per_cu,layout (labs_set_launch)")
     ap.add_argument("--cpu-walks", type=int, default=0, help="oracle sample size (0: all walks)")
     ap.add_argument("--cpu-min-s", type=float, default=10.0, help="minimum oracle timing")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-target section")

@@ -99,11 +99,15 @@ typedef struct labs_tabu_params {
 
 /* Launch configuration of the batched walk kernels.  Lanes per walk =
  * group_lanes / walks_per_group: 64 (one wavefront per walk: {64, 1},
- * {128, 2}, {256, 4}) or 128 ({128, 1}: the walks of 64 < N <= 128 run on
+ * {128, 2}, {256, 4}), 128 ({128, 1}: the walks of 64 < N <= 128 run on
  * two wavefronts each, exchanging their minima through LDS; the batch's
- * other walks run one per wavefront, two per 128-lane workgroup).  Fewer
- * lanes than a wavefront per walk, and four wavefronts per walk, are not
- * built (LABS_E_INVAL). */
+ * other walks run one per wavefront, two per 128-lane workgroup), or 32 /
+ * 16 ({64, 2} and {128, 4}: the walks of N <= 32 run two per wavefront, 32
+ * lanes each; {64, 4}: those of N <= 16 four per wavefront and those of
+ * 16 < N <= 32 two; the batch's longer walks run one per wavefront, one or
+ * two per workgroup).  Four wavefronts per walk, and two walks of two
+ * wavefronts in one workgroup ({256, 1}, {256, 2}), are not built
+ * (LABS_E_INVAL). */
 typedef struct labs_launch {
     int32_t group_lanes;     /* 64, 128 or 256 lanes per workgroup */
     int32_t walks_per_group; /* 1, 2 or 4 */
@@ -270,9 +274,11 @@ int labs_get_launch(labs_handle *h, int32_t n_min, int32_t n_max, labs_launch *o
 
 /*
  * Autotuner: times the launch configurations that apply to the length range
- * [n_min, n_max] -- {64, 1}, {128, 2}, {256, 4} (one wavefront per walk) and,
- * when the range reaches 64 < N <= 128, {128, 1} (two wavefronts per walk),
- * each with both layouts of those walks where they are present, and each
+ * [n_min, n_max] -- {64, 1}, {128, 2}, {256, 4} (one wavefront per walk);
+ * when the range reaches 64 < N <= 128, {128, 1} (two wavefronts per walk);
+ * when n_min <= 32, {64, 2} and {128, 4} (two walks per wavefront), and
+ * when n_min <= 16 also {64, 4} (four) -- each with both layouts of the
+ * walks of 64 < N <= 128 where they are present, and each
  * as a grid of one walk per wavefront (or pair) and as a persistent queue
  * at 1, 2, 4 and 8 x 4 / (wavefronts per group) groups per CU -- on `walks`
  * random-start walks with lengths spread evenly over [n_min, n_max] and

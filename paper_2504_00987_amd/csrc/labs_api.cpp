@@ -216,13 +216,13 @@ labs_launch default_launch(int n_max) {
     return l;
 }
 
-// Lanes per walk 64 (one wavefront) or 128 (two, one walk per workgroup).
+// Lanes per walk 16 or 32 (several walks of N <= 32 per wavefront; longer
+// walks of the batch take one wavefront each), 64 (one wavefront) or 128
+// (two, one walk per workgroup).
 const char *launch_problem(const labs_launch &l) {
     const int g = l.group_lanes, w = l.walks_per_group;
     if (g != 64 && g != 128 && g != 256) return "group_lanes must be 64, 128 or 256";
     if (w != 1 && w != 2 && w != 4) return "walks_per_group must be 1, 2 or 4";
-    if (g / w < 64)
-        return "fewer than 64 lanes per walk (several walks per wavefront) are not built";
     if (g / w > 128) return "four wavefronts per walk are not built";
     if (g / w == 128 && w != 1)
         return "two wavefronts per walk take one 128-lane workgroup each (a walk's barriers "
@@ -235,7 +235,9 @@ const char *launch_problem(const labs_launch &l) {
 
 WalkLaunch walk_launch(const labs_handle *h, const labs_launch &l) {
     WalkLaunch w;
-    w.split = l.group_lanes / l.walks_per_group == 128;
+    const int lanes = l.group_lanes / l.walks_per_group;
+    w.split = lanes == 128;
+    w.lanes = lanes < 64 ? lanes : 64;
     w.waves_per_group = l.group_lanes / 64;
     w.lag = l.layout == 1 || (l.layout == 0 && w.split);
     const int cus = std::max(1, h->num_cus);
@@ -633,7 +635,7 @@ int tabu_batch_impl(labs_handle *h, const labs_tabu_params *p, const int8_t *sta
     // The launch groups present run concurrently: the first on `s`, the
     // others on the handle's side streams, forked from and joined into `s`.
     const SideStreams &sides = h->sides;
-    const WalkGroups wg = walk_launch_groups(a.class_end, WL.split);
+    const WalkGroups wg = walk_launch_groups(a.class_end, WL.split, WL.lanes);
     hipStream_t streams[kWalkClasses];
     const int n_sides = std::max(0, wg.n - 1);
     streams[0] = s;
@@ -729,6 +731,15 @@ extern "C" int labs_autotune(labs_handle *h, const labs_tabu_params *p, int32_t 
             cands.push_back(labs_launch{128, 1, 0, 0, layout});
             for (int gpc : {1, 2, 4, 8}) cands.push_back(labs_launch{128, 1, 1, gpc, layout});
         }
+        // several walks per wavefront where walks of N <= 32 are present
+        // (16 lanes per walk only where N <= 16 ones are)
+        constexpr int kSub[3][2] = {{64, 2}, {128, 4}, {64, 4}};  // group lanes, walks
+        for (const auto &gw : kSub) {
+            if (n_min > gw[0] / gw[1]) continue;
+            cands.push_back(labs_launch{gw[0], gw[1], 0, 0, layout});
+            for (int gpc : {1, 2, 4, 8})
+                cands.push_back(labs_launch{gw[0], gw[1], 1, gpc * 4 / (gw[0] / 64), layout});
+        }
     }
     float best_ms = 1e30f;
     labs_launch best = cands[0];
@@ -741,7 +752,8 @@ extern "C" int labs_autotune(labs_handle *h, const labs_tabu_params *p, int32_t 
         const labs_launch &c = cands[i];
         const WalkLaunch wc = walk_launch(h, c), w0 = walk_launch(h, cands[0]);
         if (i > 0 && wc.waves_per_group == w0.waves_per_group && wc.split == w0.split &&
-            wc.lag == w0.lag && wc.groups == w0.groups && wc.split_groups == w0.split_groups)
+            wc.lag == w0.lag && wc.lanes == w0.lanes && wc.groups == w0.groups &&
+            wc.split_groups == w0.split_groups)
             continue;  // the same kernels as the default, timed first
         rc = run(c);
         hipEventRecord(e0, s);

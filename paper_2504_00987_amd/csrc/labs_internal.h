@@ -17,6 +17,18 @@ struct RuleParams {
     int32_t slo_num, slo_den, shi_num, shi_den;  // LABS_STEPS_RANGE bounds
 };
 
+// Length classes of stand-alone walks, longest first: a class fixes the
+// neighbours per lane (NW) and how many 16-lag chunks a window spans (NB).
+// The last two (N <= 32, N <= 16) are also the walks that fit a 32- or
+// 16-lane group of a wavefront that runs several walks.
+constexpr int kWalkClasses = 8;
+constexpr int kClassMaxN[kWalkClasses] = {256, 193, 128, 97, 64, 49, 32, 16};
+inline int walk_class(int n) {
+    int c = 0;
+    while (c + 1 < kWalkClasses && n <= kClassMaxN[c + 1]) ++c;
+    return c;
+}
+
 struct TabuLaunchArgs {
     const int8_t *starts;     // [W][start_stride] or null
     int32_t start_stride;
@@ -25,8 +37,8 @@ struct TabuLaunchArgs {
     int32_t n_max;            // longest walk in the batch
     const int32_t *order;     // device [W] walk ids in processing order, or null
     int64_t W;
-    int64_t class_end[6];     // processing-order positions [class_end[c-1], class_end[c])
-                              // hold the walks of length class c (kWalkClasses)
+    int64_t class_end[kWalkClasses];  // processing-order positions [class_end[c-1],
+                                      // class_end[c]) hold the walks of class c
     uint32_t k0, k1;
     RuleParams rule;
     int8_t *best_seq;
@@ -38,64 +50,75 @@ struct TabuLaunchArgs {
     uint32_t *counter;        // device, 32 words per class: persistent queue heads
 };
 
-// Length classes of stand-alone walks, longest first: a class fixes the
-// neighbours per lane (NW) and how many 16-lag chunks a window spans (NB).
-constexpr int kWalkClasses = 6;
-constexpr int kClassMaxN[kWalkClasses] = {256, 193, 128, 97, 64, 49};
-inline int walk_class(int n) {
-    int c = 0;
-    while (c + 1 < kWalkClasses && n <= kClassMaxN[c + 1]) ++c;
-    return c;
-}
 // Streams besides the caller's one that a batch may fork onto.
 constexpr int kSideStreams = kWalkClasses - 1;
+
+// Kernel forms of a launch group.
+enum WalkKind : int {
+    kKindWave = 0,    // one walk per wavefront
+    kKindSplit = 1,   // one walk of 64 < N <= 128 per two wavefronts
+    kKindGroup2 = 2,  // two walks of N <= 32 per wavefront (32 lanes each)
+    kKindGroup4 = 4,  // four walks of N <= 16 per wavefront (16 lanes each)
+};
+
 // Launch groups of a batch: runs of consecutive length classes (hence of
 // consecutive positions of the processing order) that one kernel launch
 // covers, each on a stream of its own.  Both classes of N > 128, when
 // present, share one launch (the four-neighbour layout serves both); so do
 // the classes of N <= 128 when more than one is present -- or, with
 // two-wavefront walks (split), classes 2..3 (64 < N <= 128) form one group
-// and classes 4..5 another.
+// and the shorter classes another.  With several walks per wavefront
+// (`lanes` = 32 or 16 lanes per walk) the walks of N <= 32 leave the
+// one-walk-per-wavefront group: with 32 lanes both short classes form one
+// group of two walks per wavefront; with 16, N <= 16 runs four per
+// wavefront and 16 < N <= 32 two.
 struct WalkGroups {
     int n;
-    int first[kWalkClasses], last[kWalkClasses];
+    int first[kWalkClasses], last[kWalkClasses], kind[kWalkClasses];
 };
-inline WalkGroups walk_launch_groups(const int64_t *class_end, bool split) {
+inline WalkGroups walk_launch_groups(const int64_t *class_end, bool split, int lanes = 64) {
     WalkGroups g;
     g.n = 0;
     auto present = [&](int c) { return class_end[c] > (c ? class_end[c - 1] : 0); };
-    auto range = [&](int lo, int hi) {
+    auto add = [&](int f, int z, int kind) {
+        g.first[g.n] = f;
+        g.last[g.n] = z;
+        g.kind[g.n] = kind;
+        ++g.n;
+    };
+    auto range = [&](int lo, int hi, int kind) {
         int f = -1, z = -1;
         for (int c = lo; c <= hi; ++c)
             if (present(c)) {
                 if (f < 0) f = c;
                 z = c;
             }
-        if (f < 0) return;
-        g.first[g.n] = f;
-        g.last[g.n] = z;
-        ++g.n;
+        if (f >= 0) add(f, z, kind);
     };
-    range(0, 1);
+    const int short_end = lanes < 64 ? 5 : kWalkClasses - 1;
+    range(0, 1, kKindWave);
     if (split) {
-        if (present(2) || present(3)) {  // the two-wavefront kernel takes both
-            g.first[g.n] = 2;
-            g.last[g.n] = 3;
-            ++g.n;
-        }
-        range(4, 5);
+        if (present(2) || present(3)) add(2, 3, kKindSplit);  // the two-wavefront kernel takes both
+        range(4, short_end, kKindWave);
     } else {
-        range(2, 5);
+        range(2, short_end, kKindWave);
+    }
+    if (lanes == 32) {
+        range(6, 7, kKindGroup2);
+    } else if (lanes == 16) {
+        range(6, 6, kKindGroup2);
+        range(7, 7, kKindGroup4);
     }
     return g;
 }
 
 // How labs_tabu_batch launches its walks.
 struct WalkLaunch {
-    int waves_per_group;  // one-wavefront walks: 1, 2 or 4 per workgroup
+    int waves_per_group;  // wavefronts per workgroup (one-wavefront walks: that many per group)
     bool split;           // walks of 64 < N <= 128 on two wavefronts each
     bool lag;             // walks of 64 < N <= 128 in the lag form
-    int groups;           // persistent grid of the one-wavefront kernels (0: none)
+    int lanes;            // lanes per walk of N <= 32: 64 (one walk per wavefront), 32 or 16
+    int groups;           // persistent grid of the one-wavefront and group kernels (0: none)
     int split_groups;     // persistent grid of the two-wavefront kernel (0: none)
 };
 
@@ -188,7 +211,7 @@ hipError_t launch_bruteforce(int n, const BruteParts &p, hipStream_t s);
 int64_t skew_brute_waves(int n);
 hipError_t launch_skew_bruteforce(int n, const BruteParts &p, hipStream_t s);
 
-// Launch group g (walk_launch_groups(a.class_end, l.split)) runs on
+// Launch group g (walk_launch_groups(a.class_end, l.split, l.lanes)) runs on
 // streams[g]; a.counter must point at 32 * kWalkClasses writable uint32 (the
 // queue head of a group at 32 * its first class).
 hipError_t launch_tabu(const TabuLaunchArgs &a, const WalkLaunch &l, const hipStream_t *streams);

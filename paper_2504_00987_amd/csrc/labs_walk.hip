@@ -4,7 +4,9 @@
 //   tabu_kernel     independent tabu walks (Alg. 2 / Alg. 4), one walk per
 //                   wave, either one wave per walk or a persistent grid
 //                   draining a longest-first work queue; one instantiation
-//                   per length class
+//                   per length class (tabu_kernel_mixed: several classes in
+//                   one launch; tabu_kernel_split: a walk on two waves;
+//                   tabu_kernel_group: two or four walks of N <= 32 per wave)
 //   fill_u32_kernel device-side fill (queue heads, flags), capturable
 //   order_by_length_kernel  longest-first processing order built on the
 //                   device (the allocation-free entry point's lengths)
@@ -133,9 +135,241 @@ __device__ void run_split_item(const TabuLaunchArgs &a, int64_t w, int N, uint8_
 // lane-0-only fetch lets the optimiser thread that branch into the loop's
 // other lane-0 branches, and lanes then reach the readlane before lane 0 has
 // fetched, disagreeing on the index.
-__device__ __forceinline__ uint32_t next_work(uint32_t *counter) {
-    const uint32_t v = atomicAdd(counter, lane_id() == 0 ? 1u : 0u);
+__device__ __forceinline__ uint32_t next_work(uint32_t *counter, uint32_t take = 1u) {
+    const uint32_t v = atomicAdd(counter, lane_id() == 0 ? take : 0u);
     return readlane_u(v, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Several walks per wavefront (N <= 32).
+// ---------------------------------------------------------------------------
+// A wavefront runs G walks of N <= GL = 64 / G at once, lane l of group
+// g = l / GL owning neighbour j = l % GL and lag k = j + 1 of walk g.  The
+// step is the lag form's (rows of t_jk; v_j as dot products of row j with
+// C; u_j kept per neighbour; one byte of each row rewritten per move), with
+// every per-walk quantity (the sequence mask, E, the best, the chosen move,
+// the schedule) held per lane for the lane's own walk instead of in scalar
+// registers, the minimum and the energy taken within each group of lanes,
+// and a tied move picked by its rank within the group.  Walks of different
+// lengths share the step loop; a walk past its last step, or a group past
+// the end of the range, takes no move.
+//
+// LDS of one walk: 16 spare bytes, rows j = 0..GL-1 of kGroupRow bytes
+// (t_jk for k = 1..GL in bytes 0..GL-1, zero past the sequence; 48 bytes
+// apart, an odd number of 16-byte slots, so that 16-byte reads of
+// consecutive rows are conflict-free), C_k as int8 (GL bytes), then the
+// sequence as int8 with zeros around it, SP[q] for q = -GL .. 2 GL - 1.
+constexpr int kGroupRow = 48;
+template <int GL>
+struct GroupLds {
+    static constexpr int BASE = 16;
+    static constexpr int CB = BASE + GL * kGroupRow;
+    static constexpr int SPLO = CB + GL, SP = SPLO + GL;
+    static constexpr int BYTES = SPLO + 3 * GL;
+    static_assert(BYTES % 16 == 0, "16-byte aligned walks");
+};
+
+// ds_swizzle in its 32-lane bit-mask mode: lane i reads lane i ^ 16.
+constexpr int kSwizzleXor16 = (0x10 << 10) | 0x1f;
+
+// Minimum and sum over each group of GL = 16 or 32 consecutive lanes, every
+// lane receiving its group's value: row (16-lane) reductions by DPP, then,
+// for GL = 32, the two rows of a group combined by the swizzle.
+template <int GL>
+__device__ __forceinline__ int group_min(int v) {
+    v = min(v, __builtin_amdgcn_mov_dpp(v, LABS_DPP_QUAD_1032, 0xf, 0xf, true));
+    v = min(v, __builtin_amdgcn_mov_dpp(v, LABS_DPP_QUAD_2301, 0xf, 0xf, true));
+    v = min(v, __builtin_amdgcn_mov_dpp(v, LABS_DPP_ROW_HALF_MIRROR, 0xf, 0xf, true));
+    v = min(v, __builtin_amdgcn_mov_dpp(v, LABS_DPP_ROW_MIRROR, 0xf, 0xf, true));
+    if constexpr (GL == 32) v = min(v, __builtin_amdgcn_ds_swizzle(v, kSwizzleXor16));
+    return v;
+}
+
+template <int GL>
+__device__ __forceinline__ int group_sum(int v) {
+    v += __builtin_amdgcn_mov_dpp(v, LABS_DPP_QUAD_1032, 0xf, 0xf, true);
+    v += __builtin_amdgcn_mov_dpp(v, LABS_DPP_QUAD_2301, 0xf, 0xf, true);
+    v += __builtin_amdgcn_mov_dpp(v, LABS_DPP_ROW_HALF_MIRROR, 0xf, 0xf, true);
+    v += __builtin_amdgcn_mov_dpp(v, LABS_DPP_ROW_MIRROR, 0xf, 0xf, true);
+    if constexpr (GL == 32) v += __builtin_amdgcn_ds_swizzle(v, kSwizzleXor16);
+    return v;
+}
+
+// Group g's GL bits of a wave-wide ballot.
+template <int GL>
+__device__ __forceinline__ uint32_t group_bits(uint64_t m, int g) {
+    return (uint32_t)(m >> (GL * g)) & (GL == 32 ? 0xffffffffu : 0xffffu);
+}
+
+// The value v of lane `src` (any lane of the wavefront), per lane.
+__device__ __forceinline__ int lane_value(int v, int src) {
+    return __builtin_amdgcn_ds_bpermute(src << 2, v);
+}
+
+// Walks at processing-order positions pos0 .. pos0 + G - 1 (those below
+// `end`), all of N <= 64 / G, on one wavefront; `lds` holds G walks'
+// GroupLds.  Results as the one-walk-per-wavefront form writes them.
+template <int G, bool TRACE>
+__device__ void run_group_walks(const TabuLaunchArgs &a, int64_t pos0, int64_t end,
+                                uint8_t *lds_wave) {
+    constexpr int GL = 64 / G;
+    constexpr int NB = GL / 16;  // 16-lag chunks of a row
+    using L = GroupLds<GL>;
+    const int lane = lane_id();
+    const int g = lane / GL, j = lane % GL;
+    const int64_t pos = pos0 + g;
+    const bool live = pos < end;
+    const int64_t w = live ? (a.order ? (int64_t)a.order[pos] : pos) : 0;
+    const int N = live ? (a.ns ? a.ns[w] : a.n_uniform) : 0;
+    uint8_t *const lds = lds_wave + g * L::BYTES;
+    uint8_t *const rows = lds + L::BASE;
+    int8_t *const CB = (int8_t *)(lds + L::CB);
+
+    // start (bit i set <=> s_i = -1): the caller's row, or the low N bits
+    // of the draw (w, 0, 0, START)
+    uint32_t M;
+    if (a.starts != nullptr) {
+        const int8_t *row = a.starts + w * (int64_t)a.start_stride;
+        M = group_bits<GL>(ballot(j < N && row[j] < 0), g);
+    } else {
+        const Draw4 d = philox10((uint32_t)w, 0u, 0u, kTagStart, a.k0, a.k1);
+        M = N > 0 ? d.w0 & (0xffffffffu >> (32 - N)) : 0u;
+    }
+    Schedule sch = make_schedule(a.rule, N, a.k0, a.k1, (uint32_t)w, 0u);
+    if (!live) sch.T = 0;
+    const uint32_t Mr = N > 0 ? __builtin_bitreverse32(M) >> (32 - N) : 0u;  // bit i: s_{N-1-i}
+
+    // row j: s_{j+k} is bit k-1 of R, s_{j-k} bit k-1 of Lb
+    const int nr = max(N - 1 - j, 0), nl = j < N ? j : 0;
+    const uint64_t R = (uint64_t)M >> (j + 1);
+    const uint64_t Lb = j < N ? (uint64_t)Mr >> (N - j) : 0ull;
+    uint32_t *const row = (uint32_t *)(rows + kGroupRow * j);
+#pragma unroll
+    for (int d = 0; d < GL / 4; ++d)
+        row[d] = add_bytes(pack_bits4(R, 4 * d, nr), pack_bits4(Lb, 4 * d, nl));
+    for (int idx = j; idx < 3 * GL / 4; idx += GL) {
+        const int x = 4 * idx - GL;  // SP[x .. x+3]
+        ((uint32_t *)(lds + L::SPLO))[idx] = x < 0 ? 0u : pack_bits4(M, x, N);
+    }
+    const int nu = min(nr, nl);
+    int u2 = 2 * (nu - 2 * __popcll((R ^ Lb) & ((1ull << nu) - 1ull)));
+    const int k = j + 1;
+    int C = k < N ? (N - k) - 2 * __popcll(((uint64_t)M ^ ((uint64_t)M >> k)) &
+                                           ((1ull << (N - k)) - 1ull))
+                  : 0;
+    CB[j] = (int8_t)C;
+    int E = group_sum<GL>(C * C);
+    int tabu = j < N ? 0 : INT_MAX;  // lanes past the sequence are never admissible
+    const bool asp = a.rule.aspiration && j < N;
+    const uint32_t rowm1 = lds_offset(lds) + (uint32_t)(L::BASE + kGroupRow * j - 1);
+    const uint32_t spj = lds_offset(lds) + (uint32_t)(L::SP + 2 * j);
+    uint32_t best = M;
+    int bestE = E;
+    const int T_all = -wave_min(-sch.T);  // the longest walk of the wavefront
+
+    wave_sync();
+    uint4 tc[NB];
+#pragma unroll
+    for (int r = 0; r < NB; ++r) tc[r] = ((const uint4 *)(rows + kGroupRow * j))[r];
+
+    for (int t0 = 1; t0 <= T_all; t0 += GL) {
+        // lane j of a group: the draws of its walk's step t0 + j
+        uint32_t dr0;
+        int expire;
+        {
+            const Draw4 d = philox10((uint32_t)w, 0u, (uint32_t)(t0 + j), kTagStep, a.k0, a.k1);
+            dr0 = d.w0;
+            expire = t0 + j + sch.lo + (int)below(d.w1, (uint32_t)(sch.hi - sch.lo + 1));
+        }
+        const int t_end = min(T_all, t0 + GL - 1);
+        for (int t = t0; t <= t_end; ++t) {
+            const int src = g * GL + (t - t0);  // the lane holding this step's draws
+            wave_sync();                        // the previous move's C and row bytes
+            uint4 cc[NB];
+#pragma unroll
+            for (int r = 0; r < NB; ++r) cc[r] = ((const uint4 *)CB)[r];
+            const uint32_t dr = (uint32_t)lane_value((int)dr0, src);
+            const int tabu_new = lane_value(expire, src);
+            // key d_j = 2 u_j - s_j v_j: candE_j = E + 4 (N - 1) + 4 d_j
+            const int thr = ((bestE - E) >> 2) - (N - 1);
+            int v = 0;
+#pragma unroll
+            for (int r = 0; r < NB; ++r) v = dot16(tc[r], cc[r], v);
+            const int ns = (M >> j) & 1u ? 1 : -1;  // -s_j
+            const int d = mad_i24_after_dot(ns, v, u2);
+            const int key = tabu < t || (asp && d < thr) ? d : INT_MAX;
+            const int m = group_min<GL>(key);
+            // ties: the r-th lowest tied neighbour of the group, r from the
+            // step's first draw
+            const uint32_t tied = group_bits<GL>(ballot(key == m), g);
+            const int r = (int)below(dr, (uint32_t)__popc(tied));
+            const bool mine = key == m && __popc(tied & ((1u << j) - 1u)) == r;
+            const int pick = __builtin_ctz(group_bits<GL>(ballot(mine), g));
+            if (t <= sch.T) {
+                const bool neg = (M >> pick) & 1u;
+                const int sm = neg ? -1 : 1;  // old s_pick
+                const int k2 = neg ? 2 : -2;  // -2 s_pick(old)
+                const int k4 = neg ? 4 : -4;
+                M ^= 1u << pick;
+                E += 4 * (N - 1 + m);
+                if (E < bestE) {
+                    bestE = E;
+                    best = M;
+                }
+                if constexpr (TRACE) {
+                    if (j == 0) a.trace[w * (int64_t)a.trace_stride + t - 1] = (int16_t)pick;
+                }
+                // as in the lag form: q = 2j - pick is the other end of lag
+                // |pick - j| of row j; C_k -= 2 s_pick(old) t_pick,k from row
+                // pick, which the move leaves unchanged; lane pick stores the
+                // new s_pick into SP[pick] after every read of it
+                const uint32_t qa = spj - (uint32_t)pick;
+                int sq = lds_load_i8(qa);
+                asm("" : "+v"(sq));  // one sign-extending load
+                const int tpk = ((const int8_t *)rows)[kGroupRow * pick + j];
+                C += k2 * tpk;
+                CB[j] = (int8_t)C;
+                u2 += k4 * sq;
+                lds_store_i8(rowm1 + (uint32_t)abs(pick - j), sq - sm);
+                if (j == pick) {
+                    lds_store_i8(qa, ns);
+                    u2 += 4;
+                    tabu = tabu_new;
+                }
+            }
+            wave_sync();
+#pragma unroll
+            for (int r = 0; r < NB; ++r) tc[r] = ((const uint4 *)(rows + kGroupRow * j))[r];
+        }
+    }
+    if (live) {
+        int8_t *out = a.best_seq + w * (int64_t)a.out_stride;
+        for (int i = j; i < a.out_stride; i += GL)
+            out[i] = i < N ? (((best >> i) & 1u) ? (int8_t)-1 : (int8_t)1) : (int8_t)0;
+        if (j == 0) {
+            a.best_e[w] = bestE;
+            a.final_e[w] = E;
+        }
+    }
+}
+
+// Walks of N <= 64 / G at positions [begin, end), G per wavefront and WAVES
+// wavefronts per workgroup.  PERSIST: a grid sized to the device takes G
+// positions at a time from the queue head `counter`; otherwise one
+// wavefront per G positions.
+template <int G, int WAVES, bool PERSIST, bool TRACE>
+__global__ __launch_bounds__(64 * WAVES) void tabu_kernel_group(TabuLaunchArgs a, int64_t begin,
+                                                                int64_t end, uint32_t *counter) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds_all[WAVES][G * GroupLds<64 / G>::BYTES];
+    uint8_t *lds = lds_all[threadIdx.x >> 6];
+    if constexpr (PERSIST) {
+        for (int64_t pos = begin + next_work(counter, G); pos < end;
+             pos = begin + next_work(counter, G))
+            run_group_walks<G, TRACE>(a, pos, end, lds);
+    } else {
+        const int64_t pos = begin + ((int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6)) * G;
+        if (pos < end) run_group_walks<G, TRACE>(a, pos, end, lds);
+    }
 }
 
 // Walks at positions [begin, end) of the processing order, all of one length
@@ -210,8 +444,8 @@ __global__ __launch_bounds__(128) void tabu_kernel_split(TabuLaunchArgs a, int64
     }
 }
 
-// Walks of the classes with N <= 128 (processing-order positions
-// [class_end[1], class_end[5])) in one launch: each wavefront runs the
+// Walks of the classes with N <= 128 (processing-order positions from
+// class_end[1] on) in one launch: each wavefront runs the
 // instantiation of its own walk's class, in LDS scratch sized for the
 // largest of them.  One launch on the caller's stream spares a batch of
 // several such classes the fork to side streams and the join back, whose
@@ -235,8 +469,12 @@ __device__ __forceinline__ void run_mixed_item(const TabuLaunchArgs &a, int64_t 
         run_tabu_item<2, 5, TRACE, LAG>(a, w, N, lds);
     else if (N > kClassMaxN[5])
         run_tabu_item<1, 4, TRACE>(a, w, N, lds);
-    else
+    else if (N > kClassMaxN[6])
         run_tabu_item<1, 3, TRACE>(a, w, N, lds);
+    else if (N > kClassMaxN[7])
+        run_tabu_item<1, 2, TRACE>(a, w, N, lds);
+    else
+        run_tabu_item<1, 1, TRACE>(a, w, N, lds);
 }
 
 // Walks of N > 128 (classes 0 and 1, positions [0, class_end[1])) in one
@@ -439,27 +677,61 @@ hipError_t launch_split(const TabuLaunchArgs &a, int64_t begin, int64_t end, int
                               : launch_split_t<false, LAG>(a, begin, end, groups, counter, s);
 }
 
+template <int G, int WAVES, bool TRACE>
+hipError_t launch_group_t(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
+                          uint32_t *counter, hipStream_t s) {
+    const int64_t need = (end - begin + G * WAVES - 1) / (G * WAVES);
+    if (groups > 0) {
+        hipError_t e = launch_fill_u32(counter, 0u, 1, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((tabu_kernel_group<G, WAVES, true, TRACE>),
+                           dim3((unsigned)std::min<int64_t>(groups, need)), dim3(64 * WAVES), 0, s,
+                           a, begin, end, counter);
+    } else {
+        hipLaunchKernelGGL((tabu_kernel_group<G, WAVES, false, TRACE>), dim3((unsigned)need),
+                           dim3(64 * WAVES), 0, s, a, begin, end, counter);
+    }
+    return hipGetLastError();
+}
+
+template <int G, int WAVES>
+hipError_t launch_group(const TabuLaunchArgs &a, int64_t begin, int64_t end, int groups,
+                        uint32_t *counter, hipStream_t s) {
+    if (end <= begin) return hipSuccess;
+    if constexpr (WAVES > 2) {
+        return hipErrorInvalidValue;  // 32 or 16 lanes per walk: 64- or 128-lane workgroups
+    } else {
+        return a.trace != nullptr
+                   ? launch_group_t<G, WAVES, true>(a, begin, end, groups, counter, s)
+                   : launch_group_t<G, WAVES, false>(a, begin, end, groups, counter, s);
+    }
+}
+
 // One launch per launch group (walk_launch_groups), group g on streams[g]
 // with the queue head of its first class (32 words apart).
 template <int WPG, bool LAG>
 hipError_t launch_tabu_wpg(const TabuLaunchArgs &a, const WalkLaunch &l, const hipStream_t *st) {
-    static_assert(kWalkClasses == 6, "one launcher per class below");
+    static_assert(kWalkClasses == 8, "one launcher per class below");
     const int64_t *ce = a.class_end;
-    const WalkGroups wg = walk_launch_groups(ce, l.split);
+    const WalkGroups wg = walk_launch_groups(ce, l.split, l.lanes);
     hipError_t e = hipSuccess;
     for (int g = 0; g < wg.n && e == hipSuccess; ++g) {
-        const int f = wg.first[g], z = wg.last[g];
+        const int f = wg.first[g], z = wg.last[g], kind = wg.kind[g];
         const int64_t begin = f ? ce[f - 1] : 0, end = ce[z];
         uint32_t *q = a.counter + 32 * f;
-        const int groups = l.split && f == 2 ? l.split_groups : l.groups;
-        if (f == 0 && z == 1)
+        const int groups = kind == kKindSplit ? l.split_groups : l.groups;
+        if (kind == kKindGroup2)
+            e = launch_group<2, WPG>(a, begin, end, groups, q, st[g]);
+        else if (kind == kKindGroup4)
+            e = launch_group<4, WPG>(a, begin, end, groups, q, st[g]);
+        else if (kind == kKindSplit)
+            e = launch_split<LAG>(a, begin, end, groups, q, st[g]);
+        else if (f == 0 && z == 1)
             e = launch_mixed<WPG, true, false>(a, begin, end, groups, q, st[g]);
         else if (f == 0)
             e = launch_tabu_part<4, 16, WPG>(a, begin, end, groups, q, st[g]);
         else if (f == 1)
             e = launch_tabu_part<4, 12, WPG>(a, begin, end, groups, q, st[g]);
-        else if (l.split && f == 2)
-            e = launch_split<LAG>(a, begin, end, groups, q, st[g]);
         else if (z > f)  // several classes of N <= 128 in one launch
             e = launch_mixed<WPG, false, LAG>(a, begin, end, groups, q, st[g]);
         else if (f == 2)
@@ -468,8 +740,12 @@ hipError_t launch_tabu_wpg(const TabuLaunchArgs &a, const WalkLaunch &l, const h
             e = launch_tabu_part<2, 6, WPG, LAG>(a, begin, end, groups, q, st[g]);
         else if (f == 4)
             e = launch_tabu_part<1, 4, WPG>(a, begin, end, groups, q, st[g]);
-        else
+        else if (f == 5)
             e = launch_tabu_part<1, 3, WPG>(a, begin, end, groups, q, st[g]);
+        else if (f == 6)
+            e = launch_tabu_part<1, 2, WPG>(a, begin, end, groups, q, st[g]);
+        else
+            e = launch_tabu_part<1, 1, WPG>(a, begin, end, groups, q, st[g]);
     }
     return e;
 }
@@ -478,6 +754,13 @@ hipError_t launch_tabu_wpg(const TabuLaunchArgs &a, const WalkLaunch &l, const h
 
 hipError_t launch_tabu(const TabuLaunchArgs &a, const WalkLaunch &l, const hipStream_t *streams) {
     if (a.W <= 0) return hipSuccess;
+    // every launch range lies inside the processing order [0, W)
+    int64_t prev = 0;
+    for (int c = 0; c < kWalkClasses; ++c) {
+        if (a.class_end[c] < prev || a.class_end[c] > a.W) return hipErrorInvalidValue;
+        prev = a.class_end[c];
+    }
+    if (prev != a.W) return hipErrorInvalidValue;
     switch (l.waves_per_group * 2 + (l.lag ? 1 : 0)) {
     case 2: return launch_tabu_wpg<1, false>(a, l, streams);
     case 3: return launch_tabu_wpg<1, true>(a, l, streams);

@@ -4,6 +4,7 @@ All results are integers decided by integer arithmetic and the shared RNG
 contract, so the bar is bit-exact equality of energies, best sequences,
 final energies and per-step flip traces.
 """
+import dataclasses
 import sys
 
 import numpy as np
@@ -240,6 +241,104 @@ def test_tabu_launch_invariance(lb, launch):
     assert np.array_equal(res.best_e.cpu().numpy(), be)
     assert np.array_equal(res.final_e.cpu().numpy(), fe)
     assert np.array_equal(res.best_seq.cpu().numpy(), best)
+
+
+# Several walks per wavefront: 32 lanes per walk ({64, 2}, {128, 4}) or 16
+# ({64, 4}: N <= 16 four per wavefront, 16 < N <= 32 two), as a grid of one
+# wavefront per two or four walks or a persistent queue at the automatic and
+# a fixed grid; the batch's longer walks keep their one-wavefront kernels.
+SUBWAVE_GRID = [(gl, wpg, p, g, 0) for gl, wpg in ((64, 2), (128, 4), (64, 4))
+                for p, g in ((0, 0), (1, 0), (1, 2))]
+
+
+@pytest.mark.parametrize("launch", SUBWAVE_GRID)
+def test_tabu_subwave_launch(lb, launch):
+    # N in 3..40 (both short classes and part of 32 < N <= 49), 301 walks:
+    # the last wavefront of each class has empty groups
+    ns = I.uneven_lengths(301, 3, 40, seed=51)
+    say(f"tabu: N in 3..40, launch configuration {launch} gives identical walks")
+    rules = I.rules_tabu(3)
+    lb.set_launch(*launch)
+    try:
+        res = lb.tabu_batch(rules, len(ns), 5151, ns=ns)
+    finally:
+        lb.set_launch(None)
+    best, be, fe = O.tabu_batch(len(ns), osched(rules), 5151, ns=ns, stride=128, nthreads=8)
+    assert np.array_equal(res.best_e.cpu().numpy(), be)
+    assert np.array_equal(res.final_e.cpu().numpy(), fe)
+    assert np.array_equal(res.best_seq.cpu().numpy(), best)
+
+
+@pytest.mark.parametrize("launch", [(64, 2, 0, 0, 0), (64, 4, 1, 0, 0), (128, 4, 1, 1, 0)])
+@pytest.mark.parametrize("asp", [1, 0])
+def test_tabu_subwave_traces_and_starts(lb, launch, asp):
+    # every N in 3..33 three times, the caller's starts (all +1, alternating,
+    # random), paper walk lengths (differing within a wavefront) and traces
+    ns = np.repeat(np.arange(3, 34, dtype=np.int32), 3)
+    say(f"tabu: every N in 3..33, starts and traces, aspiration={asp}, launch {launch}")
+    starts = I.random_pm1_ragged(ns, 64, seed=52)
+    for i, n in enumerate(ns):
+        if i % 3 == 0:
+            starts[i, :n] = 1
+        elif i % 3 == 1:
+            starts[i, :n] = [(-1) ** j for j in range(n)]
+    rules = dataclasses.replace(I.RULES_PAPER_LITERAL, aspiration=asp)
+    lb.set_launch(*launch)
+    try:
+        res = lb.tabu_batch(rules, len(ns), 53, ns=ns, starts=torch.from_numpy(starts).cuda(),
+                            trace_stride=64)
+    finally:
+        lb.set_launch(None)
+    best, be, fe, trs = _oracle_walks(len(ns), ns, rules, 53, starts=starts)
+    assert np.array_equal(res.best_e.cpu().numpy(), be)
+    assert np.array_equal(res.final_e.cpu().numpy(), fe)
+    assert np.array_equal(res.best_seq.cpu().numpy(), best)
+    tr = res.trace.cpu().numpy()
+    for w in range(len(ns)):
+        assert np.array_equal(tr[w, : len(trs[w])], trs[w]), f"N={ns[w]}"
+
+
+@pytest.mark.parametrize("n,W", [(32, 37), (17, 3), (16, 13), (5, 66), (3, 1)])
+@pytest.mark.parametrize("launch", [(64, 2, 0, 0, 0), (64, 4, 0, 0, 0), (128, 4, 1, 2, 0)])
+def test_tabu_subwave_uniform(lb, n, W, launch):
+    # one length for the whole batch (no per-walk lengths), walk counts that
+    # leave the last wavefront partly empty
+    say(f"tabu: {W} walks of N={n}, launch {launch}")
+    rules = I.rules_tabu(4)
+    lb.set_launch(*launch)
+    try:
+        res = lb.tabu_batch(rules, W, 600 + n, n_uniform=n, trace_stride=4 * n)
+    finally:
+        lb.set_launch(None)
+    best, be, fe, trs = _oracle_walks(W, n, rules, 600 + n)
+    assert np.array_equal(res.best_e.cpu().numpy(), be)
+    assert np.array_equal(res.final_e.cpu().numpy(), fe)
+    assert np.array_equal(res.best_seq.cpu().numpy(), best)
+    tr = res.trace.cpu().numpy()
+    for w in range(W):
+        assert np.array_equal(tr[w, : len(trs[w])], trs[w])
+
+
+def test_autotune_short_range():
+    # N <= 32 adds the several-walks-per-wavefront points to the tuned grid
+    from paper_2504_00987_amd.labs import Labs
+    say("autotune over N in [3, 32], then parity under the tuned launch")
+    h = Labs(0)
+    try:
+        rules = I.rules_tabu(3)
+        tried = h.autotune(rules, 3, 32, 2048, seed=5)
+        assert tried >= 25
+        gl, wpg, pers, gpc, lay = h.get_launch(3, 32)
+        assert (gl, wpg) in ((64, 1), (128, 2), (256, 4), (64, 2), (128, 4), (64, 4))
+        say(f"autotune chose {(gl, wpg, pers, gpc, lay)} after {tried} configurations")
+        ns = I.uneven_lengths(500, 3, 32, seed=54)
+        res = h.tabu_batch(rules, len(ns), 55, ns=ns)
+        best, be, fe = O.tabu_batch(len(ns), osched(rules), 55, ns=ns, stride=128, nthreads=8)
+        assert np.array_equal(res.best_e.cpu().numpy(), be)
+        assert np.array_equal(res.final_e.cpu().numpy(), fe)
+        assert np.array_equal(res.best_seq.cpu().numpy(), best)
+    finally:
+        h.close()
 
 
 def test_autotune_then_parity():
@@ -797,7 +896,8 @@ def test_tabu_all_classes_ragged(lb):
 
 
 @pytest.mark.parametrize("launch", [(256, 4, 0, 0, 0), (128, 2, 1, 1, 0), (128, 1, 0, 0, 1),
-                                    (128, 1, 1, 2, 2), (64, 1, 0, 0, 1)])
+                                    (128, 1, 1, 2, 2), (64, 1, 0, 0, 1), (64, 4, 0, 0, 0),
+                                    (128, 4, 1, 2, 1)])
 def test_tabu_every_length(lb, launch):
     """One walk at every N in 3..256, move traces compared: each N has its own
     placement of the reversed records (a shift of 0..15 records that keeps the

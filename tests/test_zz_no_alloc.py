@@ -35,7 +35,7 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("launch", [None, (64, 1, 1, 0, 0), (256, 4, 1, 2, 0), (128, 2, 0, 0, 0),
-                                    (128, 1, 1, 0, 1)])
+                                    (128, 1, 1, 0, 1), (64, 4, 1, 0, 0), (128, 4, 0, 0, 0)])
 def test_noalloc_equals_allocating_entry_point(lb, launch):
     rules = I.rules_tabu(3)
     if launch is None:
