@@ -169,19 +169,30 @@ struct GroupLds {
     static_assert(BYTES % 16 == 0, "16-byte aligned walks");
 };
 
-// ds_swizzle in its 32-lane bit-mask mode: lane i reads lane i ^ 16.
-constexpr int kSwizzleXor16 = (0x10 << 10) | 0x1f;
+// The two 16-lane rows of each 32-lane half, every lane receiving both:
+// v_permlane16_swap with the value as both operands swaps the odd rows of
+// one copy with the even rows of the other, so one copy holds rows 0, 0,
+// 2, 2 and the other 1, 1, 3, 3 (a register exchange, no LDS trip).
+__device__ __forceinline__ void row_pair(int v, int &a, int &b) {
+    const auto r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+    a = (int)r[0];
+    b = (int)r[1];
+}
 
 // Minimum and sum over each group of GL = 16 or 32 consecutive lanes, every
 // lane receiving its group's value: row (16-lane) reductions by DPP, then,
-// for GL = 32, the two rows of a group combined by the swizzle.
+// for GL = 32, the two rows of a group combined.
 template <int GL>
 __device__ __forceinline__ int group_min(int v) {
     v = min(v, __builtin_amdgcn_mov_dpp(v, LABS_DPP_QUAD_1032, 0xf, 0xf, true));
     v = min(v, __builtin_amdgcn_mov_dpp(v, LABS_DPP_QUAD_2301, 0xf, 0xf, true));
     v = min(v, __builtin_amdgcn_mov_dpp(v, LABS_DPP_ROW_HALF_MIRROR, 0xf, 0xf, true));
     v = min(v, __builtin_amdgcn_mov_dpp(v, LABS_DPP_ROW_MIRROR, 0xf, 0xf, true));
-    if constexpr (GL == 32) v = min(v, __builtin_amdgcn_ds_swizzle(v, kSwizzleXor16));
+    if constexpr (GL == 32) {
+        int a, b;
+        row_pair(v, a, b);
+        v = min(a, b);
+    }
     return v;
 }
 
@@ -191,7 +202,11 @@ __device__ __forceinline__ int group_sum(int v) {
     v += __builtin_amdgcn_mov_dpp(v, LABS_DPP_QUAD_2301, 0xf, 0xf, true);
     v += __builtin_amdgcn_mov_dpp(v, LABS_DPP_ROW_HALF_MIRROR, 0xf, 0xf, true);
     v += __builtin_amdgcn_mov_dpp(v, LABS_DPP_ROW_MIRROR, 0xf, 0xf, true);
-    if constexpr (GL == 32) v += __builtin_amdgcn_ds_swizzle(v, kSwizzleXor16);
+    if constexpr (GL == 32) {
+        int a, b;
+        row_pair(v, a, b);
+        v = a + b;
+    }
     return v;
 }
 
@@ -265,6 +280,7 @@ __device__ void run_group_walks(const TabuLaunchArgs &a, int64_t pos0, int64_t e
     const uint32_t spj = lds_offset(lds) + (uint32_t)(L::SP + 2 * j);
     uint32_t best = M;
     int bestE = E;
+    int ns = (M >> j) & 1u ? 1 : -1;      // -s_j (lanes past the sequence: unused)
     const int T_all = -wave_min(-sch.T);  // the longest walk of the wavefront
 
     wave_sync();
@@ -295,16 +311,17 @@ __device__ void run_group_walks(const TabuLaunchArgs &a, int64_t pos0, int64_t e
             int v = 0;
 #pragma unroll
             for (int r = 0; r < NB; ++r) v = dot16(tc[r], cc[r], v);
-            const int ns = (M >> j) & 1u ? 1 : -1;  // -s_j
             const int d = mad_i24_after_dot(ns, v, u2);
             const int key = tabu < t || (asp && d < thr) ? d : INT_MAX;
             const int m = group_min<GL>(key);
             // ties: the r-th lowest tied neighbour of the group, r from the
             // step's first draw
-            const uint32_t tied = group_bits<GL>(ballot(key == m), g);
+            const uint64_t tied_all = ballot(key == m);
+            const uint32_t tied = group_bits<GL>(tied_all, g);
             const int r = (int)below(dr, (uint32_t)__popc(tied));
-            const bool mine = key == m && __popc(tied & ((1u << j) - 1u)) == r;
-            const int pick = __builtin_ctz(group_bits<GL>(ballot(mine), g));
+            const uint64_t mine = tied_all & ballot(__popc(tied & ((1u << j) - 1u)) == r);
+            int pick = __builtin_ctz(group_bits<GL>(mine, g));
+            asm("" : "+v"(pick));  // taken here, before the branch below
             if (t <= sch.T) {
                 const bool neg = (M >> pick) & 1u;
                 const int sm = neg ? -1 : 1;  // old s_pick
@@ -326,13 +343,14 @@ __device__ void run_group_walks(const TabuLaunchArgs &a, int64_t pos0, int64_t e
                 const uint32_t qa = spj - (uint32_t)pick;
                 int sq = lds_load_i8(qa);
                 asm("" : "+v"(sq));  // one sign-extending load
-                const int tpk = ((const int8_t *)rows)[kGroupRow * pick + j];
-                C += k2 * tpk;
+                const int tpk = ((const int8_t *)rows)[__umul24(kGroupRow, pick) + j];
+                C += __mul24(k2, tpk);  // 24-bit products: full-rate multiply-adds
                 CB[j] = (int8_t)C;
-                u2 += k4 * sq;
+                u2 += __mul24(k4, sq);
                 lds_store_i8(rowm1 + (uint32_t)abs(pick - j), sq - sm);
                 if (j == pick) {
                     lds_store_i8(qa, ns);
+                    ns = -ns;
                     u2 += 4;
                     tabu = tabu_new;
                 }
