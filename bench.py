@@ -466,8 +466,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="tabu_n64",
-                    choices=["tabu_n64", "tabu_uneven", "tabu_n120", "tabu_n256", "tabu_long_uneven"])
-    ap.add_argument("--more-workloads", default="tabu_uneven,tabu_n120",
+                    choices=["tabu_n64", "tabu_uneven", "tabu_n120", "tabu_n256", "tabu_long_uneven",
+                             "tabu_n32"])
+    ap.add_argument("--more-workloads", default="tabu_uneven,tabu_n120,tabu_n32",
                     help="walk workloads timed after the headline one, each with its own "
                          "roofline and CPU baseline (comma list, empty for none)")
     ap.add_argument("--no-peaks", action="store_true",

@@ -110,8 +110,10 @@ TABU_LONG_UNEVEN = TabuWorkload("tabu_long_uneven", 4096, None, 129, 256, rules=
                                 seed=1007)
 # The top of the N = 64..120 range in one length (two neighbours per lane).
 TABU_N120 = TabuWorkload("tabu_n120", 4096, 120, rules=rules_tabu(4), seed=1008)
+# Short walks, as many as fill the device two walks per wavefront.
+TABU_N32 = TabuWorkload("tabu_n32", 16384, 32, rules=rules_tabu(4), seed=1009)
 TABU_WORKLOADS = {w.name: w for w in (TABU_N64, TABU_UNEVEN, TABU_N120, TABU_N256,
-                                      TABU_LONG_UNEVEN)}
+                                      TABU_LONG_UNEVEN, TABU_N32)}
 MEMETIC_N20 = MemeticWorkload("memetic_n20", 20, 100, 1, 50, seed=1000)
 MEMETIC_N120 = MemeticWorkload("memetic_n120", 120, 100, 256, 100000, seed=1003)
 SERVING_SEED = 1004
