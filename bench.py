@@ -1,6 +1,6 @@
 """Benchmark of the batched tabu-search hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload tabu_n64|tabu_uneven|tabu_n256|tabu_long_uneven]
+    python bench.py [--steps K] [--warmup W] [--workload tabu_n64|tabu_uneven|tabu_n120|tabu_n32|tabu_n256|tabu_long_uneven]
                     [--no-cpu] [--no-ttt] [--no-serving] [--no-skew]
 
 A step is one labs_tabu_batch call over the whole batch (every walk scores
@@ -53,15 +53,95 @@ KERNEL_SOURCES = ("paper_2504_00987_amd/csrc/labs_device.hpp",
                   "paper_2504_00987_amd/csrc/labs_api.cpp")
 
 # Counter readings per call of labs_tabu_batch (rocprofv3 --pmc, one pass per
-# counter group, the same bench command), valid only for the walk kernel
-# digest and the launch they were profiled under; otherwise nothing is
-# attached (they are never carried over to other code or another launch).
-# FETCH_SIZE / WRITE_SIZE are in KiB and scaled by what the same counters read
-# for a 256 MiB device copy (FETCH 0.5x, WRITE 1.0x of the bytes moved).
-# LdsUtil = SQ_LDS_IDX_ACTIVE / (GRBM_GUI_ACTIVE x CUs), rocprofv3's own
-# definition for gfx950.  The summaries live in profiles/.
+# counter group, the same bench command with --launch), per workload and the
+# launch it was profiled under, valid only for the walk kernel digest they
+# were taken with; otherwise nothing is attached (they are never carried over
+# to other code or another launch).  FETCH_SIZE / WRITE_SIZE are in KiB and
+# scaled by what the same counters read for a 256 MiB device copy (FETCH 0.5x,
+# WRITE 1.0x of the bytes moved).  GRBM_GUI_ACTIVE is the sum over the 8
+# XCDs; the LDS busy fraction is SQ_LDS_IDX_ACTIVE over one XCD's busy cycles
+# times the CUs.  SQ_WAVE_CYCLES and the SQ_*_ANY counters are wave-time in
+# units of four cycles.  The summaries live in profiles/.
 COPY_SCALE = {"FETCH_SIZE": 262144 / 131087, "WRITE_SIZE": 262144 / 262144}
-COUNTERS = {}
+XCDS = 8
+COUNTERS_SOURCE = "profiles/tabu_kernel_counters.md"
+COUNTERS_DIGEST = "fe465dccc763caf3"
+COUNTERS = {
+    ("tabu_n64", (64, 1, 0, 0, 0)): {
+        "SQ_WAVES": 4096, "SQ_INSTS_VALU": 45513148, "SQ_INSTS_SALU": 33101021,
+        "SQ_INSTS_LDS": 13721600, "SQ_LDS_BANK_CONFLICT": 2847176,
+        "SQ_LDS_IDX_ACTIVE": 47100360, "GRBM_GUI_ACTIVE": 2609778, "SQ_WAVE_CYCLES": 249660040,
+        "SQ_ACTIVE_INST_ANY": 100487624, "SQ_WAIT_ANY": 90895511, "SQ_WAIT_INST_ANY": 58259716,
+        "FETCH_SIZE": 86.4, "WRITE_SIZE": 768.0},
+    ("tabu_n64", (128, 2, 0, 0, 0)): {
+        "SQ_WAVES": 4096, "SQ_INSTS_VALU": 45537724, "SQ_INSTS_SALU": 33121501,
+        "SQ_INSTS_LDS": 13721600, "SQ_LDS_BANK_CONFLICT": 2847176,
+        "SQ_LDS_IDX_ACTIVE": 47100360, "GRBM_GUI_ACTIVE": 2646535, "SQ_WAVE_CYCLES": 245269960,
+        "SQ_ACTIVE_INST_ANY": 100529958, "SQ_WAIT_ANY": 84746689, "SQ_WAIT_INST_ANY": 59977321,
+        "FETCH_SIZE": 82.9, "WRITE_SIZE": 640.0},
+    ("tabu_n64", (256, 4, 0, 0, 0)): {
+        "SQ_WAVES": 4096, "SQ_INSTS_VALU": 45537724, "SQ_INSTS_SALU": 33121501,
+        "SQ_INSTS_LDS": 13721600, "SQ_LDS_BANK_CONFLICT": 2847176,
+        "SQ_LDS_IDX_ACTIVE": 47100360, "GRBM_GUI_ACTIVE": 2592680, "SQ_WAVE_CYCLES": 245232673,
+        "SQ_ACTIVE_INST_ANY": 100530887, "SQ_WAIT_ANY": 84757765, "SQ_WAIT_INST_ANY": 59892082,
+        "FETCH_SIZE": 84.4, "WRITE_SIZE": 576.0},
+    ("tabu_uneven", (64, 1, 0, 0, 0)): {
+        "SQ_WAVES": 8192, "SQ_INSTS_VALU": 238153444, "SQ_INSTS_SALU": 107004426,
+        "SQ_INSTS_LDS": 65717792, "SQ_LDS_BANK_CONFLICT": 35697887,
+        "SQ_LDS_IDX_ACTIVE": 263385095, "GRBM_GUI_ACTIVE": 11029192,
+        "SQ_WAVE_CYCLES": 1235303639, "SQ_ACTIVE_INST_ANY": 427094151, "SQ_WAIT_ANY": 286131928,
+        "SQ_WAIT_INST_ANY": 522120579, "FETCH_SIZE": 649.8, "WRITE_SIZE": 1361.1},
+    ("tabu_uneven", (128, 2, 0, 0, 0)): {
+        "SQ_WAVES": 8192, "SQ_INSTS_VALU": 238981029, "SQ_INSTS_SALU": 107045386,
+        "SQ_INSTS_LDS": 65717792, "SQ_LDS_BANK_CONFLICT": 35697887,
+        "SQ_LDS_IDX_ACTIVE": 263385095, "GRBM_GUI_ACTIVE": 12388612,
+        "SQ_WAVE_CYCLES": 1042550823, "SQ_ACTIVE_INST_ANY": 427827378, "SQ_WAIT_ANY": 249565843,
+        "SQ_WAIT_INST_ANY": 365191708, "FETCH_SIZE": 652.3, "WRITE_SIZE": 1357.5},
+    ("tabu_n120", (64, 1, 0, 0, 1)): {
+        "SQ_WAVES": 4096, "SQ_INSTS_VALU": 215952677, "SQ_INSTS_SALU": 116891741,
+        "SQ_INSTS_LDS": 67190784, "SQ_LDS_BANK_CONFLICT": 12524579,
+        "SQ_LDS_IDX_ACTIVE": 241409059, "GRBM_GUI_ACTIVE": 14406405,
+        "SQ_WAVE_CYCLES": 800766535, "SQ_ACTIVE_INST_ANY": 421355269, "SQ_WAIT_ANY": 213563067,
+        "SQ_WAIT_INST_ANY": 165870752, "FETCH_SIZE": 221.8, "WRITE_SIZE": 768.0},
+    ("tabu_n120", (64, 1, 0, 0, 0)): {
+        "SQ_WAVES": 4096, "SQ_INSTS_VALU": 283060663, "SQ_INSTS_SALU": 107530772,
+        "SQ_INSTS_LDS": 80859136, "SQ_LDS_BANK_CONFLICT": 17711104,
+        "SQ_LDS_IDX_ACTIVE": 305389568, "GRBM_GUI_ACTIVE": 13948288,
+        "SQ_WAVE_CYCLES": 1335925024, "SQ_ACTIVE_INST_ANY": 486242726, "SQ_WAIT_ANY": 371340236,
+        "SQ_WAIT_INST_ANY": 478321465, "FETCH_SIZE": 72.8, "WRITE_SIZE": 768.0},
+    ("tabu_n32", (64, 2, 0, 0, 0)): {
+        "SQ_WAVES": 8192, "SQ_INSTS_VALU": 69795840, "SQ_INSTS_SALU": 11116544,
+        "SQ_INSTS_LDS": 11632640, "SQ_LDS_BANK_CONFLICT": 3187117,
+        "SQ_LDS_IDX_ACTIVE": 39068077, "GRBM_GUI_ACTIVE": 2376758, "SQ_WAVE_CYCLES": 364185264,
+        "SQ_ACTIVE_INST_ANY": 103968681, "SQ_WAIT_ANY": 87324500, "SQ_WAIT_INST_ANY": 172880964,
+        "FETCH_SIZE": 66.1, "WRITE_SIZE": 2560.0},
+    ("tabu_n32", (128, 4, 0, 0, 0)): {
+        "SQ_WAVES": 8192, "SQ_INSTS_VALU": 69836800, "SQ_INSTS_SALU": 11124736,
+        "SQ_INSTS_LDS": 11632640, "SQ_LDS_BANK_CONFLICT": 3187117,
+        "SQ_LDS_IDX_ACTIVE": 39068077, "GRBM_GUI_ACTIVE": 2378718, "SQ_WAVE_CYCLES": 365049252,
+        "SQ_ACTIVE_INST_ANY": 104017290, "SQ_WAIT_ANY": 85964492, "SQ_WAIT_INST_ANY": 175257056,
+        "FETCH_SIZE": 66.4, "WRITE_SIZE": 2304.0},
+    ("tabu_n32", (64, 4, 0, 0, 0)): {
+        "SQ_WAVES": 8192, "SQ_INSTS_VALU": 69795840, "SQ_INSTS_SALU": 11116544,
+        "SQ_INSTS_LDS": 11632640, "SQ_LDS_BANK_CONFLICT": 3187117,
+        "SQ_LDS_IDX_ACTIVE": 39068077, "GRBM_GUI_ACTIVE": 2382263, "SQ_WAVE_CYCLES": 364275246,
+        "SQ_ACTIVE_INST_ANY": 103967987, "SQ_WAIT_ANY": 87361757, "SQ_WAIT_INST_ANY": 172911534,
+        "FETCH_SIZE": 66.4, "WRITE_SIZE": 2560.0},
+    ("tabu_n256", (256, 4, 0, 0, 0)): {
+        "SQ_WAVES": 4096, "SQ_INSTS_VALU": 2027584427, "SQ_INSTS_SALU": 381779144,
+        "SQ_INSTS_LDS": 541691904, "SQ_LDS_BANK_CONFLICT": 4194304,
+        "SQ_LDS_IDX_ACTIVE": 2027626496, "GRBM_GUI_ACTIVE": 105913952,
+        "SQ_WAVE_CYCLES": 5969956875, "SQ_ACTIVE_INST_ANY": 3033241603,
+        "SQ_WAIT_ANY": 1285248671, "SQ_WAIT_INST_ANY": 1651569280, "FETCH_SIZE": 178.8,
+        "WRITE_SIZE": 1088.0},
+    ("tabu_long_uneven", (256, 4, 0, 0, 0)): {
+        "SQ_WAVES": 4096, "SQ_INSTS_VALU": 1391622528, "SQ_INSTS_SALU": 281735379,
+        "SQ_INSTS_LDS": 368409501, "SQ_LDS_BANK_CONFLICT": 114441374,
+        "SQ_LDS_IDX_ACTIVE": 1480472504, "GRBM_GUI_ACTIVE": 74012817,
+        "SQ_WAVE_CYCLES": 4305453584, "SQ_ACTIVE_INST_ANY": 2100988399,
+        "SQ_WAIT_ANY": 989271524, "SQ_WAIT_INST_ANY": 1215233290, "FETCH_SIZE": 451.0,
+        "WRITE_SIZE": 1184.9},
+}
 
 
 def kernel_digest() -> str:
@@ -184,7 +264,7 @@ def tabu_section(args, lb, wl, peaks=None):
         "lds": {
             # algorithmic LDS bytes: two spins and C_k as int8 per lag term;
             # the lag form reads one byte of its row per lag term and C_k as
-            # a broadcast, so the hardware figure (hardware.lds_util, from
+            # a broadcast, so the hardware figure (hardware.lds_busy_frac, from
             # counters) is the measured one
             "algorithmic_bytes_per_launch": 3 * lag_terms,
             "achieved": 3 * lag_terms / (kernel_ms * 1e-3) / 1e12,
@@ -201,18 +281,23 @@ def tabu_section(args, lb, wl, peaks=None):
         roof["lds"]["frac_of_measured_peak"] = 3 * lag_terms / (kernel_ms * 1e-3) / peaks["lds_bytes_per_s"]
     digest = kernel_digest()
     c = COUNTERS.get((wl.name, tuple(launch)))
-    if c is not None and c["digest"] == digest:
+    if c is not None and COUNTERS_DIGEST == digest:
         roof["traffic"] = (c["FETCH_SIZE"] * COPY_SCALE["FETCH_SIZE"]
                            + c["WRITE_SIZE"] * COPY_SCALE["WRITE_SIZE"]) * 1024
         lane_ops = c["SQ_INSTS_VALU"] * 64
+        wave = c["SQ_WAVE_CYCLES"]
         roof["hardware"] = {
             "valu_lane_ops_per_launch": lane_ops,
             "valu_issue_frac": lane_ops / (kernel_ms * 1e-3) / PEAK_INT32_OPS,
+            "salu_instructions_per_launch": c["SQ_INSTS_SALU"],
             "lds_instructions_per_launch": c["SQ_INSTS_LDS"],
             "lds_bank_conflict_cycles_per_launch": c["SQ_LDS_BANK_CONFLICT"],
-            "lds_util": c["SQ_LDS_IDX_ACTIVE"] / (c["GRBM_GUI_ACTIVE"] * CUS),
-            "launch": list(c["launch"]),
-            "source": c["source"],
+            "lds_busy_frac": c["SQ_LDS_IDX_ACTIVE"] / (c["GRBM_GUI_ACTIVE"] / XCDS * CUS),
+            "wave_time": {"issuing": c["SQ_ACTIVE_INST_ANY"] / wave,
+                          "waiting_any": c["SQ_WAIT_ANY"] / wave,
+                          "waiting_for_issue": c["SQ_WAIT_INST_ANY"] / wave},
+            "launch": list(launch),
+            "source": COUNTERS_SOURCE,
         }
     roof["kernel_digest"] = digest
 
