@@ -216,6 +216,13 @@ __device__ __forceinline__ uint32_t group_bits(uint64_t m, int g) {
     return (uint32_t)(m >> (GL * g)) & (GL == 32 ? 0xffffffffu : 0xffffu);
 }
 
+// |a - b| + c in one instruction, every operand per lane.
+__device__ __forceinline__ uint32_t absdiff_add_v(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t d;
+    asm("v_sad_u32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 // The value v of lane `src` (any lane of the wavefront), per lane.
 __device__ __forceinline__ int lane_value(int v, int src) {
     return __builtin_amdgcn_ds_bpermute(src << 2, v);
@@ -280,6 +287,7 @@ __device__ void run_group_walks(const TabuLaunchArgs &a, int64_t pos0, int64_t e
     const uint32_t spj = lds_offset(lds) + (uint32_t)(L::SP + 2 * j);
     uint32_t best = M;
     int bestE = E;
+    int thr = -(N - 1);                   // ((bestE - E) >> 2) - (N - 1), kept per move
     int ns = (M >> j) & 1u ? 1 : -1;      // -s_j (lanes past the sequence: unused)
     const int T_all = -wave_min(-sch.T);  // the longest walk of the wavefront
 
@@ -306,8 +314,8 @@ __device__ void run_group_walks(const TabuLaunchArgs &a, int64_t pos0, int64_t e
             for (int r = 0; r < NB; ++r) cc[r] = ((const uint4 *)CB)[r];
             const uint32_t dr = (uint32_t)lane_value((int)dr0, src);
             const int tabu_new = lane_value(expire, src);
-            // key d_j = 2 u_j - s_j v_j: candE_j = E + 4 (N - 1) + 4 d_j
-            const int thr = ((bestE - E) >> 2) - (N - 1);
+            // key d_j = 2 u_j - s_j v_j: candE_j = E + 4 (N - 1) + 4 d_j, an
+            // aspiration candidate when d_j < thr
             int v = 0;
 #pragma unroll
             for (int r = 0; r < NB; ++r) v = dot16(tc[r], cc[r], v);
@@ -328,10 +336,14 @@ __device__ void run_group_walks(const TabuLaunchArgs &a, int64_t pos0, int64_t e
                 const int k2 = neg ? 2 : -2;  // -2 s_pick(old)
                 const int k4 = neg ? 4 : -4;
                 M ^= 1u << pick;
+                // E changes by 4 (N - 1 + m); every energy of a walk is the
+                // same modulo 4, so the threshold moves by N - 1 + m exactly
                 E += 4 * (N - 1 + m);
+                thr -= N - 1 + m;
                 if (E < bestE) {
                     bestE = E;
                     best = M;
+                    thr = -(N - 1);
                 }
                 if constexpr (TRACE) {
                     if (j == 0) a.trace[w * (int64_t)a.trace_stride + t - 1] = (int16_t)pick;
@@ -347,7 +359,7 @@ __device__ void run_group_walks(const TabuLaunchArgs &a, int64_t pos0, int64_t e
                 C += __mul24(k2, tpk);  // 24-bit products: full-rate multiply-adds
                 CB[j] = (int8_t)C;
                 u2 += __mul24(k4, sq);
-                lds_store_i8(rowm1 + (uint32_t)abs(pick - j), sq - sm);
+                lds_store_i8(absdiff_add_v((uint32_t)pick, (uint32_t)j, rowm1), sq - sm);
                 if (j == pick) {
                     lds_store_i8(qa, ns);
                     ns = -ns;

@@ -380,6 +380,30 @@ def test_tabu_n64_full_size(lb):
     assert np.array_equal(res.best_seq.cpu().numpy(), best)
 
 
+@pytest.fixture(scope="module")
+def n32_oracle():
+    wl = I.TABU_N32
+    return O.tabu_batch(wl.walks, osched(wl.rules), wl.seed, n_uniform=wl.n, stride=128, nthreads=16)
+
+
+@pytest.mark.parametrize("launch", [None, (64, 2, 0, 0, 0), (128, 4, 0, 0, 0), (64, 4, 0, 0, 0)])
+def test_tabu_n32_full_size(lb, n32_oracle, launch):
+    # the short-walk bench row at full size, all walks, in the default launch
+    # and in each several-walks-per-wavefront launch the autotuner picks from
+    wl = I.TABU_N32
+    say(f"tabu: {wl.name} full size W={wl.walks} N={wl.n}, launch {launch}, all walks against the oracle")
+    if launch is not None:
+        lb.set_launch(*launch)
+    try:
+        res = lb.tabu_batch(wl.rules, wl.walks, wl.seed, n_uniform=wl.n)
+    finally:
+        lb.set_launch(None)
+    best, be, fe = n32_oracle
+    assert np.array_equal(res.best_e.cpu().numpy(), be)
+    assert np.array_equal(res.final_e.cpu().numpy(), fe)
+    assert np.array_equal(res.best_seq.cpu().numpy(), best)
+
+
 @pytest.mark.parametrize("name,n_sample", [("tabu_uneven", 256), ("tabu_long_uneven", 48)])
 def test_tabu_uneven_full_size_sampled(lb, name, n_sample):
     # tabu_long_uneven: both N > 128 classes, mixed in one launch
