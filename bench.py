@@ -65,81 +65,81 @@ KERNEL_SOURCES = ("paper_2504_00987_amd/csrc/labs_device.hpp",
 COPY_SCALE = {"FETCH_SIZE": 262144 / 131087, "WRITE_SIZE": 262144 / 262144}
 XCDS = 8
 COUNTERS_SOURCE = "profiles/tabu_kernel_counters.md"
-COUNTERS_DIGEST = "fe465dccc763caf3"
+COUNTERS_DIGEST = "d86abee156d02fcd"
 COUNTERS = {
     ("tabu_n64", (64, 1, 0, 0, 0)): {
         "SQ_WAVES": 4096, "SQ_INSTS_VALU": 45513148, "SQ_INSTS_SALU": 33101021,
         "SQ_INSTS_LDS": 13721600, "SQ_LDS_BANK_CONFLICT": 2847176,
-        "SQ_LDS_IDX_ACTIVE": 47100360, "GRBM_GUI_ACTIVE": 2609778, "SQ_WAVE_CYCLES": 249660040,
-        "SQ_ACTIVE_INST_ANY": 100487624, "SQ_WAIT_ANY": 90895511, "SQ_WAIT_INST_ANY": 58259716,
-        "FETCH_SIZE": 86.4, "WRITE_SIZE": 768.0},
+        "SQ_LDS_IDX_ACTIVE": 47100360, "GRBM_GUI_ACTIVE": 2601964, "SQ_WAVE_CYCLES": 249569998,
+        "SQ_ACTIVE_INST_ANY": 100487566, "SQ_WAIT_ANY": 90706737, "SQ_WAIT_INST_ANY": 58256468,
+        "FETCH_SIZE": 86.3, "WRITE_SIZE": 768.0},
     ("tabu_n64", (128, 2, 0, 0, 0)): {
         "SQ_WAVES": 4096, "SQ_INSTS_VALU": 45537724, "SQ_INSTS_SALU": 33121501,
         "SQ_INSTS_LDS": 13721600, "SQ_LDS_BANK_CONFLICT": 2847176,
-        "SQ_LDS_IDX_ACTIVE": 47100360, "GRBM_GUI_ACTIVE": 2646535, "SQ_WAVE_CYCLES": 245269960,
-        "SQ_ACTIVE_INST_ANY": 100529958, "SQ_WAIT_ANY": 84746689, "SQ_WAIT_INST_ANY": 59977321,
+        "SQ_LDS_IDX_ACTIVE": 47100360, "GRBM_GUI_ACTIVE": 2663512, "SQ_WAVE_CYCLES": 245099899,
+        "SQ_ACTIVE_INST_ANY": 100529661, "SQ_WAIT_ANY": 84504397, "SQ_WAIT_INST_ANY": 59940558,
         "FETCH_SIZE": 82.9, "WRITE_SIZE": 640.0},
     ("tabu_n64", (256, 4, 0, 0, 0)): {
         "SQ_WAVES": 4096, "SQ_INSTS_VALU": 45537724, "SQ_INSTS_SALU": 33121501,
         "SQ_INSTS_LDS": 13721600, "SQ_LDS_BANK_CONFLICT": 2847176,
-        "SQ_LDS_IDX_ACTIVE": 47100360, "GRBM_GUI_ACTIVE": 2592680, "SQ_WAVE_CYCLES": 245232673,
-        "SQ_ACTIVE_INST_ANY": 100530887, "SQ_WAIT_ANY": 84757765, "SQ_WAIT_INST_ANY": 59892082,
-        "FETCH_SIZE": 84.4, "WRITE_SIZE": 576.0},
+        "SQ_LDS_IDX_ACTIVE": 47100360, "GRBM_GUI_ACTIVE": 2581868, "SQ_WAVE_CYCLES": 245078670,
+        "SQ_ACTIVE_INST_ANY": 100531003, "SQ_WAIT_ANY": 84774672, "SQ_WAIT_INST_ANY": 59853037,
+        "FETCH_SIZE": 84.3, "WRITE_SIZE": 576.0},
     ("tabu_uneven", (64, 1, 0, 0, 0)): {
         "SQ_WAVES": 8192, "SQ_INSTS_VALU": 238153444, "SQ_INSTS_SALU": 107004426,
         "SQ_INSTS_LDS": 65717792, "SQ_LDS_BANK_CONFLICT": 35697887,
-        "SQ_LDS_IDX_ACTIVE": 263385095, "GRBM_GUI_ACTIVE": 11029192,
-        "SQ_WAVE_CYCLES": 1235303639, "SQ_ACTIVE_INST_ANY": 427094151, "SQ_WAIT_ANY": 286131928,
-        "SQ_WAIT_INST_ANY": 522120579, "FETCH_SIZE": 649.8, "WRITE_SIZE": 1361.1},
+        "SQ_LDS_IDX_ACTIVE": 263385095, "GRBM_GUI_ACTIVE": 10985562,
+        "SQ_WAVE_CYCLES": 1234862050, "SQ_ACTIVE_INST_ANY": 427093639, "SQ_WAIT_ANY": 285878199,
+        "SQ_WAIT_INST_ANY": 521906131, "FETCH_SIZE": 649.7, "WRITE_SIZE": 1361.1},
     ("tabu_uneven", (128, 2, 0, 0, 0)): {
         "SQ_WAVES": 8192, "SQ_INSTS_VALU": 238981029, "SQ_INSTS_SALU": 107045386,
         "SQ_INSTS_LDS": 65717792, "SQ_LDS_BANK_CONFLICT": 35697887,
-        "SQ_LDS_IDX_ACTIVE": 263385095, "GRBM_GUI_ACTIVE": 12388612,
-        "SQ_WAVE_CYCLES": 1042550823, "SQ_ACTIVE_INST_ANY": 427827378, "SQ_WAIT_ANY": 249565843,
-        "SQ_WAIT_INST_ANY": 365191708, "FETCH_SIZE": 652.3, "WRITE_SIZE": 1357.5},
+        "SQ_LDS_IDX_ACTIVE": 263385095, "GRBM_GUI_ACTIVE": 12271074,
+        "SQ_WAVE_CYCLES": 1042614629, "SQ_ACTIVE_INST_ANY": 427827603, "SQ_WAIT_ANY": 249505982,
+        "SQ_WAIT_INST_ANY": 365174338, "FETCH_SIZE": 652.3, "WRITE_SIZE": 1357.5},
     ("tabu_n120", (64, 1, 0, 0, 1)): {
         "SQ_WAVES": 4096, "SQ_INSTS_VALU": 215952677, "SQ_INSTS_SALU": 116891741,
         "SQ_INSTS_LDS": 67190784, "SQ_LDS_BANK_CONFLICT": 12524579,
-        "SQ_LDS_IDX_ACTIVE": 241409059, "GRBM_GUI_ACTIVE": 14406405,
-        "SQ_WAVE_CYCLES": 800766535, "SQ_ACTIVE_INST_ANY": 421355269, "SQ_WAIT_ANY": 213563067,
-        "SQ_WAIT_INST_ANY": 165870752, "FETCH_SIZE": 221.8, "WRITE_SIZE": 768.0},
+        "SQ_LDS_IDX_ACTIVE": 241409059, "GRBM_GUI_ACTIVE": 14284657,
+        "SQ_WAVE_CYCLES": 800801250, "SQ_ACTIVE_INST_ANY": 421352876, "SQ_WAIT_ANY": 213547711,
+        "SQ_WAIT_INST_ANY": 165909700, "FETCH_SIZE": 221.8, "WRITE_SIZE": 768.0},
     ("tabu_n120", (64, 1, 0, 0, 0)): {
         "SQ_WAVES": 4096, "SQ_INSTS_VALU": 283060663, "SQ_INSTS_SALU": 107530772,
         "SQ_INSTS_LDS": 80859136, "SQ_LDS_BANK_CONFLICT": 17711104,
-        "SQ_LDS_IDX_ACTIVE": 305389568, "GRBM_GUI_ACTIVE": 13948288,
-        "SQ_WAVE_CYCLES": 1335925024, "SQ_ACTIVE_INST_ANY": 486242726, "SQ_WAIT_ANY": 371340236,
-        "SQ_WAIT_INST_ANY": 478321465, "FETCH_SIZE": 72.8, "WRITE_SIZE": 768.0},
+        "SQ_LDS_IDX_ACTIVE": 305389568, "GRBM_GUI_ACTIVE": 13798582,
+        "SQ_WAVE_CYCLES": 1335622124, "SQ_ACTIVE_INST_ANY": 486242920, "SQ_WAIT_ANY": 371210146,
+        "SQ_WAIT_INST_ANY": 478122981, "FETCH_SIZE": 72.8, "WRITE_SIZE": 768.0},
     ("tabu_n32", (64, 2, 0, 0, 0)): {
-        "SQ_WAVES": 8192, "SQ_INSTS_VALU": 69795840, "SQ_INSTS_SALU": 11116544,
+        "SQ_WAVES": 8192, "SQ_INSTS_VALU": 65617920, "SQ_INSTS_SALU": 11116544,
         "SQ_INSTS_LDS": 11632640, "SQ_LDS_BANK_CONFLICT": 3187117,
-        "SQ_LDS_IDX_ACTIVE": 39068077, "GRBM_GUI_ACTIVE": 2376758, "SQ_WAVE_CYCLES": 364185264,
-        "SQ_ACTIVE_INST_ANY": 103968681, "SQ_WAIT_ANY": 87324500, "SQ_WAIT_INST_ANY": 172880964,
-        "FETCH_SIZE": 66.1, "WRITE_SIZE": 2560.0},
+        "SQ_LDS_IDX_ACTIVE": 39068077, "GRBM_GUI_ACTIVE": 2262614, "SQ_WAVE_CYCLES": 346610506,
+        "SQ_ACTIVE_INST_ANY": 99852280, "SQ_WAIT_ANY": 79737626, "SQ_WAIT_INST_ANY": 167031042,
+        "FETCH_SIZE": 66.4, "WRITE_SIZE": 2560.0},
     ("tabu_n32", (128, 4, 0, 0, 0)): {
-        "SQ_WAVES": 8192, "SQ_INSTS_VALU": 69836800, "SQ_INSTS_SALU": 11124736,
+        "SQ_WAVES": 8192, "SQ_INSTS_VALU": 65658880, "SQ_INSTS_SALU": 11124736,
         "SQ_INSTS_LDS": 11632640, "SQ_LDS_BANK_CONFLICT": 3187117,
-        "SQ_LDS_IDX_ACTIVE": 39068077, "GRBM_GUI_ACTIVE": 2378718, "SQ_WAVE_CYCLES": 365049252,
-        "SQ_ACTIVE_INST_ANY": 104017290, "SQ_WAIT_ANY": 85964492, "SQ_WAIT_INST_ANY": 175257056,
+        "SQ_LDS_IDX_ACTIVE": 39068077, "GRBM_GUI_ACTIVE": 2275775, "SQ_WAVE_CYCLES": 350983808,
+        "SQ_ACTIVE_INST_ANY": 99899856, "SQ_WAIT_ANY": 84060248, "SQ_WAIT_INST_ANY": 166888188,
         "FETCH_SIZE": 66.4, "WRITE_SIZE": 2304.0},
     ("tabu_n32", (64, 4, 0, 0, 0)): {
-        "SQ_WAVES": 8192, "SQ_INSTS_VALU": 69795840, "SQ_INSTS_SALU": 11116544,
+        "SQ_WAVES": 8192, "SQ_INSTS_VALU": 65617920, "SQ_INSTS_SALU": 11116544,
         "SQ_INSTS_LDS": 11632640, "SQ_LDS_BANK_CONFLICT": 3187117,
-        "SQ_LDS_IDX_ACTIVE": 39068077, "GRBM_GUI_ACTIVE": 2382263, "SQ_WAVE_CYCLES": 364275246,
-        "SQ_ACTIVE_INST_ANY": 103967987, "SQ_WAIT_ANY": 87361757, "SQ_WAIT_INST_ANY": 172911534,
-        "FETCH_SIZE": 66.4, "WRITE_SIZE": 2560.0},
+        "SQ_LDS_IDX_ACTIVE": 39068077, "GRBM_GUI_ACTIVE": 2257735, "SQ_WAVE_CYCLES": 346415465,
+        "SQ_ACTIVE_INST_ANY": 99852339, "SQ_WAIT_ANY": 79589295, "SQ_WAIT_INST_ANY": 166986902,
+        "FETCH_SIZE": 66.1, "WRITE_SIZE": 2560.0},
     ("tabu_n256", (256, 4, 0, 0, 0)): {
         "SQ_WAVES": 4096, "SQ_INSTS_VALU": 2027584427, "SQ_INSTS_SALU": 381779144,
         "SQ_INSTS_LDS": 541691904, "SQ_LDS_BANK_CONFLICT": 4194304,
-        "SQ_LDS_IDX_ACTIVE": 2027626496, "GRBM_GUI_ACTIVE": 105913952,
-        "SQ_WAVE_CYCLES": 5969956875, "SQ_ACTIVE_INST_ANY": 3033241603,
-        "SQ_WAIT_ANY": 1285248671, "SQ_WAIT_INST_ANY": 1651569280, "FETCH_SIZE": 178.8,
+        "SQ_LDS_IDX_ACTIVE": 2027626496, "GRBM_GUI_ACTIVE": 104918601,
+        "SQ_WAVE_CYCLES": 5969856813, "SQ_ACTIVE_INST_ANY": 3033241604,
+        "SQ_WAIT_ANY": 1285200532, "SQ_WAIT_INST_ANY": 1651320943, "FETCH_SIZE": 178.8,
         "WRITE_SIZE": 1088.0},
     ("tabu_long_uneven", (256, 4, 0, 0, 0)): {
         "SQ_WAVES": 4096, "SQ_INSTS_VALU": 1391622528, "SQ_INSTS_SALU": 281735379,
         "SQ_INSTS_LDS": 368409501, "SQ_LDS_BANK_CONFLICT": 114441374,
-        "SQ_LDS_IDX_ACTIVE": 1480472504, "GRBM_GUI_ACTIVE": 74012817,
-        "SQ_WAVE_CYCLES": 4305453584, "SQ_ACTIVE_INST_ANY": 2100988399,
-        "SQ_WAIT_ANY": 989271524, "SQ_WAIT_INST_ANY": 1215233290, "FETCH_SIZE": 451.0,
+        "SQ_LDS_IDX_ACTIVE": 1480472504, "GRBM_GUI_ACTIVE": 73416403,
+        "SQ_WAVE_CYCLES": 4305665929, "SQ_ACTIVE_INST_ANY": 2100988162,
+        "SQ_WAIT_ANY": 989274429, "SQ_WAIT_INST_ANY": 1215310331, "FETCH_SIZE": 451.0,
         "WRITE_SIZE": 1184.9},
 }
 
