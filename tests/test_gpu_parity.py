@@ -381,6 +381,29 @@ def test_tabu_n64_full_size(lb):
 
 
 @pytest.fixture(scope="module")
+def n120_oracle():
+    wl = I.TABU_N120
+    return O.tabu_batch(wl.walks, osched(wl.rules), wl.seed, n_uniform=wl.n, stride=128, nthreads=16)
+
+
+@pytest.mark.parametrize("launch", [(64, 1, 0, 0, 0), (64, 1, 0, 0, 1), (128, 1, 0, 0, 0)])
+def test_tabu_n120_full_size(lb, n120_oracle, launch):
+    # the N = 120 bench row at full size, all walks, in the record and the lag
+    # layout (the two the autotuner chooses between) and on two wavefronts
+    wl = I.TABU_N120
+    say(f"tabu: {wl.name} full size W={wl.walks} N={wl.n}, launch {launch}, all walks against the oracle")
+    lb.set_launch(*launch)
+    try:
+        res = lb.tabu_batch(wl.rules, wl.walks, wl.seed, n_uniform=wl.n)
+    finally:
+        lb.set_launch(None)
+    best, be, fe = n120_oracle
+    assert np.array_equal(res.best_e.cpu().numpy(), be)
+    assert np.array_equal(res.final_e.cpu().numpy(), fe)
+    assert np.array_equal(res.best_seq.cpu().numpy(), best)
+
+
+@pytest.fixture(scope="module")
 def n32_oracle():
     wl = I.TABU_N32
     return O.tabu_batch(wl.walks, osched(wl.rules), wl.seed, n_uniform=wl.n, stride=128, nthreads=16)
