@@ -356,6 +356,15 @@ typedef struct labs_memetic_params {
                             N > 128 a child's walk takes 17.7 KB of LDS, and
                             B is further limited to what one workgroup can
                             hold (LABS_E_INVAL beyond). */
+    int32_t resume;      /* 1: continue the replicas this handle holds (left
+                            by its last labs_memetic_run or put there by
+                            labs_memetic_load) instead of drawing new
+                            populations; pops, K, the lengths and the seed
+                            must be those of the held state.  `generations`
+                            stays the total per replica, so a run to G1 and a
+                            resumed run to G give the results of one run to
+                            G (with stop_all, when G1 is a multiple of
+                            chunk). */
 } labs_memetic_params;
 
 #define LABS_MAX_CHILDREN 8
@@ -391,6 +400,29 @@ int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
                      uint64_t seed, int8_t *best_seq, int32_t out_stride,
                      int32_t *best_e, int64_t *hit_gen, int64_t *gens_done,
                      void *stream);
+
+/*
+ * Checkpoints of the memetic replicas a handle holds (after a
+ * labs_memetic_run, also a cancelled one, or a labs_memetic_load): the
+ * populations, their energies, each replica's best, generation count and hit
+ * generation, and whether a replica has reached the target (the global flag
+ * of Sec. IV).  The draws are counter-based, so no generator state is saved,
+ * and a resumed run continues bit for bit (labs_memetic_params.resume).
+ * The blob is host memory in a fixed layout: a 256-byte header (magic
+ * "LABSMEM", version, pops, K, seed, the smallest generation count), the
+ * per-replica lengths (int32, padded to 256 bytes), then the state arrays.
+ *   labs_memetic_checkpoint_bytes  size of the blob for the held state
+ *                                  (LABS_E_INVAL when the handle holds none)
+ *   labs_memetic_save   copies the held state into `dst` (host, `bytes` >=
+ *                       the size) after the work already on `stream`;
+ *                       returns once the copy is complete
+ *   labs_memetic_load   validates a blob (magic, version, sizes, lengths in
+ *                       range) and makes it the held state, ordered on
+ *                       `stream`; returns once `src` may be reused
+ */
+int labs_memetic_checkpoint_bytes(labs_handle *h, int64_t *bytes);
+int labs_memetic_save(labs_handle *h, void *dst, int64_t bytes, void *stream);
+int labs_memetic_load(labs_handle *h, const void *src, int64_t bytes, void *stream);
 
 /*
  * Stop every labs_memetic_run of this handle that is running or still being

@@ -22,7 +22,9 @@ EXPORTED = [
     "labs_skew_bruteforce_min", "labs_tabu_batch",
     "labs_tabu_batch_noalloc",
     "labs_set_launch", "labs_get_launch", "labs_device_peaks",
-    "labs_autotune", "labs_memetic_run", "labs_cancel", "labs_server_create", "labs_server_submit",
+    "labs_autotune", "labs_memetic_run", "labs_cancel",
+    "labs_memetic_checkpoint_bytes", "labs_memetic_save", "labs_memetic_load",
+    "labs_server_create", "labs_server_submit",
     "labs_server_poll", "labs_server_cancel", "labs_server_stats", "labs_server_destroy",
 ]
 
@@ -45,7 +47,7 @@ class MemeticParams(ctypes.Structure):
                 ("p_mut", ctypes.c_uint32), ("tabu", TabuParams), ("generations", ctypes.c_int64),
                 ("target_e", ctypes.c_int32), ("mode", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("stop_all", ctypes.c_int32), ("waves_per_replica", ctypes.c_int32),
-                ("children", ctypes.c_int32)]
+                ("children", ctypes.c_int32), ("resume", ctypes.c_int32)]
 
 
 class LabsError(RuntimeError):
@@ -93,6 +95,9 @@ def load():
     L.labs_memetic_run.argtypes = [P, ctypes.POINTER(MemeticParams), P, i32, i32, u64, P, i32,
                                    P, P, P, P]
     L.labs_cancel.argtypes = [P]
+    L.labs_memetic_checkpoint_bytes.argtypes = [P, ctypes.POINTER(i64)]
+    L.labs_memetic_save.argtypes = [P, P, i64, P]
+    L.labs_memetic_load.argtypes = [P, P, i64, P]
     L.labs_server_create.argtypes = [P, ctypes.POINTER(MemeticParams), i32, PP]
     L.labs_server_submit.argtypes = [P, i32, u64, i32, i64, ctypes.POINTER(i64)]
     L.labs_server_poll.argtypes = [P, i64, P, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]

@@ -75,6 +75,14 @@ struct labs_handle {
     uint32_t *cancel_dev = nullptr;
     std::atomic<uint32_t> cancel_epoch{0};
     hipEvent_t poll_event[4] = {};
+    // The memetic replicas held in `mem` (after a run or a load): what a
+    // resumed run or a checkpoint must match.
+    struct MemState {
+        bool valid = false;
+        int32_t pops = 0, K = 0;
+        uint64_t seed = 0;
+        std::vector<int32_t> ns;
+    } held;
     bool has_override = false;
     labs_launch override_launch{64, 1, 0, 0, 0};
     // tuned launches by (length bucket of n_min, of n_max), buckets of 16

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cstring>
 #include <vector>
 
@@ -33,6 +34,21 @@ MemeticStateDev carve_state(void *base, int S, int K, size_t *bytes_out) {
     return st;
 }
 
+// Device layout of a run in `mem`: [slots][ns][flags: any_hit, stop][state].
+struct MemLayout {
+    size_t off_ns, off_flag, off_state, state_bytes;
+    size_t total() const { return off_state + state_bytes; }
+};
+static MemLayout mem_layout(int pops, int K) {
+    MemLayout l;
+    carve_state(nullptr, pops, K, &l.state_bytes);
+    const size_t slots_bytes = (size_t)pops * sizeof(MemeticSlot);
+    l.off_ns = align256(slots_bytes);
+    l.off_flag = l.off_ns + align256((size_t)pops * 4);
+    l.off_state = l.off_flag + 256;
+    return l;
+}
+
 static_assert(kMaxChildren == LABS_MAX_CHILDREN, "kernel and ABI limits agree");
 
 int split_wide(const labs_handle *h, int waves_per_replica, int64_t n_wide) {
@@ -58,6 +74,7 @@ int check_memetic(labs_handle *h, const labs_memetic_params *p) {
         return fail(h, LABS_E_INVAL, "unknown mode %d", p->mode);
     if (p->chunk < 1 || p->chunk > (1 << 20)) return fail(h, LABS_E_INVAL, "chunk out of [1, 2^20]");
     if (p->stop_all != 0 && p->stop_all != 1) return fail(h, LABS_E_INVAL, "stop_all must be 0 or 1");
+    if (p->resume != 0 && p->resume != 1) return fail(h, LABS_E_INVAL, "resume must be 0 or 1");
     if (p->waves_per_replica < 0 || p->waves_per_replica > 2)
         return fail(h, LABS_E_INVAL, "waves_per_replica must be 0, 1 or 2");
     if (p->children < 0 || p->children > LABS_MAX_CHILDREN)
@@ -145,6 +162,17 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
     }
     const int children = std::max(1, (int)p->children);
     if ((rc = check_children(h, children, classes))) return rc;
+    const bool resume = p->resume == 1;
+    if (resume) {
+        const auto &hd = h->held;
+        if (!hd.valid) return fail(h, LABS_E_INVAL, "resume: this handle holds no memetic replicas");
+        if (hd.pops != pops || hd.K != p->K || hd.seed != seed)
+            return fail(h, LABS_E_INVAL, "resume: pops, K or seed differ from the held replicas "
+                        "(%d, %d, %llu)", hd.pops, hd.K, (unsigned long long)hd.seed);
+        for (int i = 0; i < pops; ++i)
+            if ((ns_host ? ns_host[i] : n_uniform) != hd.ns[(size_t)i])
+                return fail(h, LABS_E_INVAL, "resume: the length of replica %d differs", i);
+    }
 
     // Everything below is enqueued on the caller's stream.
     DeviceGuard g(h->device);
@@ -153,18 +181,35 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
     const uint32_t epoch = h->cancel_epoch.load();
 
     // Device memory: [slots][ns][flags: any_hit, stop][state]
-    size_t state_bytes = 0;
-    carve_state(nullptr, pops, p->K, &state_bytes);
-    const size_t slots_bytes = (size_t)pops * sizeof(MemeticSlot);
-    const size_t off_ns = (slots_bytes + 255) & ~(size_t)255;
-    const size_t off_flag = off_ns + (((size_t)pops * 4 + 255) & ~(size_t)255);
-    const size_t off_state = off_flag + 256;
-    if ((rc = mem_acquire(h, s, off_state + state_bytes))) return rc;
+    const MemLayout lay = mem_layout(pops, p->K);
+    const size_t off_ns = lay.off_ns, off_flag = lay.off_flag;
+    // A fresh run replaces the held replicas (valid again once enqueued;
+    // growing the buffer frees the old one); a resumed run keeps the size.
+    if (!resume) h->held.valid = false;
+    if ((rc = mem_acquire(h, s, lay.total()))) return rc;
     char *base = (char *)h->mem.ptr;
     MemeticSlot *d_slots = (MemeticSlot *)base;
     int32_t *d_ns = (int32_t *)(base + off_ns);
     uint32_t *d_flag = (uint32_t *)(base + off_flag);  // [0] any_hit, [1] stop
-    MemeticStateDev st = carve_state(base + off_state, pops, p->K, nullptr);
+    MemeticStateDev st = carve_state(base + lay.off_state, pops, p->K, nullptr);
+
+    // A resumed run starts from the smallest generation count among the
+    // replicas still going (read back once); launches past a replica's
+    // limit do nothing, so a lower start only costs launches.
+    int64_t gen_start = 0;
+    if (resume) {
+        std::vector<int64_t> gen((size_t)pops);
+        std::vector<int32_t> be((size_t)pops);
+        hipError_t e = hipMemcpyAsync(gen.data(), st.gen, (size_t)pops * 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(be.data(), st.bestE, (size_t)pops * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(h, e, "resume: generation counts");
+        gen_start = p->generations;
+        for (int i = 0; i < pops; ++i)
+            if (gen[(size_t)i] < p->generations && (p->target_e < 0 || be[(size_t)i] > p->target_e))
+                gen_start = std::min(gen_start, gen[(size_t)i]);
+    }
 
     const size_t stage = off_flag;  // slots + ns
     if ((rc = stage_acquire(h, stage))) return rc;
@@ -202,8 +247,14 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
     a.classes = classes;
     a.split_wide = split_wide(h, p->waves_per_replica, n_wide);
     a.children = children;
-    if ((e = launch_fill_u32(d_flag, 0u, 2, s)) != hipSuccess) return hip_fail(h, e, "fill");
-    if ((e = launch_memetic_init(a, s)) != hipSuccess) return hip_fail(h, e, "memetic init");
+    if (resume) {
+        // any_hit carries over (the global flag of the run being continued);
+        // the stop flag is this run's
+        if ((e = launch_fill_u32(d_flag + 1, 0u, 1, s)) != hipSuccess) return hip_fail(h, e, "fill");
+    } else {
+        if ((e = launch_fill_u32(d_flag, 0u, 2, s)) != hipSuccess) return hip_fail(h, e, "fill");
+        if ((e = launch_memetic_init(a, s)) != hipSuccess) return hip_fail(h, e, "memetic init");
+    }
 
     // Chunk boundaries: the latch turns a reached target (stop_all) or a
     // cancel into the stop flag every later launch of the run reads first,
@@ -243,7 +294,7 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
     bool cancelled = false;
     constexpr int kLag = 2;
     int64_t n_chunks = 0;
-    for (int64_t done = 0; done < G;) {
+    for (int64_t done = gen_start; done < G;) {
         const int64_t step = std::min(chunk, G - done);
         if (p->mode == LABS_MODE_GRAPH) {
             // launches past a replica's generation limit return at once, so
@@ -314,6 +365,134 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
     }
     if (rc) return rc;
     if (er != hipSuccess) return hip_fail(h, er, "hipEventRecord");
+    if (!resume) {
+        h->held.valid = true;
+        h->held.pops = pops;
+        h->held.K = p->K;
+        h->held.seed = seed;
+        h->held.ns.assign((size_t)pops, n_uniform);
+        if (ns_host) h->held.ns.assign(ns_host, ns_host + pops);
+    }
     if (cancelled) return fail(h, LABS_E_CANCELLED, "cancelled by labs_cancel");
+    return LABS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Checkpoints of the held replicas.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr char kCkptMagic[8] = {'L', 'A', 'B', 'S', 'M', 'E', 'M', '\0'};
+constexpr uint32_t kCkptVersion = 1;
+constexpr size_t kCkptHeaderBytes = 256;
+
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t pops, K;
+    uint32_t any_hit;   // a replica has reached the target (the global flag)
+    uint64_t seed;
+    int64_t gen_min;    // smallest generation count (informative)
+    int64_t state_bytes;
+};
+static_assert(sizeof(CkptHeader) <= kCkptHeaderBytes, "header fits its slot");
+
+size_t ckpt_bytes(int pops, int K) {
+    return kCkptHeaderBytes + align256((size_t)pops * 4) + mem_layout(pops, K).state_bytes;
+}
+
+}  // namespace
+
+extern "C" int labs_memetic_checkpoint_bytes(labs_handle *h, int64_t *bytes) {
+    if (!h || !bytes) return LABS_E_INVAL;
+    h->last_error.clear();
+    if (!h->held.valid) return fail(h, LABS_E_INVAL, "this handle holds no memetic replicas");
+    *bytes = (int64_t)ckpt_bytes(h->held.pops, h->held.K);
+    return LABS_OK;
+}
+
+extern "C" int labs_memetic_save(labs_handle *h, void *dst, int64_t bytes, void *stream) {
+    if (!h) return LABS_E_INVAL;
+    h->last_error.clear();
+    if (!dst) return fail(h, LABS_E_INVAL, "null destination");
+    if (!h->held.valid) return fail(h, LABS_E_INVAL, "this handle holds no memetic replicas");
+    const int pops = h->held.pops, K = h->held.K;
+    const size_t need = ckpt_bytes(pops, K);
+    if (bytes < (int64_t)need) return fail(h, LABS_E_INVAL, "bytes=%lld < %zu", (long long)bytes, need);
+    DeviceGuard g(h->device);
+    hipStream_t s = (hipStream_t)stream;
+    const MemLayout lay = mem_layout(pops, K);
+    char *out = (char *)dst;
+    char *state = out + kCkptHeaderBytes + align256((size_t)pops * 4);
+    uint32_t any_hit = 0;
+    hipError_t e = hipSuccess;
+    if (h->mem_event_valid) e = hipStreamWaitEvent(s, h->mem_event, 0);
+    const char *base = (const char *)h->mem.ptr;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&any_hit, base + lay.off_flag, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(state, base + lay.off_state, lay.state_bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "checkpoint copy");
+    CkptHeader hd;
+    std::memset(&hd, 0, sizeof(hd));
+    std::memcpy(hd.magic, kCkptMagic, sizeof(kCkptMagic));
+    hd.version = kCkptVersion;
+    hd.pops = pops;
+    hd.K = K;
+    hd.any_hit = any_hit;
+    hd.seed = h->held.seed;
+    hd.state_bytes = (int64_t)lay.state_bytes;
+    const MemeticStateDev st = carve_state(state, pops, K, nullptr);
+    hd.gen_min = INT64_MAX;
+    for (int i = 0; i < pops; ++i) hd.gen_min = std::min<int64_t>(hd.gen_min, st.gen[i]);
+    std::memset(out, 0, kCkptHeaderBytes + align256((size_t)pops * 4));
+    std::memcpy(out, &hd, sizeof(hd));
+    std::memcpy(out + kCkptHeaderBytes, h->held.ns.data(), (size_t)pops * 4);
+    return LABS_OK;
+}
+
+extern "C" int labs_memetic_load(labs_handle *h, const void *src, int64_t bytes, void *stream) {
+    if (!h) return LABS_E_INVAL;
+    h->last_error.clear();
+    if (!src) return fail(h, LABS_E_INVAL, "null source");
+    if (bytes < (int64_t)kCkptHeaderBytes) return fail(h, LABS_E_INVAL, "not a checkpoint (too short)");
+    CkptHeader hd;
+    std::memcpy(&hd, src, sizeof(hd));
+    if (std::memcmp(hd.magic, kCkptMagic, sizeof(kCkptMagic)) != 0)
+        return fail(h, LABS_E_INVAL, "not a checkpoint (magic)");
+    if (hd.version != kCkptVersion) return fail(h, LABS_E_INVAL, "checkpoint version %u", hd.version);
+    if (hd.pops < 1 || hd.pops > (1 << 24) || hd.K < 2 || hd.K > LABS_MAX_K)
+        return fail(h, LABS_E_INVAL, "checkpoint pops=%d K=%d out of range", hd.pops, hd.K);
+    const MemLayout lay = mem_layout(hd.pops, hd.K);
+    if (hd.state_bytes != (int64_t)lay.state_bytes || bytes < (int64_t)ckpt_bytes(hd.pops, hd.K))
+        return fail(h, LABS_E_INVAL, "checkpoint sizes do not match pops=%d K=%d", hd.pops, hd.K);
+    const char *in = (const char *)src;
+    std::vector<int32_t> ns((size_t)hd.pops);
+    std::memcpy(ns.data(), in + kCkptHeaderBytes, (size_t)hd.pops * 4);
+    for (int32_t n : ns)
+        if (n < LABS_MIN_N || n > LABS_MAX_N)
+            return fail(h, LABS_E_INVAL, "checkpoint length N=%d out of [%d, %d]", n, LABS_MIN_N,
+                        LABS_MAX_N);
+    DeviceGuard g(h->device);
+    hipStream_t s = (hipStream_t)stream;
+    h->held.valid = false;  // growing the buffer frees the held replicas
+    int rc = mem_acquire(h, s, lay.total());
+    if (rc) return rc;
+    char *base = (char *)h->mem.ptr;
+    const uint32_t flags[2] = {hd.any_hit ? 1u : 0u, 0u};
+    hipError_t e = hipMemcpyAsync(base + lay.off_flag, flags, sizeof(flags), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + lay.off_state, in + kCkptHeaderBytes + align256((size_t)hd.pops * 4),
+                           lay.state_bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // `src` may be reused on return
+    if (e == hipSuccess) e = hipEventRecord(h->mem_event, s);
+    if (e != hipSuccess) return hip_fail(h, e, "checkpoint load");
+    h->mem_event_valid = true;
+    h->held.valid = true;
+    h->held.pops = hd.pops;
+    h->held.K = hd.K;
+    h->held.seed = hd.seed;
+    h->held.ns = std::move(ns);
     return LABS_OK;
 }

@@ -227,6 +227,7 @@ extern "C" int labs_server_create(labs_handle *h, const labs_memetic_params *par
     h->last_error.clear();
     int rc = check_memetic(h, params);
     if (rc) return rc;
+    if (params->resume) return fail(h, LABS_E_INVAL, "the server starts every request afresh (resume=0)");
     if (max_slots < 1 || max_slots > (1 << 20)) return fail(h, LABS_E_INVAL, "max_slots out of [1, 2^20]");
     DeviceGuard g(h->device);
     labs_server *s = new labs_server();

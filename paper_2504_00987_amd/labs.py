@@ -206,9 +206,10 @@ class Labs:
                        mut_rule: int = MUT_INV_N, p_mut: int = 0, target: int = -1,
                        mode: int = PERSISTENT, chunk: int = 64,
                        stop_all: int = 0, waves_per_replica: int = 0,
-                       children: int = 1) -> _lib.MemeticParams:
+                       children: int = 1, resume: int = 0) -> _lib.MemeticParams:
         return _lib.MemeticParams(K, p_comb, mut_rule, p_mut, tabu_params(rules), generations,
-                                  target, mode, chunk, stop_all, waves_per_replica, children)
+                                  target, mode, chunk, stop_all, waves_per_replica, children,
+                                  resume)
 
     def memetic_run(self, K: int, rules: Rules, generations: int, pops: int, seed: int,
                     ns=None, n_uniform: int = 0, out_stride: int | None = None, stream=None,
@@ -238,6 +239,19 @@ class Labs:
     def cancel(self):
         """labs_cancel: stop this handle's memetic runs at their next chunk boundary."""
         self._check(self.L.labs_cancel(self.h))
+
+    def memetic_save(self, stream=None) -> bytes:
+        """labs_memetic_save: a checkpoint of the replicas this handle holds."""
+        n = ctypes.c_int64(0)
+        self._check(self.L.labs_memetic_checkpoint_bytes(self.h, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(self.L.labs_memetic_save(self.h, buf, n.value, _stream(stream)))
+        return buf.raw
+
+    def memetic_load(self, blob: bytes, stream=None):
+        """labs_memetic_load: hold the replicas of a checkpoint (resume=1 continues them)."""
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        self._check(self.L.labs_memetic_load(self.h, buf, len(blob), _stream(stream)))
 
 
 class Server:

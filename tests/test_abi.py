@@ -52,8 +52,8 @@ def test_struct_layouts_match_header():
     from paper_2504_00987_amd import _lib
     assert ctypes.sizeof(_lib.TabuParams) == 56
     assert ctypes.sizeof(_lib.Launch) == 20
-    # K, p_comb, mut_rule, p_mut (16) + tabu (56) + generations (8, aligned at 72) + 6 ints
-    assert ctypes.sizeof(_lib.MemeticParams) == 104
+    # K, p_comb, mut_rule, p_mut (16) + tabu (56) + generations (8, aligned at 72) + 7 ints, padded to 8
+    assert ctypes.sizeof(_lib.MemeticParams) == 112
 
 
 def test_limits_match_header():

@@ -592,6 +592,111 @@ def test_memetic_cancel(lb, mode):
     assert (res2.gens_done.cpu().numpy() == 8).all()
 
 
+def _same_memetic(a, b):
+    torch.cuda.synchronize()
+    for x, y in ((a.best_seq, b.best_seq), (a.best_e, b.best_e), (a.hit_gen, b.hit_gen),
+                 (a.gens_done, b.gens_done)):
+        assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("stop", [False, True])
+def test_memetic_checkpoint_resume(lb, mode, stop):
+    # a run to G equals a run to G1 continued to G on its own handle, and
+    # equals the same run saved, loaded into another handle and continued
+    # there; with a target and the global stop flag as well (G1 a multiple
+    # of the chunk). Lengths over all three replica classes.
+    from paper_2504_00987_amd.labs import Labs
+    ns = I.uneven_lengths(40, 20, 140, seed=61)
+    K, G, G1, chunk, seed = 24, 96, 40, 8, 6161
+    rules = I.RULES_MEMETIC
+    kw = dict(ns=ns, mode=mode, chunk=chunk)
+    if stop:
+        probe = lb.memetic_run(K, rules, G, len(ns), seed, ns=ns, mode=2, chunk=chunk)
+        kw.update(target=int(np.median(probe.best_e.cpu().numpy())), stop_all=1)
+    say(f"memetic checkpoint and resume, mode {mode}, stop {stop}")
+    full = lb.memetic_run(K, rules, G, len(ns), seed, **kw)
+    torch.cuda.synchronize()
+    if stop:
+        assert (full.hit_gen.cpu().numpy() >= 0).any()
+    lb.memetic_run(K, rules, G1, len(ns), seed, **kw)
+    blob = lb.memetic_save()
+    cont = lb.memetic_run(K, rules, G, len(ns), seed, resume=1, **kw)
+    _same_memetic(full, cont)
+    # a resumed run past the limit changes nothing
+    again = lb.memetic_run(K, rules, G, len(ns), seed, resume=1, **kw)
+    _same_memetic(full, again)
+    h2 = Labs(0)
+    try:
+        h2.memetic_load(blob)
+        assert h2.memetic_save() == blob  # the loaded state is the saved one
+        res = h2.memetic_run(K, rules, G, len(ns), seed, resume=1, **kw)
+        _same_memetic(full, res)
+    finally:
+        h2.close()
+
+
+def test_memetic_cancel_then_resume(lb):
+    # a cancelled run, continued, equals the uninterrupted run
+    import threading
+    from paper_2504_00987_amd import _lib
+    n, K, pops, chunk, seed = 24, 16, 6, 16, 778
+    rules = I.RULES_MEMETIC
+    say("memetic cancel, then resume")
+    t = threading.Timer(0.3, lb.cancel)
+    t.start()
+    try:
+        lb.memetic_run(K, rules, 10**6, pops, seed, n_uniform=n, mode=2, chunk=chunk)
+    except _lib.LabsError as ex:
+        assert ex.code == _lib.LABS_E_CANCELLED
+    t.join()
+    torch.cuda.synchronize()
+    done = int(lb._last_memetic.gens_done[0].item())
+    assert 0 < done < 10**6 and done % chunk == 0
+    Gf = done + 3 * chunk
+    cont = lb.memetic_run(K, rules, Gf, pops, seed, n_uniform=n, mode=2, chunk=chunk, resume=1)
+    torch.cuda.synchronize()
+    full = lb.memetic_run(K, rules, Gf, pops, seed, n_uniform=n, mode=2, chunk=chunk)
+    _same_memetic(full, cont)
+
+
+def test_memetic_resume_errors(lb):
+    from paper_2504_00987_amd import _lib
+    from paper_2504_00987_amd.labs import Labs
+    rules = I.RULES_MEMETIC
+    say("memetic resume and checkpoint: invalid uses")
+    h2 = Labs(0)
+    try:
+        with pytest.raises(_lib.LabsError) as ex:
+            h2.memetic_run(16, rules, 8, 4, 1, n_uniform=20, resume=1)  # nothing held
+        assert ex.value.code == _lib.LABS_E_INVAL
+        with pytest.raises(_lib.LabsError):
+            h2.memetic_save()
+        h2.memetic_run(16, rules, 8, 4, 1, n_uniform=20)
+        blob = h2.memetic_save()
+        for bad in (dict(seed=2), dict(pops=5), dict(K=17), dict(n=21)):
+            a = dict(seed=1, pops=4, K=16, n=20)
+            a.update(bad)
+            with pytest.raises(_lib.LabsError) as ex:
+                h2.memetic_run(a["K"], rules, 16, a["pops"], a["seed"], n_uniform=a["n"], resume=1)
+            assert ex.value.code == _lib.LABS_E_INVAL
+        for junk in (blob[:100], b"X" + blob[1:], blob[:-1]):
+            with pytest.raises(_lib.LabsError) as ex:
+                h2.memetic_load(junk)
+            assert ex.value.code == _lib.LABS_E_INVAL
+        # a failed load leaves the held replicas usable
+        res = h2.memetic_run(16, rules, 16, 4, 1, n_uniform=20, resume=1)
+        torch.cuda.synchronize()
+        assert (res.gens_done.cpu().numpy() == 16).all()
+        # the server starts every request afresh
+        import ctypes
+        p = Labs.memetic_params(16, rules, 0, resume=1)
+        out = ctypes.c_void_p()
+        assert h2.L.labs_server_create(h2.h, ctypes.byref(p), 8, ctypes.byref(out)) == _lib.LABS_E_INVAL
+    finally:
+        h2.close()
+
+
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_memetic_n20_modes(lb, mode):
     wl = I.MEMETIC_N20
