@@ -94,3 +94,50 @@ def test_noalloc_caller_starts_and_limits(lb):
     _same(ref, got)
     # W = 0 is a no-op
     lb.tabu_batch(rules, 0, 1, n_uniform=20, noalloc=True)
+
+
+@pytest.mark.parametrize("launch", [None, (64, 1, 1, 0, 0), (64, 2, 0, 0, 0)])
+def test_noalloc_replayed_in_a_graph(lb, launch):
+    # what the allocation-free entry point is for: a call captured into a HIP
+    # graph (one length, so the call copies nothing from the host), replayed
+    # several times with eager work between the replays; every replay equals
+    # the eager call (the persistent launch resets its queue head with a fill
+    # kernel inside the graph)
+    rules = I.rules_tabu(2)
+    W, seed = 2048, 4321
+    n = 24 if launch == (64, 2, 0, 0, 0) else 64
+    say(f"noalloc in a graph: launch {launch}, {W} walks of N={n}")
+    if launch is not None:
+        lb.set_launch(*launch)
+    try:
+        ref = lb.tabu_batch(rules, W, seed, n_uniform=n)
+        torch.cuda.synchronize()
+        dev = torch.device("cuda", 0)
+        out = (torch.empty((W, 128), dtype=torch.int8, device=dev),
+               torch.empty(W, dtype=torch.int32, device=dev),
+               torch.empty(W, dtype=torch.int32, device=dev), None)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):  # a first call on the capture stream
+            lb.tabu_batch(rules, W, seed, n_uniform=n, out=out, stream=s, noalloc=True)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            lb.tabu_batch(rules, W, seed, n_uniform=n, out=out, stream=s, noalloc=True)
+        torch.cuda.synchronize()
+        for rep in range(4):
+            out[0].fill_(7)
+            out[1].fill_(-1)
+            out[2].fill_(-1)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out[0], ref.best_seq), f"replay {rep}"
+            assert torch.equal(out[1], ref.best_e) and torch.equal(out[2], ref.final_e)
+            # eager work on the same scratch between replays
+            lb.tabu_batch(rules, 64, rep, n_uniform=20, noalloc=True)
+            torch.cuda.synchronize()
+        del g
+    finally:
+        lb.set_launch(None)
