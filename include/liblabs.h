@@ -119,7 +119,8 @@ typedef struct labs_launch {
                                 on one wavefront, lag form on two), 1 lag form
                                 (t_jk rows, 18.5 KB of LDS per walk), 2 record
                                 form (sequence windows, 9.5 KB) */
-} labs_launch;               /* default (untuned): {64, 1, 0, 0, 0} up to
+} labs_launch;               /* default (untuned): {64, 2, 0, 0, 0} when
+                                every walk has N <= 32, {64, 1, 0, 0, 0} up to
                                 N = 128, {256, 4, 0, 0, 0} above */
 
 typedef struct labs_handle labs_handle;
@@ -283,7 +284,8 @@ int labs_get_launch(labs_handle *h, int32_t n_min, int32_t n_max, labs_launch *o
  * at 1, 2, 4 and 8 x 4 / (wavefronts per group) groups per CU -- on `walks`
  * random-start walks with lengths spread evenly over [n_min, n_max] and
  * parameters `p` (each: one warm-up call, then four calls back to back).
- * The default launch stays unless a configuration is more than 2 % faster.
+ * The default runs first until the GPU is at its steady clock (at least 16
+ * calls and 25 ms), and stays unless a configuration is more than 2 % faster.
  * The choice is kept for batches whose shortest and longest lengths fall in
  * the length buckets (of 16) of n_min and n_max, so that tuning one range
  * leaves the others alone.  *tried (may be NULL) receives the number of

@@ -200,16 +200,19 @@ RuleParams to_rule(const labs_tabu_params &p) {
 
 int bucket_of(int n) { return std::min(LABS_MAX_N / 16 - 1, std::max(0, (n - 1) / 16)); }
 
-// One wave per walk.  Up to N = 128, one walk per 64-lane workgroup: the
-// kernels compiled for that size keep their registers low enough for four
-// wavefronts per SIMD (the two-neighbour ones need 104 VGPRs there, 136 with
-// four walks per workgroup), 3 to 8 % faster on the N = 64 and uneven
-// batches.  Longer walks are bound by LDS (18 KB per walk), and four walks
-// per 256-lane workgroup, one per SIMD of a CU, time best there.
+// Up to N = 128, one walk per 64-lane workgroup: the kernels compiled for
+// that size keep their registers low enough for four wavefronts per SIMD
+// (the two-neighbour ones need 104 VGPRs there, 136 with four walks per
+// workgroup); batches of several lengths run 10-25 % slower in the mixed
+// kernel with two or four walks per workgroup, batches of one length within
+// about 1 %.  Batches whose walks all have N <= 32 run two walks per
+// wavefront (1.35-1.45x faster at N = 32, uniform or mixed down to N = 3).
+// Longer walks are bound by LDS (18 KB per walk), and four walks per
+// 256-lane workgroup, one per SIMD of a CU, time best there.
 labs_launch default_launch(int n_max) {
     labs_launch l;
     l.group_lanes = n_max <= 128 ? 64 : 256;
-    l.walks_per_group = n_max <= 128 ? 1 : 4;
+    l.walks_per_group = n_max <= 32 ? 2 : n_max <= 128 ? 1 : 4;
     l.persistent = 0;
     l.groups_per_cu = 0;
     l.layout = 0;
@@ -748,6 +751,21 @@ extern "C" int labs_autotune(labs_handle *h, const labs_tabu_params *p, int32_t 
         return tabu_batch_impl(h, p, nullptr, 0, uneven ? ns.data() : nullptr, n_min, walks, seed,
                                best_seq, LABS_MAX_N, be, fe, nullptr, 0, s, &c);
     };
+    // Steady state first: an idle GPU runs its first few milliseconds of work
+    // at a lower clock, which would count against the configuration timed
+    // first (the default).  The default runs for at least 16 calls and 25 ms.
+    {
+        float one = 0.f;
+        rc = run(cands[0]);
+        hipEventRecord(e0, s);
+        if (rc == LABS_OK) rc = run(cands[0]);
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        hipEventElapsedTime(&one, e0, e1);
+        const int calls = std::max(16, (int)std::min(4096.f, 25.f / std::max(one, 1e-3f)));
+        for (int i = 0; i < calls && rc == LABS_OK; ++i) rc = run(cands[0]);
+        hipStreamSynchronize(s);
+    }
     for (size_t i = 0; i < cands.size() && rc == LABS_OK; ++i) {
         const labs_launch &c = cands[i];
         const WalkLaunch wc = walk_launch(h, c), w0 = walk_launch(h, cands[0]);
