@@ -499,6 +499,49 @@ def _oracle_memetic(n_list, K, rules, gens, seed, target=-1, p_comb=I.P_COMB_090
         return list(ex.map(one, range(len(n_list))))
 
 
+@pytest.mark.parametrize("launch", [(64, 2, 0, 0, 0), (64, 4, 1, 0, 0)])
+def test_tabu_range_rule_subwave(lb, launch):
+    # the RANGE walk length (different lengths per walk within a wavefront's
+    # groups) with several walks per wavefront, traced
+    ns = np.repeat(np.array([3, 9, 16, 17, 25, 32], dtype=np.int32), 5)
+    rules = I.Rules(I.STEPS_RANGE, 0, I.TENURE_LINEAR, 0, 1, 1, 1, 10, 1, 1, 1, 2, 3, 2)
+    say(f"tabu RANGE rule, N <= 32, launch {launch}")
+    lb.set_launch(*launch)
+    try:
+        res = lb.tabu_batch(rules, len(ns), 4343, ns=ns, trace_stride=64)
+    finally:
+        lb.set_launch(None)
+    best, be, fe, trs = _oracle_walks(len(ns), ns, rules, 4343)
+    assert np.array_equal(res.best_e.cpu().numpy(), be)
+    assert np.array_equal(res.final_e.cpu().numpy(), fe)
+    assert np.array_equal(res.best_seq.cpu().numpy(), best)
+    tr = res.trace.cpu().numpy()
+    for w in range(len(ns)):
+        assert np.array_equal(tr[w, : len(trs[w])], trs[w])
+
+
+def test_autotune_across_all_short_forms():
+    # a range from the several-walks-per-wavefront classes to 64 < N <= 128:
+    # every launch form is a candidate; parity under the kept one
+    from paper_2504_00987_amd.labs import Labs
+    say("autotune over N in [3, 130], then parity under the tuned launch")
+    h = Labs(0)
+    try:
+        rules = I.rules_tabu(2)
+        tried = h.autotune(rules, 3, 130, 1024, seed=9)
+        assert tried >= 40
+        launch = h.get_launch(3, 130)
+        say(f"autotune kept {launch} after {tried} configurations")
+        ns = I.uneven_lengths(400, 3, 130, seed=57)
+        res = h.tabu_batch(rules, len(ns), 58, ns=ns, out_stride=256)
+        best, be, fe = O.tabu_batch(len(ns), osched(rules), 58, ns=ns, stride=256, nthreads=8)
+        assert np.array_equal(res.best_e.cpu().numpy(), be)
+        assert np.array_equal(res.final_e.cpu().numpy(), fe)
+        assert np.array_equal(res.best_seq.cpu().numpy(), best)
+    finally:
+        h.close()
+
+
 def test_tabu_range_rule(lb):
     # Sec. III.B's walk length randInt[N/2, 3N/2] as the RANGE rule, and an
     # asymmetric range, traced, against the oracle; lengths over two classes
@@ -630,6 +673,26 @@ def test_memetic_checkpoint_resume(lb, mode, stop):
     try:
         h2.memetic_load(blob)
         assert h2.memetic_save() == blob  # the loaded state is the saved one
+        res = h2.memetic_run(K, rules, G, len(ns), seed, resume=1, **kw)
+        _same_memetic(full, res)
+    finally:
+        h2.close()
+
+
+def test_memetic_checkpoint_resume_batched_children(lb):
+    # the batched-generation variant (4 children per generation) resumes too
+    from paper_2504_00987_amd.labs import Labs
+    ns = I.uneven_lengths(24, 30, 120, seed=63)
+    K, G, G1, chunk, seed = 24, 48, 16, 8, 6363
+    rules = I.RULES_MEMETIC
+    kw = dict(ns=ns, mode=2, chunk=chunk, children=4)
+    say("memetic checkpoint and resume, 4 children per generation")
+    full = lb.memetic_run(K, rules, G, len(ns), seed, **kw)
+    lb.memetic_run(K, rules, G1, len(ns), seed, **kw)
+    blob = lb.memetic_save()
+    h2 = Labs(0)
+    try:
+        h2.memetic_load(blob)
         res = h2.memetic_run(K, rules, G, len(ns), seed, resume=1, **kw)
         _same_memetic(full, res)
     finally:
