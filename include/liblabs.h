@@ -230,6 +230,8 @@ int labs_skew_bruteforce_min(labs_handle *h, int32_t n, int32_t *min_e, int64_t 
  *   trace         optional device int16 [walks][trace_stride]: the 0-based
  *                 index flipped at step t goes to trace[w][t-1]
  *                 (trace_stride >= the longest walk), or NULL
+ * walks may be up to 2^31 - 1; batches whose grid would pass 2^30
+ * work-items run as several launches, in order, on `stream`.
  * Asynchronous on `stream`; ns_host is read before the call returns.
  */
 int labs_tabu_batch(labs_handle *h, const labs_tabu_params *p,
@@ -370,9 +372,11 @@ typedef struct labs_memetic_params {
 } labs_memetic_params;
 
 #define LABS_MAX_CHILDREN 8
+#define LABS_MAX_REPLICAS (1 << 22) /* replicas of one labs_memetic_run */
 
 /*
- * Run `pops` independent memetic replicas (population id = index).
+ * Run `pops` independent memetic replicas (population id = index),
+ * 0 <= pops <= LABS_MAX_REPLICAS.
  * Replica p: K members from the draws (p, m, q, INIT), bit i of member m
  * being bit i % 128 of draw q = i / 128 as for walk starts; per generation g,
  * crossover (binary-tournament parents, one-point cut) or sampling, per-bit

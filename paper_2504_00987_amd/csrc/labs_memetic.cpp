@@ -137,6 +137,8 @@ extern "C" int labs_memetic_run(labs_handle *h, const labs_memetic_params *p,
     int rc = check_memetic(h, p);
     if (rc) return rc;
     if (pops < 0) return fail(h, LABS_E_INVAL, "pops < 0");
+    // one workgroup of up to 8 wavefronts per replica in one grid
+    if (pops > LABS_MAX_REPLICAS) return fail(h, LABS_E_INVAL, "pops > %d", LABS_MAX_REPLICAS);
     if (pops == 0) return LABS_OK;
     if (!best_seq || !best_e) return fail(h, LABS_E_INVAL, "null output");
     const RuleParams rule = to_rule(p->tabu);
@@ -462,7 +464,7 @@ extern "C" int labs_memetic_load(labs_handle *h, const void *src, int64_t bytes,
     if (std::memcmp(hd.magic, kCkptMagic, sizeof(kCkptMagic)) != 0)
         return fail(h, LABS_E_INVAL, "not a checkpoint (magic)");
     if (hd.version != kCkptVersion) return fail(h, LABS_E_INVAL, "checkpoint version %u", hd.version);
-    if (hd.pops < 1 || hd.pops > (1 << 24) || hd.K < 2 || hd.K > LABS_MAX_K)
+    if (hd.pops < 1 || hd.pops > LABS_MAX_REPLICAS || hd.K < 2 || hd.K > LABS_MAX_K)
         return fail(h, LABS_E_INVAL, "checkpoint pops=%d K=%d out of range", hd.pops, hd.K);
     const MemLayout lay = mem_layout(hd.pops, hd.K);
     if (hd.state_bytes != (int64_t)lay.state_bytes || bytes < (int64_t)ckpt_bytes(hd.pops, hd.K))

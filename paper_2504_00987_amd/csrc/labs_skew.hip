@@ -72,10 +72,18 @@ hipError_t launch_skew_deviation(const int8_t *seqs, const int32_t *ns, int32_t 
                                  int32_t stride, int64_t count, int32_t *out, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     constexpr int WPG = 4;
-    const int64_t grid = (count + WPG - 1) / WPG;
-    hipLaunchKernelGGL(skew_deviation_kernel<WPG>, dim3((unsigned)grid), dim3(64 * WPG), 0, s, seqs,
-                       ns, n_uniform, stride, count, out);
-    return hipGetLastError();
+    // at most 2^30 work-items per launch (a grid's x extent in work-items is
+    // a 32-bit count): larger batches run as consecutive launches
+    constexpr int64_t kRowsPerLaunch = (int64_t(1) << 30) / 64;
+    for (int64_t b0 = 0; b0 < count; b0 += kRowsPerLaunch) {
+        const int64_t n = std::min(kRowsPerLaunch, count - b0);
+        hipLaunchKernelGGL(skew_deviation_kernel<WPG>, dim3((unsigned)((n + WPG - 1) / WPG)),
+                           dim3(64 * WPG), 0, s, seqs + b0 * (int64_t)stride, ns ? ns + b0 : nullptr,
+                           n_uniform, stride, n, out + b0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace liblabs

@@ -617,14 +617,38 @@ hipError_t launch_order_by_length(const int32_t *ns, int64_t W, int32_t *order, 
     return hipGetLastError();
 }
 
+namespace {
+
+// Work-items of one launch at most (a grid's x extent in work-items is a
+// 32-bit count): a grid of one workgroup per few positions that would pass
+// it runs as consecutive launches over sub-ranges of the positions.
+constexpr int64_t kMaxLaunchItems = int64_t(1) << 30;
+
+// launch(b, e, grid) for consecutive sub-ranges [b, e) of [begin, end), with
+// `per_group` positions per workgroup of `lanes` lanes.
+template <typename F>
+hipError_t launch_in_ranges(int64_t begin, int64_t end, int per_group, int lanes, F &&launch) {
+    const int64_t step = kMaxLaunchItems / lanes * per_group;
+    for (int64_t b = begin; b < end; b += step) {
+        const int64_t e = std::min(end, b + step);
+        launch(b, e, (unsigned)((e - b + per_group - 1) / per_group));
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
 hipError_t launch_energy(const int8_t *seqs, const int32_t *ns, int32_t n_uniform,
                          int32_t stride, int64_t count, int32_t *out, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     constexpr int WPG = 4;
-    const int64_t grid = (count + WPG - 1) / WPG;
-    hipLaunchKernelGGL(energy_kernel<WPG>, dim3((unsigned)grid), dim3(64 * WPG), 0, s, seqs, ns,
-                       n_uniform, stride, count, out);
-    return hipGetLastError();
+    return launch_in_ranges(0, count, WPG, 64 * WPG, [&](int64_t b, int64_t e, unsigned grid) {
+        hipLaunchKernelGGL(energy_kernel<WPG>, dim3(grid), dim3(64 * WPG), 0, s,
+                           seqs + b * (int64_t)stride, ns ? ns + b : nullptr, n_uniform, stride,
+                           e - b, out + b);
+    });
 }
 
 namespace {
@@ -640,9 +664,10 @@ hipError_t launch_tabu_part_t(const TabuLaunchArgs &a, int64_t begin, int64_t en
                            dim3((unsigned)std::min<int64_t>(groups, need)), dim3(64 * WPG), 0, s, a,
                            begin, end, counter);
     } else {
-        const int64_t grid = (end - begin + WPG - 1) / WPG;
-        hipLaunchKernelGGL((tabu_kernel<NW, NB, WPG, false, TRACE, LAG>), dim3((unsigned)grid),
-                           dim3(64 * WPG), 0, s, a, begin, end, counter);
+        return launch_in_ranges(begin, end, WPG, 64 * WPG, [&](int64_t b, int64_t e, unsigned grid) {
+            hipLaunchKernelGGL((tabu_kernel<NW, NB, WPG, false, TRACE, LAG>), dim3(grid),
+                               dim3(64 * WPG), 0, s, a, b, e, counter);
+        });
     }
     return hipGetLastError();
 }
@@ -667,9 +692,10 @@ hipError_t launch_mixed_t(const TabuLaunchArgs &a, int64_t begin, int64_t end, i
                            dim3((unsigned)std::min<int64_t>(groups, need)), dim3(64 * WPG), 0, s, a,
                            begin, end, counter);
     } else {
-        const int64_t grid = (end - begin + WPG - 1) / WPG;
-        hipLaunchKernelGGL((tabu_kernel_mixed<WPG, false, TRACE, LONG, LAG>), dim3((unsigned)grid),
-                           dim3(64 * WPG), 0, s, a, begin, end, counter);
+        return launch_in_ranges(begin, end, WPG, 64 * WPG, [&](int64_t b, int64_t e, unsigned grid) {
+            hipLaunchKernelGGL((tabu_kernel_mixed<WPG, false, TRACE, LONG, LAG>), dim3(grid),
+                               dim3(64 * WPG), 0, s, a, b, e, counter);
+        });
     }
     return hipGetLastError();
 }
@@ -693,8 +719,10 @@ hipError_t launch_split_t(const TabuLaunchArgs &a, int64_t begin, int64_t end, i
                            dim3((unsigned)std::min<int64_t>(groups, end - begin)), dim3(128), 0, s,
                            a, begin, end, counter);
     } else {
-        hipLaunchKernelGGL((tabu_kernel_split<false, TRACE, LAG>), dim3((unsigned)(end - begin)),
-                           dim3(128), 0, s, a, begin, end, counter);
+        return launch_in_ranges(begin, end, 1, 128, [&](int64_t b, int64_t e, unsigned grid) {
+            hipLaunchKernelGGL((tabu_kernel_split<false, TRACE, LAG>), dim3(grid), dim3(128), 0, s,
+                               a, b, e, counter);
+        });
     }
     return hipGetLastError();
 }
@@ -718,8 +746,11 @@ hipError_t launch_group_t(const TabuLaunchArgs &a, int64_t begin, int64_t end, i
                            dim3((unsigned)std::min<int64_t>(groups, need)), dim3(64 * WAVES), 0, s,
                            a, begin, end, counter);
     } else {
-        hipLaunchKernelGGL((tabu_kernel_group<G, WAVES, false, TRACE>), dim3((unsigned)need),
-                           dim3(64 * WAVES), 0, s, a, begin, end, counter);
+        return launch_in_ranges(begin, end, G * WAVES, 64 * WAVES,
+                                [&](int64_t b, int64_t e, unsigned grid) {
+            hipLaunchKernelGGL((tabu_kernel_group<G, WAVES, false, TRACE>), dim3(grid),
+                               dim3(64 * WAVES), 0, s, a, b, e, counter);
+        });
     }
     return hipGetLastError();
 }

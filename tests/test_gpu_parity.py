@@ -454,6 +454,52 @@ def test_tabu_uneven_full_size_sampled(lb, name, n_sample):
     assert np.all(be_g % 4 == (ns // 2) % 4)
 
 
+@pytest.mark.parametrize("launch,n", [((64, 1, 0, 0, 0), 8), (None, 8), ((128, 1, 0, 0, 1), 70)])
+def test_tabu_largest_grids(lb, launch, n):
+    # 2^24 + 37 walks: one walk per 64-lane workgroup (and one per two
+    # wavefronts) passes 2^30 work-items, so the batch runs as several
+    # launches; 128-byte rows put the last walks past 2^31 bytes of output.
+    # Sampled walks (both sides of every launch boundary) against the
+    # oracle, and the energy of every returned sequence (that launch splits
+    # too) against its best energy.
+    from paper_2504_00987_amd import _lib
+    W = (1 << 24) + 37
+    rules = I.rules_tabu(1)
+    say(f"tabu: {W} walks of N={n}, launch {launch}")
+    if launch is not None:
+        lb.set_launch(*launch)
+    try:
+        res = lb.tabu_batch(rules, W, 2024, n_uniform=n)
+    finally:
+        lb.set_launch(None)
+    torch.cuda.synchronize()
+    be = res.best_e.cpu().numpy()
+    fe = res.final_e.cpu().numpy()
+    rng = np.random.default_rng(64)
+    edges = [0, 1, (1 << 23) - 1, 1 << 23, (1 << 24) - 1, 1 << 24, (1 << 24) + 1, W - 1]
+    sample = np.unique(np.concatenate([edges, rng.choice(W, size=24, replace=False)]))
+    sch = osched(rules)
+    for w in sample:
+        w = int(w)
+        T, lo, hi = O.walk_schedule(n, sch, 2024, w, 0)
+        b, e1, f1, _, _ = O.tabu_walk(O.random_start(n, 2024, w), 2024, w, 0, T, lo, hi, 1)
+        assert be[w] == e1 and fe[w] == f1, w
+        assert np.array_equal(res.best_seq[w, :n].cpu().numpy(), b), w
+        assert not res.best_seq[w, n:].any()
+    E = lb.energy_batch(res.best_seq, n_uniform=n).cpu().numpy()
+    assert np.array_equal(E, be)
+    assert np.all(be <= fe)
+    del res, E
+    torch.cuda.empty_cache()
+
+
+def test_memetic_replica_limit(lb):
+    from paper_2504_00987_amd import _lib
+    with pytest.raises(_lib.LabsError) as ex:
+        lb.memetic_run(16, I.RULES_MEMETIC, 1, (1 << 22) + 1, 1, n_uniform=20)
+    assert ex.value.code == _lib.LABS_E_INVAL
+
+
 def test_tabu_zero_walks_and_zero_steps(lb):
     say("tabu: W=0 and zero-step walks")
     r = lb.tabu_batch(I.rules_tabu(4), 0, 1, n_uniform=64)
