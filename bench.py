@@ -65,81 +65,81 @@ KERNEL_SOURCES = ("paper_2504_00987_amd/csrc/labs_device.hpp",
 COPY_SCALE = {"FETCH_SIZE": 262144 / 131087, "WRITE_SIZE": 262144 / 262144}
 XCDS = 8
 COUNTERS_SOURCE = "profiles/tabu_kernel_counters.md"
-COUNTERS_DIGEST = "447281fc8f89ef91"
+COUNTERS_DIGEST = "65597ff269d66762"
 COUNTERS = {
     ("tabu_n64", (64, 1, 0, 0, 0)): {
         "SQ_WAVES": 4096, "SQ_INSTS_VALU": 45513148, "SQ_INSTS_SALU": 33101021,
         "SQ_INSTS_LDS": 13721600, "SQ_LDS_BANK_CONFLICT": 2847176,
-        "SQ_LDS_IDX_ACTIVE": 47100360, "GRBM_GUI_ACTIVE": 2606365, "SQ_WAVE_CYCLES": 249757774,
-        "SQ_ACTIVE_INST_ANY": 100487494, "SQ_WAIT_ANY": 90922924, "SQ_WAIT_INST_ANY": 58243225,
+        "SQ_LDS_IDX_ACTIVE": 47100360, "GRBM_GUI_ACTIVE": 2602963, "SQ_WAVE_CYCLES": 249625723,
+        "SQ_ACTIVE_INST_ANY": 100487299, "SQ_WAIT_ANY": 90887124, "SQ_WAIT_INST_ANY": 58246496,
         "FETCH_SIZE": 86.3, "WRITE_SIZE": 768.0},
     ("tabu_n64", (128, 2, 0, 0, 0)): {
         "SQ_WAVES": 4096, "SQ_INSTS_VALU": 45537724, "SQ_INSTS_SALU": 33121501,
         "SQ_INSTS_LDS": 13721600, "SQ_LDS_BANK_CONFLICT": 2847176,
-        "SQ_LDS_IDX_ACTIVE": 47100360, "GRBM_GUI_ACTIVE": 2645800, "SQ_WAVE_CYCLES": 245165575,
-        "SQ_ACTIVE_INST_ANY": 100530620, "SQ_WAIT_ANY": 84465549, "SQ_WAIT_INST_ANY": 59963871,
+        "SQ_LDS_IDX_ACTIVE": 47100360, "GRBM_GUI_ACTIVE": 2641890, "SQ_WAVE_CYCLES": 244954014,
+        "SQ_ACTIVE_INST_ANY": 100529590, "SQ_WAIT_ANY": 84688251, "SQ_WAIT_INST_ANY": 59949379,
         "FETCH_SIZE": 82.9, "WRITE_SIZE": 640.0},
     ("tabu_n64", (256, 4, 0, 0, 0)): {
         "SQ_WAVES": 4096, "SQ_INSTS_VALU": 45537724, "SQ_INSTS_SALU": 33121501,
         "SQ_INSTS_LDS": 13721600, "SQ_LDS_BANK_CONFLICT": 2847176,
-        "SQ_LDS_IDX_ACTIVE": 47100360, "GRBM_GUI_ACTIVE": 2574854, "SQ_WAVE_CYCLES": 245187042,
-        "SQ_ACTIVE_INST_ANY": 100530769, "SQ_WAIT_ANY": 84902537, "SQ_WAIT_INST_ANY": 59811594,
-        "FETCH_SIZE": 84.4, "WRITE_SIZE": 576.0},
+        "SQ_LDS_IDX_ACTIVE": 47100360, "GRBM_GUI_ACTIVE": 2565526, "SQ_WAVE_CYCLES": 245254690,
+        "SQ_ACTIVE_INST_ANY": 100531017, "SQ_WAIT_ANY": 85030196, "SQ_WAIT_INST_ANY": 59846120,
+        "FETCH_SIZE": 84.3, "WRITE_SIZE": 576.0},
     ("tabu_uneven", (64, 1, 0, 0, 0)): {
         "SQ_WAVES": 8192, "SQ_INSTS_VALU": 238153444, "SQ_INSTS_SALU": 107004426,
         "SQ_INSTS_LDS": 65717792, "SQ_LDS_BANK_CONFLICT": 35697887,
-        "SQ_LDS_IDX_ACTIVE": 263385095, "GRBM_GUI_ACTIVE": 11018876,
-        "SQ_WAVE_CYCLES": 1235220259, "SQ_ACTIVE_INST_ANY": 427094035, "SQ_WAIT_ANY": 286042235,
-        "SQ_WAIT_INST_ANY": 522032286, "FETCH_SIZE": 649.8, "WRITE_SIZE": 1361.1},
+        "SQ_LDS_IDX_ACTIVE": 263385095, "GRBM_GUI_ACTIVE": 10981097,
+        "SQ_WAVE_CYCLES": 1235198368, "SQ_ACTIVE_INST_ANY": 427094313, "SQ_WAIT_ANY": 286088155,
+        "SQ_WAIT_INST_ANY": 522007640, "FETCH_SIZE": 649.8, "WRITE_SIZE": 1361.1},
     ("tabu_uneven", (128, 2, 0, 0, 0)): {
         "SQ_WAVES": 8192, "SQ_INSTS_VALU": 238981029, "SQ_INSTS_SALU": 107045386,
         "SQ_INSTS_LDS": 65717792, "SQ_LDS_BANK_CONFLICT": 35697887,
-        "SQ_LDS_IDX_ACTIVE": 263385095, "GRBM_GUI_ACTIVE": 12305987,
-        "SQ_WAVE_CYCLES": 1042539483, "SQ_ACTIVE_INST_ANY": 427827602, "SQ_WAIT_ANY": 249695792,
-        "SQ_WAIT_INST_ANY": 365135718, "FETCH_SIZE": 652.4, "WRITE_SIZE": 1357.5},
+        "SQ_LDS_IDX_ACTIVE": 263385095, "GRBM_GUI_ACTIVE": 12292234,
+        "SQ_WAVE_CYCLES": 1042541253, "SQ_ACTIVE_INST_ANY": 427827244, "SQ_WAIT_ANY": 249638089,
+        "SQ_WAIT_INST_ANY": 365200678, "FETCH_SIZE": 652.3, "WRITE_SIZE": 1357.5},
     ("tabu_n120", (64, 1, 0, 0, 1)): {
         "SQ_WAVES": 4096, "SQ_INSTS_VALU": 215952677, "SQ_INSTS_SALU": 116891741,
         "SQ_INSTS_LDS": 67190784, "SQ_LDS_BANK_CONFLICT": 12524579,
-        "SQ_LDS_IDX_ACTIVE": 241409059, "GRBM_GUI_ACTIVE": 14372588,
-        "SQ_WAVE_CYCLES": 800716236, "SQ_ACTIVE_INST_ANY": 421353938, "SQ_WAIT_ANY": 213591738,
-        "SQ_WAIT_INST_ANY": 165745435, "FETCH_SIZE": 221.8, "WRITE_SIZE": 768.0},
+        "SQ_LDS_IDX_ACTIVE": 241409059, "GRBM_GUI_ACTIVE": 14282818,
+        "SQ_WAVE_CYCLES": 800668253, "SQ_ACTIVE_INST_ANY": 421353424, "SQ_WAIT_ANY": 213610749,
+        "SQ_WAIT_INST_ANY": 165679612, "FETCH_SIZE": 221.8, "WRITE_SIZE": 768.0},
     ("tabu_n120", (64, 1, 0, 0, 0)): {
         "SQ_WAVES": 4096, "SQ_INSTS_VALU": 283060663, "SQ_INSTS_SALU": 107530772,
         "SQ_INSTS_LDS": 80859136, "SQ_LDS_BANK_CONFLICT": 17711104,
-        "SQ_LDS_IDX_ACTIVE": 305389568, "GRBM_GUI_ACTIVE": 13885110,
-        "SQ_WAVE_CYCLES": 1335886398, "SQ_ACTIVE_INST_ANY": 486242648, "SQ_WAIT_ANY": 371277166,
-        "SQ_WAIT_INST_ANY": 478278746, "FETCH_SIZE": 72.8, "WRITE_SIZE": 768.0},
+        "SQ_LDS_IDX_ACTIVE": 305389568, "GRBM_GUI_ACTIVE": 13829119,
+        "SQ_WAVE_CYCLES": 1335726845, "SQ_ACTIVE_INST_ANY": 486242331, "SQ_WAIT_ANY": 371388113,
+        "SQ_WAIT_INST_ANY": 478146242, "FETCH_SIZE": 72.8, "WRITE_SIZE": 768.0},
     ("tabu_n32", (64, 2, 0, 0, 0)): {
         "SQ_WAVES": 8192, "SQ_INSTS_VALU": 65617920, "SQ_INSTS_SALU": 11116544,
         "SQ_INSTS_LDS": 11632640, "SQ_LDS_BANK_CONFLICT": 3187117,
-        "SQ_LDS_IDX_ACTIVE": 39068077, "GRBM_GUI_ACTIVE": 2267507, "SQ_WAVE_CYCLES": 346725272,
-        "SQ_ACTIVE_INST_ANY": 99852000, "SQ_WAIT_ANY": 79840975, "SQ_WAIT_INST_ANY": 167101898,
-        "FETCH_SIZE": 66.4, "WRITE_SIZE": 2560.0},
+        "SQ_LDS_IDX_ACTIVE": 39068077, "GRBM_GUI_ACTIVE": 2257454, "SQ_WAVE_CYCLES": 347045904,
+        "SQ_ACTIVE_INST_ANY": 99851470, "SQ_WAIT_ANY": 79889195, "SQ_WAIT_INST_ANY": 167204589,
+        "FETCH_SIZE": 66.1, "WRITE_SIZE": 2560.0},
     ("tabu_n32", (128, 4, 0, 0, 0)): {
         "SQ_WAVES": 8192, "SQ_INSTS_VALU": 65658880, "SQ_INSTS_SALU": 11124736,
         "SQ_INSTS_LDS": 11632640, "SQ_LDS_BANK_CONFLICT": 3187117,
-        "SQ_LDS_IDX_ACTIVE": 39068077, "GRBM_GUI_ACTIVE": 2264740, "SQ_WAVE_CYCLES": 351026193,
-        "SQ_ACTIVE_INST_ANY": 99900640, "SQ_WAIT_ANY": 84319298, "SQ_WAIT_INST_ANY": 166867021,
+        "SQ_LDS_IDX_ACTIVE": 39068077, "GRBM_GUI_ACTIVE": 2248578, "SQ_WAVE_CYCLES": 351115208,
+        "SQ_ACTIVE_INST_ANY": 99899866, "SQ_WAIT_ANY": 84375146, "SQ_WAIT_INST_ANY": 166874530,
         "FETCH_SIZE": 66.4, "WRITE_SIZE": 2304.0},
     ("tabu_n32", (64, 4, 0, 0, 0)): {
         "SQ_WAVES": 8192, "SQ_INSTS_VALU": 65617920, "SQ_INSTS_SALU": 11116544,
         "SQ_INSTS_LDS": 11632640, "SQ_LDS_BANK_CONFLICT": 3187117,
-        "SQ_LDS_IDX_ACTIVE": 39068077, "GRBM_GUI_ACTIVE": 2257929, "SQ_WAVE_CYCLES": 346871681,
-        "SQ_ACTIVE_INST_ANY": 99853876, "SQ_WAIT_ANY": 79922146, "SQ_WAIT_INST_ANY": 167130627,
+        "SQ_LDS_IDX_ACTIVE": 39068077, "GRBM_GUI_ACTIVE": 2251066, "SQ_WAVE_CYCLES": 347053631,
+        "SQ_ACTIVE_INST_ANY": 99853791, "SQ_WAIT_ANY": 80004182, "SQ_WAIT_INST_ANY": 167201910,
         "FETCH_SIZE": 66.4, "WRITE_SIZE": 2560.0},
     ("tabu_n256", (256, 4, 0, 0, 0)): {
         "SQ_WAVES": 4096, "SQ_INSTS_VALU": 2027584427, "SQ_INSTS_SALU": 381779144,
         "SQ_INSTS_LDS": 541691904, "SQ_LDS_BANK_CONFLICT": 4194304,
-        "SQ_LDS_IDX_ACTIVE": 2027626496, "GRBM_GUI_ACTIVE": 105170203,
-        "SQ_WAVE_CYCLES": 5969893421, "SQ_ACTIVE_INST_ANY": 3033241795,
-        "SQ_WAIT_ANY": 1285315724, "SQ_WAIT_INST_ANY": 1651418021, "FETCH_SIZE": 178.8,
+        "SQ_LDS_IDX_ACTIVE": 2027626496, "GRBM_GUI_ACTIVE": 105383441,
+        "SQ_WAVE_CYCLES": 5970235536, "SQ_ACTIVE_INST_ANY": 3033241847,
+        "SQ_WAIT_ANY": 1285363394, "SQ_WAIT_INST_ANY": 1651510685, "FETCH_SIZE": 178.8,
         "WRITE_SIZE": 1088.0},
     ("tabu_long_uneven", (256, 4, 0, 0, 0)): {
         "SQ_WAVES": 4096, "SQ_INSTS_VALU": 1391622528, "SQ_INSTS_SALU": 281735379,
         "SQ_INSTS_LDS": 368409501, "SQ_LDS_BANK_CONFLICT": 114441374,
-        "SQ_LDS_IDX_ACTIVE": 1480472504, "GRBM_GUI_ACTIVE": 73776820,
-        "SQ_WAVE_CYCLES": 4305537632, "SQ_ACTIVE_INST_ANY": 2100988393,
-        "SQ_WAIT_ANY": 989271314, "SQ_WAIT_INST_ANY": 1215186632, "FETCH_SIZE": 451.0,
+        "SQ_LDS_IDX_ACTIVE": 1480472504, "GRBM_GUI_ACTIVE": 73559732,
+        "SQ_WAVE_CYCLES": 4305539543, "SQ_ACTIVE_INST_ANY": 2100988348,
+        "SQ_WAIT_ANY": 989369525, "SQ_WAIT_INST_ANY": 1215187811, "FETCH_SIZE": 451.0,
         "WRITE_SIZE": 1184.9},
 }
 
